@@ -1,0 +1,129 @@
+/*
+ * libess: linear elliptical slice sampling on MI355X (gfx950).
+ *
+ * Samples N(0, I_d) restricted to the polytope {x : A x <= b} (Wu & Gardner,
+ * arXiv 2407.10449, Section 1) with many independent Markov chains.  One
+ * transition (Algorithm 1) draws nu ~ N(0, I), forms the ellipse
+ * x cos(theta) + nu sin(theta) (Section 2), solves every constraint's
+ * intersection angles (Appendix B, with the edge cases of Section 3.2), builds
+ * the active intervals by sorting and a cumulative max (Algorithm 3,
+ * Proposition 1), draws theta uniformly on them, moves, and applies the
+ * safeguards of Section 3.3 (trimming by trim_eps, reject-and-stay).
+ * Non-standard normals reduce to this form by whitening (Appendix A).
+ *
+ * Conventions for every entry point:
+ *  - All array arguments are DEVICE pointers unless marked "host".
+ *  - Arrays are dense row-major; "T" is float when precision = 32 and double
+ *    when precision = 64.  b and the interval outputs are always double.
+ *  - Work is enqueued on the stream given to ess_init (a hipStream_t passed as
+ *    void*, NULL = the null stream).  Calls return once the work is queued,
+ *    except those that fill host memory, which synchronise the stream first.
+ *  - Errors are returned as ess_status; ess_last_error() gives a message for
+ *    the calling thread.  No call aborts the process.
+ *  - The library owns the memory behind an ess_ctx; callers own every pointer
+ *    they pass and may free inputs as soon as the call returns.
+ *  - Random numbers: Philox4x32-10 keyed by the seed, counter
+ *    (pair index, chain, step, stream | problem << 8); Box-Muller in float64.
+ */
+#ifndef ESS_H
+#define ESS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ess_ctx ess_ctx;
+
+typedef enum {
+    ESS_OK = 0,
+    ESS_ERR_INVALID_ARG = 1,      /* null pointer, bad size, bad precision ...   */
+    ESS_ERR_INFEASIBLE_START = 2, /* some chain has a_i^T x0 >= b_i             */
+    ESS_ERR_HIP = 3,              /* a HIP runtime call failed                   */
+    ESS_ERR_OOM = 4,              /* device allocation failed                    */
+    ESS_ERR_UNSUPPORTED = 5       /* size beyond what the kernels support        */
+} ess_status;
+
+/* ess_problem.flags */
+#define ESS_X0_BROADCAST 1u   /* x0 holds one d-vector used by every chain */
+
+/* A whitened problem: N(0, I_d) truncated to {x : A x <= b} (Section 1).
+ * The polytope must have a non-empty interior; x0 must be strictly inside
+ * (a_i^T x0 < b_i for all i), since a start on the boundary leaves the
+ * zero-length single-root case of Figure 2(d). */
+typedef struct {
+    int32_t d;            /* dimension, >= 1                                  */
+    int32_t m;            /* number of constraints, 1 .. 4096                 */
+    int32_t n_chains;     /* independent chains, >= 1                         */
+    int32_t precision;    /* 32: float storage and projections, float64 roots,
+                             interval ends and sampling; 64: float64 throughout */
+    const void* A;        /* device, m x d row-major, T                       */
+    const double* b;      /* device, m                                        */
+    const void* x0;       /* device, n_chains x d (or d with ESS_X0_BROADCAST), T */
+    uint64_t seed;        /* Philox key                                       */
+    double trim_eps;      /* >= 0, radians; every active interval [l, u] becomes
+                             [l + eps, u - eps] at its real ends (Section 3.3) */
+    uint32_t flags;
+} ess_problem;
+
+/* Validates the problem, copies A, b and x0 into library memory, computes
+ * A x0 and checks strict feasibility of every chain.  On success *out holds a
+ * new context at step 0.  ESS_ERR_INFEASIBLE_START names the first offending
+ * chain and row in ess_last_error(). */
+ess_status ess_init(const ess_problem* problem, void* stream, ess_ctx** out);
+
+/* One transition of Algorithm 1 for every chain.  x_out (nullable): n_chains x d,
+ * T, receives the state after the step. */
+ess_status ess_step(ess_ctx* ctx, void* x_out);
+
+/* n_steps transitions.  Every thin-th state is written to trace (nullable):
+ * (n_steps / thin) x n_chains x d, T.  n_rejected (host, nullable) receives the
+ * number of proposals rejected by the safeguard during this call (summed over
+ * chains; a zero-length active set counts as a rejection). */
+ess_status ess_run(ess_ctx* ctx, int64_t n_steps, int64_t thin, void* trace,
+                   int64_t* n_rejected);
+
+/* Current state (n_chains x d, T) and step counter (host). Either may be NULL. */
+ess_status ess_get_state(ess_ctx* ctx, void* x_out, uint64_t* step_out);
+
+/* Replaces the state (n_chains x d, T; strictly feasible) and the step counter.
+ * Running n steps after ess_set_state(x, s) reproduces the run that reached
+ * (x, s), bit for bit. */
+ess_status ess_set_state(ess_ctx* ctx, const void* x_in, uint64_t step);
+
+/* Per-chain rejection counters since ess_init (host, n_chains int64). */
+ess_status ess_rejections(ess_ctx* ctx, int64_t* per_chain);
+
+/* One transition from explicit inputs, for testing against a reference.
+ *  x (n_chains x d, T) becomes the state first (it must be feasible), nu
+ *  (n_chains x d, T) is the ellipse direction and u (n_chains, double, in
+ *  (0, 1)) picks theta.  Afterwards the context holds the new state and its
+ *  step counter is unchanged.
+ *  x_new      (n_chains x d, T): state after the transition
+ *  intervals  (nullable, n_chains x (m + 1) x 2 double): the non-empty active
+ *             intervals after trimming, ascending; n_intervals (nullable,
+ *             n_chains int32) their count
+ *  theta      (nullable, n_chains double): the drawn angle
+ *  rejected   (nullable, n_chains int32): 1 if the safeguard kept x
+ *  pq         (nullable, 2 x n_chains x m, T): the projections A x and A nu
+ *             the kernels used. */
+ess_status ess_transition_explicit(ess_ctx* ctx, const void* x, const void* nu,
+                                   const double* u, void* x_new, double* intervals,
+                                   int32_t* n_intervals, double* theta,
+                                   int32_t* rejected, void* pq);
+
+/* The random numbers step `step` uses: nu (n_chains x d, T, nullable) and the
+ * theta uniforms u (n_chains double, nullable).  Does not change the context. */
+ess_status ess_draw(ess_ctx* ctx, uint64_t step, void* nu, double* u);
+
+void ess_destroy(ess_ctx* ctx);
+
+/* Message for the last failed call on this thread ("" if none). */
+const char* ess_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ESS_H */

@@ -1,0 +1,231 @@
+"""Linear elliptical slice sampling on MI355X (gfx950).
+
+Python binding of libess (include/ess.h).  The functions below carry the C
+names and only marshal arguments: every step of a transition runs in the HIP
+kernels of libess.so.  PyTorch supplies device memory and the stream.
+
+The library must have been built (``python -m paper_2407_10449_amd.build`` or
+``__graft_entry__.build()``); importing the binding does not build it, and
+every call fails loudly if it is missing.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libess.so")
+
+ESS_OK = 0
+ESS_ERR_INVALID_ARG = 1
+ESS_ERR_INFEASIBLE_START = 2
+ESS_ERR_HIP = 3
+ESS_ERR_OOM = 4
+ESS_ERR_UNSUPPORTED = 5
+ESS_X0_BROADCAST = 1
+
+STATUS_NAMES = {0: "ESS_OK", 1: "ESS_ERR_INVALID_ARG", 2: "ESS_ERR_INFEASIBLE_START",
+                3: "ESS_ERR_HIP", 4: "ESS_ERR_OOM", 5: "ESS_ERR_UNSUPPORTED"}
+
+
+class EssError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class EssProblem(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("m", ctypes.c_int32), ("n_chains", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("A", ctypes.c_void_p), ("b", ctypes.c_void_p),
+                ("x0", ctypes.c_void_p), ("seed", ctypes.c_uint64), ("trim_eps", ctypes.c_double),
+                ("flags", ctypes.c_uint32)]
+
+
+_LIB = None
+
+_P = ctypes.c_void_p
+_SIGS = {
+    "ess_init": ([ctypes.POINTER(EssProblem), _P, ctypes.POINTER(_P)], ctypes.c_int),
+    "ess_step": ([_P, _P], ctypes.c_int),
+    "ess_run": ([_P, ctypes.c_int64, ctypes.c_int64, _P, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "ess_get_state": ([_P, _P, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+    "ess_set_state": ([_P, _P, ctypes.c_uint64], ctypes.c_int),
+    "ess_rejections": ([_P, _P], ctypes.c_int),
+    "ess_transition_explicit": ([_P] * 10, ctypes.c_int),
+    "ess_draw": ([_P, ctypes.c_uint64, _P, _P], ctypes.c_int),
+    "ess_destroy": ([_P], None),
+    "ess_last_error": ([], ctypes.c_char_p),
+}
+
+
+def lib():
+    """The loaded libess.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libess.so is not built at {LIB_PATH}; run "
+                              "`python -m paper_2407_10449_amd.build` first")
+        h = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(h, name)
+            fn.argtypes = args
+            fn.restype = res
+        _LIB = h
+    return _LIB
+
+
+def _check(status):
+    if status != ESS_OK:
+        raise EssError(status, lib().ess_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+# ----------------------------------------------------------- C-named calls
+def ess_init(problem, stream=None):
+    ctx = ctypes.c_void_p()
+    _check(lib().ess_init(ctypes.byref(problem), _stream_handle(stream), ctypes.byref(ctx)))
+    return ctx
+
+
+def ess_step(ctx, x_out=None):
+    _check(lib().ess_step(ctx, _ptr(x_out)))
+
+
+def ess_run(ctx, n_steps, thin=1, trace=None, want_rejections=False):
+    nrej = ctypes.c_int64(0)
+    _check(lib().ess_run(ctx, int(n_steps), int(thin), _ptr(trace),
+                         ctypes.byref(nrej) if want_rejections else None))
+    return nrej.value if want_rejections else None
+
+
+def ess_get_state(ctx, x_out=None):
+    step = ctypes.c_uint64(0)
+    _check(lib().ess_get_state(ctx, _ptr(x_out), ctypes.byref(step)))
+    return step.value
+
+
+def ess_set_state(ctx, x_in, step):
+    _check(lib().ess_set_state(ctx, _ptr(x_in), int(step)))
+
+
+def ess_rejections(ctx, n_chains):
+    out = np.zeros(n_chains, dtype=np.int64)
+    _check(lib().ess_rejections(ctx, out.ctypes.data_as(ctypes.c_void_p)))
+    return out
+
+
+def ess_transition_explicit(ctx, x, nu, u, x_new, intervals=None, n_intervals=None,
+                            theta=None, rejected=None, pq=None):
+    _check(lib().ess_transition_explicit(ctx, _ptr(x), _ptr(nu), _ptr(u), _ptr(x_new),
+                                         _ptr(intervals), _ptr(n_intervals), _ptr(theta),
+                                         _ptr(rejected), _ptr(pq)))
+
+
+def ess_draw(ctx, step, nu=None, u=None):
+    _check(lib().ess_draw(ctx, int(step), _ptr(nu), _ptr(u)))
+
+
+def ess_destroy(ctx):
+    if ctx:
+        lib().ess_destroy(ctx)
+
+
+def ess_last_error():
+    return lib().ess_last_error().decode()
+
+
+# ----------------------------------------------------------- convenience
+class Sampler:
+    """Owns one ess_ctx.  A, b, x0 may be numpy arrays or torch tensors; they
+    are copied to the device in the working precision before ess_init."""
+
+    def __init__(self, A, b, x0, n_chains, seed=0, precision=32, trim_eps=None,
+                 device="cuda", stream=None):
+        import torch
+        self.torch = torch
+        self.dtype = torch.float32 if precision == 32 else torch.float64
+        self.precision = precision
+        self.device = torch.device(device)
+        self.stream = stream
+        A = torch.as_tensor(np.asarray(A) if not torch.is_tensor(A) else A)
+        self.m, self.d = A.shape
+        self.n_chains = int(n_chains)
+        self.A = A.to(self.device, self.dtype).contiguous()
+        self.b = torch.as_tensor(np.asarray(b) if not torch.is_tensor(b) else b).to(
+            self.device, torch.float64).contiguous()
+        x0 = torch.as_tensor(np.asarray(x0) if not torch.is_tensor(x0) else x0).to(
+            self.device, self.dtype).contiguous()
+        flags = ESS_X0_BROADCAST if x0.dim() == 1 else 0
+        if trim_eps is None:
+            trim_eps = 1e-6 if precision == 32 else 0.0
+        self.trim_eps = float(trim_eps)
+        self.problem = EssProblem(self.d, self.m, self.n_chains, precision, self.A.data_ptr(),
+                                  self.b.data_ptr(), x0.data_ptr(), int(seed), self.trim_eps, flags)
+        self.ctx = ess_init(self.problem, stream)
+
+    def _empty(self, *shape, dtype=None):
+        return self.torch.empty(*shape, device=self.device, dtype=dtype or self.dtype)
+
+    def step(self):
+        x = self._empty(self.n_chains, self.d)
+        ess_step(self.ctx, x)
+        return x
+
+    def run(self, n_steps, thin=1, keep_trace=True, count_rejections=True):
+        tr = self._empty(n_steps // thin, self.n_chains, self.d) if keep_trace and n_steps // thin else None
+        nrej = ess_run(self.ctx, n_steps, thin, tr, count_rejections)
+        return tr, nrej
+
+    def state(self):
+        x = self._empty(self.n_chains, self.d)
+        step = ess_get_state(self.ctx, x)
+        return x, step
+
+    def set_state(self, x, step):
+        x = self.torch.as_tensor(x).to(self.device, self.dtype).contiguous()
+        ess_set_state(self.ctx, x, step)
+
+    def rejections(self):
+        return ess_rejections(self.ctx, self.n_chains)
+
+    def draw(self, step):
+        nu = self._empty(self.n_chains, self.d)
+        u = self._empty(self.n_chains, dtype=self.torch.float64)
+        ess_draw(self.ctx, step, nu, u)
+        return nu, u
+
+    def transition_explicit(self, x, nu, u):
+        t = self.torch
+        x = t.as_tensor(x).to(self.device, self.dtype).contiguous()
+        nu = t.as_tensor(nu).to(self.device, self.dtype).contiguous()
+        u = t.as_tensor(u).to(self.device, t.float64).contiguous()
+        C, m = self.n_chains, self.m
+        out = dict(x_new=self._empty(C, self.d),
+                   intervals=t.zeros(C, m + 1, 2, device=self.device, dtype=t.float64),
+                   n_intervals=t.zeros(C, device=self.device, dtype=t.int32),
+                   theta=t.zeros(C, device=self.device, dtype=t.float64),
+                   rejected=t.zeros(C, device=self.device, dtype=t.int32),
+                   pq=t.zeros(2, C, m, device=self.device, dtype=self.dtype))
+        ess_transition_explicit(self.ctx, x, nu, u, out["x_new"], out["intervals"],
+                                out["n_intervals"], out["theta"], out["rejected"], out["pq"])
+        return out
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            ess_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

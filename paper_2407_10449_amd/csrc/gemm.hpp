@@ -1,0 +1,249 @@
+// Constraint projections for a block of chains: out[c][i] = a_i^T y_c.
+//
+// One launch covers a "virtual" chain axis of length 2 * Cp: columns
+// [0, Cp) read the proposals x' (their projections A x' are the safeguard
+// check of Section 3.3 and, once accepted, the next step's A x_t), columns
+// [Cp, 2 Cp) read the next ellipse directions nu (their projections A nu are
+// the q_i of the trigonometric equation, Section 2).  The paper notes both
+// products are the O(md) part of a step (Section 2.2).
+//
+// Layout (all padded by the host so no tile ever leaves its buffers):
+//   A  [mp][dp]  row-major, rows >= m and columns >= d are zero
+//   Y  [Cp][dp]  one row per chain (x' or nu), columns >= d are zero
+//   P  [2][Cp][mp], Q [Cp][mp]: chain-major so a chain's m projections are
+//   contiguous for the per-chain interval kernel.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ess {
+
+struct ProjOut {
+    int m, C, Cp, mp;
+    const double* b;
+    void* P;          // [2][Cp][mp]: the committed projections live in P[sel[c]]
+    void* Q;          // [Cp][mp]
+    const int* sel;   // [Cp]
+    int* flag;        // [Cp]: set to 1 when a checked row is violated
+    int p_direct;     // 1: write P[sel[c]] (state replaced), 0: P[1 - sel[c]] (proposal)
+    int strict;       // 1: violation is p >= b (start check), 0: p > b (safeguard)
+};
+
+// Four consecutive rows i0 .. i0 + 3 of virtual column n.
+template <typename T>
+__device__ __forceinline__ void proj_store4(const ProjOut& o, int n, int i0, T v0, T v1, T v2,
+                                            T v3) {
+    if (n < o.Cp) {
+        const int c = n;
+        const int s = o.sel[c];
+        const int buf = o.p_direct ? s : 1 - s;
+        T* dst = static_cast<T*>(o.P) + (static_cast<size_t>(buf) * o.Cp + c) * o.mp + i0;
+        if constexpr (sizeof(T) == 4) {
+            *reinterpret_cast<float4*>(dst) = make_float4(v0, v1, v2, v3);
+        } else {
+            dst[0] = v0; dst[1] = v1; dst[2] = v2; dst[3] = v3;
+        }
+        if (c < o.C) {
+            const T vv[4] = {v0, v1, v2, v3};
+            bool bad = false;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + r;
+                if (i < o.m) {
+                    const double pv = static_cast<double>(vv[r]);
+                    const double bi = o.b[i];
+                    bad |= o.strict ? (pv >= bi) : (pv > bi);
+                }
+            }
+            if (bad) o.flag[c] = 1;   // every writer stores the same value
+        }
+    } else {
+        const int c = n - o.Cp;
+        T* dst = static_cast<T*>(o.Q) + static_cast<size_t>(c) * o.mp + i0;
+        if constexpr (sizeof(T) == 4) {
+            *reinterpret_cast<float4*>(dst) = make_float4(v0, v1, v2, v3);
+        } else {
+            dst[0] = v0; dst[1] = v1; dst[2] = v2; dst[3] = v3;
+        }
+    }
+}
+
+// blockIdx -> (tile row, tile column).  Workgroups are dispatched round-robin
+// over the 8 XCDs, so consecutive ids land on different L2s.  The id is first
+// regrouped so that each XCD receives a contiguous run of logical tiles, and
+// logical tiles walk a band of group_m tile rows before moving right: the
+// tiles one XCD holds share few A row panels and few chain panels.
+__device__ __forceinline__ void tile_coords(int bid, int tiles_m, int tiles_n, int group_m,
+                                            int& tm, int& tn) {
+    const int nt = tiles_m * tiles_n;
+    int logical = bid;
+    if ((nt & 7) == 0) logical = (bid & 7) * (nt >> 3) + (bid >> 3);
+    const int per_group = group_m * tiles_n;
+    const int g = logical / per_group;
+    const int first = g * group_m;
+    const int rows = min(tiles_m - first, group_m);
+    const int r = logical - g * per_group;
+    tm = first + r % rows;
+    tn = r / rows;
+}
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// float32 projections on the matrix cores (v_mfma_f32_16x16x4_f32), float32
+// accumulation.  256 threads = 2 x 2 waves, each wave owns a (BM/2) x (BN/2)
+// block of 16 x 16 MFMA tiles.  K advances 32 at a time through a double-
+// buffered LDS tile.  Inside each group of 16 k, lane l supplies the four k
+// values 4 (l / 16) .. 4 (l / 16) + 3 of its row as one 16-byte LDS read, and
+// MFMA number kk uses element kk: A and B use the same k for the same (lane
+// group, kk), so the contraction covers all 16 k exactly once.  Rows in LDS
+// are padded to 36 floats, which spreads the 16 rows of one read over
+// distinct banks.
+template <int BM, int BN>
+__global__ __launch_bounds__(256) void proj_gemm_f32(const float* __restrict__ A,
+                                                     const float* __restrict__ B0,
+                                                     const float* __restrict__ B1, int K,
+                                                     int tiles_m, int tiles_n, int tn0,
+                                                     int group_m, ProjOut o) {
+    constexpr int BK = 32, LK = BK + 4;
+    constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 16, TN = WN / 16;
+    constexpr int ALD = BM * BK / 4 / 256, BLD = BN * BK / 4 / 256;
+    static_assert(ALD >= 1 && BLD >= 1, "tile too small for 256 threads");
+    __shared__ __attribute__((aligned(16))) float As[2][BM * LK];
+    __shared__ __attribute__((aligned(16))) float Bs[2][BN * LK];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    int tm, tn;
+    tile_coords(blockIdx.x, tiles_m, tiles_n, group_m, tm, tn);
+    tn += tn0;
+    const int m0 = tm * BM, n0 = tn * BN;
+    const float* Ab = A + static_cast<size_t>(m0) * K;
+    const float* Bb = (n0 < o.Cp) ? B0 + static_cast<size_t>(n0) * K
+                                  : B1 + static_cast<size_t>(n0 - o.Cp) * K;
+
+    f32x4 ra[ALD], rb[BLD];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < ALD; ++i) {
+            const int idx = tid + i * 256, row = idx >> 3, kq = idx & 7;
+            ra[i] = *reinterpret_cast<const f32x4*>(Ab + static_cast<size_t>(row) * K + k0 + kq * 4);
+        }
+#pragma unroll
+        for (int i = 0; i < BLD; ++i) {
+            const int idx = tid + i * 256, row = idx >> 3, kq = idx & 7;
+            rb[i] = *reinterpret_cast<const f32x4*>(Bb + static_cast<size_t>(row) * K + k0 + kq * 4);
+        }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < ALD; ++i) {
+            const int idx = tid + i * 256, row = idx >> 3, kq = idx & 7;
+            *reinterpret_cast<f32x4*>(&As[buf][row * LK + kq * 4]) = ra[i];
+        }
+#pragma unroll
+        for (int i = 0; i < BLD; ++i) {
+            const int idx = tid + i * 256, row = idx >> 3, kq = idx & 7;
+            *reinterpret_cast<f32x4*>(&Bs[buf][row * LK + kq * 4]) = rb[i];
+        }
+    };
+
+    f32x4 acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    const int KT = K / BK;
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    for (int kt = 0; kt < KT; ++kt) {
+        const int buf = kt & 1;
+        if (kt + 1 < KT) gload((kt + 1) * BK);
+#pragma unroll
+        for (int kc = 0; kc < BK / 16; ++kc) {
+            f32x4 af[TM], bf[TN];
+            const int kofs = kc * 16 + (lane >> 4) * 4;
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+                af[i] = *reinterpret_cast<const f32x4*>(
+                    &As[buf][(wm * WM + i * 16 + (lane & 15)) * LK + kofs]);
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+                bf[j] = *reinterpret_cast<const f32x4*>(
+                    &Bs[buf][(wn * WN + j * 16 + (lane & 15)) * LK + kofs]);
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][kk], bf[j][kk],
+                                                                         acc[i][j], 0, 0, 0);
+        }
+        if (kt + 1 < KT) lstore(buf ^ 1);
+        __syncthreads();
+    }
+
+    // MFMA 16x16 output: lane l holds rows 4 (l / 16) .. + 3 of column l % 16.
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const int i0 = m0 + wm * WM + i * 16 + (lane >> 4) * 4;
+            const int n = n0 + wn * WN + j * 16 + (lane & 15);
+            proj_store4<float>(o, n, i0, acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]);
+        }
+}
+
+// float64 projections on the vector ALUs (MI355X runs float64 FMA on the
+// vector units at the same rate as its float64 matrix cores).  64 x 64 tile,
+// each thread a 4 x 4 block: rows 4 ty .. 4 ty + 3, columns tx + 16 u.
+template <int BM, int BN>
+__global__ __launch_bounds__(256) void proj_gemm_f64(const double* __restrict__ A,
+                                                     const double* __restrict__ B0,
+                                                     const double* __restrict__ B1, int K,
+                                                     int tiles_m, int tiles_n, int tn0,
+                                                     int group_m, ProjOut o) {
+    static_assert(BM == 64 && BN == 64, "float64 projection tile is 64 x 64");
+    constexpr int BK = 16;
+    __shared__ double As[BK][BM + 1];
+    __shared__ double Bs[BK][BN + 1];
+    const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+    int tm, tn;
+    tile_coords(blockIdx.x, tiles_m, tiles_n, group_m, tm, tn);
+    tn += tn0;
+    const int m0 = tm * BM, n0 = tn * BN;
+    const double* Ab = A + static_cast<size_t>(m0) * K;
+    const double* Bb = (n0 < o.Cp) ? B0 + static_cast<size_t>(n0) * K
+                                   : B1 + static_cast<size_t>(n0 - o.Cp) * K;
+    double acc[4][4] = {};
+    for (int k0 = 0; k0 < K; k0 += BK) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int idx = tid + r * 256, row = idx / BK, k = idx % BK;
+            As[k][row] = Ab[static_cast<size_t>(row) * K + k0 + k];
+            Bs[k][row] = Bb[static_cast<size_t>(row) * K + k0 + k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < BK; ++k) {
+            double a[4], bv[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) a[v] = As[k][ty * 4 + v];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) bv[u] = Bs[k][tx + 16 * u];
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc[v][u] = fma(a[v], bv[u], acc[v][u]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        proj_store4<double>(o, n0 + tx + 16 * u, m0 + ty * 4, acc[0][u], acc[1][u], acc[2][u],
+                            acc[3][u]);
+}
+
+}  // namespace ess

@@ -1,0 +1,203 @@
+"""HIP path vs the CPU oracle, through the C ABI (needs an MI355X)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import ess as ref_ess
+from oracle import philox as ref_philox
+from parity import TOL_ANG, compare_transition, pieces, intervals_match
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def E():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2407_10449_amd as E
+    E.lib()
+    return E
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def explicit_case(E, A, b, C, precision, seed, eps, n_ref=None, rng_seed=0):
+    """One explicit transition on the GPU and in the oracle on identical inputs."""
+    rng = np.random.default_rng(rng_seed)
+    npdt = np.float32 if precision == 32 else np.float64
+    x = synth.random_states(rng, A, b, C, scale=0.7, margin=1e-3).astype(npdt)
+    nu = rng.standard_normal(x.shape).astype(npdt)
+    u = rng.uniform(size=C)
+    s = E.Sampler(A, b, x, C, seed=seed, precision=precision, trim_eps=eps)
+    out = s.transition_explicit(x, nu, u)
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    s.close()
+    idx = np.arange(C) if n_ref is None else np.linspace(0, C - 1, n_ref).astype(int)
+    Ab = A.astype(npdt).astype(np.float64)
+    sub = {k: (v[idx] if k != "pq" else v[:, idx]) for k, v in g.items()}
+    ref = ref_ess.transition(Ab, b, x[idx].astype(np.float64), nu[idx].astype(np.float64), u[idx],
+                             eps=eps, store=npdt)
+    # second tier: the oracle fed the projections the kernels used
+    ref2 = ref_ess.transition(Ab, b, x[idx].astype(np.float64), nu[idx].astype(np.float64), u[idx],
+                              eps=eps, store=npdt, pq=(sub["pq"][0], sub["pq"][1]))
+    return Ab, x[idx].astype(np.float64), nu[idx], u[idx], sub, ref, ref2
+
+
+CASES = [
+    # name, d, m, C, precision, eps
+    ("ragged_f32", 37, 150, 300, 32, 1e-6),
+    ("bm128_f32", 200, 1030, 600, 32, 1e-6),
+    ("small_f64", 10, 20, 16, 64, 0.0),
+    ("ragged_f64", 65, 300, 130, 64, 0.0),
+    ("univariate_f32", 1, 2, 64, 32, 0.0),
+    ("one_chain_f32", 50, 100, 1, 32, 1e-6),
+    ("max_m_f32", 64, 4096, 64, 32, 1e-6),
+]
+
+
+@pytest.mark.parametrize("name,d,m,C,precision,eps", CASES, ids=[c[0] for c in CASES])
+def test_explicit_transition_matches_oracle(E, name, d, m, C, precision, eps):
+    say(f"[explicit] {name} d={d} m={m} C={C} prec={precision}")
+    rng = np.random.default_rng(d * 7 + m)
+    if name.startswith("univariate"):
+        pr = synth.univariate(-1.0, 3.0)
+        A, b = pr.A, pr.b
+    else:
+        A = rng.standard_normal((m, d)) / math.sqrt(d)
+        b = rng.uniform(0.5, 1.5, m)
+    Ab, x, nu, u, g, ref, ref2 = explicit_case(E, A, b, C, precision, seed=5, eps=eps,
+                                               n_ref=min(C, 96), rng_seed=m)
+    fails, excused = compare_transition(Ab, b, x, nu, u, g, ref)
+    assert not fails, "\n".join(fails[:10])
+    assert excused <= max(1, len(u) // 20)
+    # tier 2: same projections -> intervals and theta agree to float64 rounding
+    for c in range(len(u)):
+        gi = pieces(g["intervals"][c], g["n_intervals"][c], 0.0)
+        assert intervals_match(gi, ref2["intervals"][c], 1e-9), (c, gi, ref2["intervals"][c])
+        assert abs(g["theta"][c] - ref2["theta"][c]) <= 1e-9 * max(1.0, len(gi)), c
+
+
+def test_explicit_full_size_gp_rbf(E):
+    """d=1000, m=2000, 1024 chains (the benchmarked shape): sampled chains."""
+    say("[explicit] gp_rbf full size")
+    pr = synth.gp_rbf()
+    Ab, x, nu, u, g, ref, ref2 = explicit_case(E, pr.A, pr.b, pr.n_chains, 32, seed=0, eps=1e-6,
+                                               n_ref=24, rng_seed=3)
+    fails, excused = compare_transition(Ab, pr.b, x, nu, u, g, ref)
+    assert not fails, "\n".join(fails[:10])
+    for c in range(len(u)):
+        gi = pieces(g["intervals"][c], g["n_intervals"][c], 0.0)
+        assert intervals_match(gi, ref2["intervals"][c], 1e-9)
+
+
+def test_no_constraint_crosses_the_ellipse(E):
+    """All rows padded (b / r > 1): the active set is the whole ellipse."""
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((40, 8)) * 1e-3
+    b = np.full(40, 10.0)
+    Ab, x, nu, u, g, ref, _ = explicit_case(E, A, b, 32, 32, seed=1, eps=1e-6)
+    assert (g["n_intervals"] == 1).all()
+    assert np.allclose(g["intervals"][:, 0], [0.0, 2 * math.pi])
+    fails, _ = compare_transition(Ab, b, x, nu, u, g, ref)
+    assert not fails
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_philox_stream_matches_oracle(E, precision):
+    pr = synth.small_fp64(d=33, m=20, n_chains=70)
+    s = E.Sampler(pr.A, pr.b, pr.x0, pr.n_chains, seed=0xDEADBEEF12345, precision=precision)
+    for step in (0, 1, 12345):
+        nu, u = s.draw(step)
+        nu, u = nu.cpu().numpy(), u.cpu().numpy()
+        rn = ref_philox.normals(0xDEADBEEF12345, step, np.arange(pr.n_chains), pr.d)
+        ru = ref_philox.uniforms(0xDEADBEEF12345, step, np.arange(pr.n_chains))
+        assert np.array_equal(u, ru)                 # integer path: bit-exact
+        if precision == 64:
+            assert np.max(np.abs(nu - rn) / np.maximum(np.abs(rn), 1e-300)) < 1e-14
+        else:
+            diff = nu != rn.astype(np.float32)
+            assert diff.mean() < 1e-3                 # libm ulp ties only
+            assert np.max(np.abs(nu - rn)) < 1e-6
+    s.close()
+
+
+def test_run_matches_oracle_fp64(E):
+    """Seeded float64 runs follow the oracle's trajectories step by step."""
+    pr = synth.small_fp64()
+    T = 60
+    s = E.Sampler(pr.A, pr.b, pr.x0, pr.n_chains, seed=0, precision=64, trim_eps=0.0)
+    tr, nrej = s.run(T)
+    tr = tr.cpu().numpy()
+    rtr, _, rrej = ref_ess.run(pr.A, pr.b, pr.x0, pr.n_chains, T, seed=0)
+    err = np.abs(tr - rtr).max(axis=(0, 2))
+    assert (err < 1e-9).all(), err
+    assert nrej == rrej.sum() == 0
+    s.close()
+
+
+def test_run_matches_oracle_fp32_first_steps(E):
+    pr = synth.box_halfspace(n_chains=256)
+    T = 4
+    s = E.Sampler(pr.A, pr.b, pr.x0, pr.n_chains, seed=0, precision=32, trim_eps=1e-6)
+    tr, _ = s.run(T)
+    tr = tr.cpu().numpy()
+    rtr, _, _ = ref_ess.run(pr.A, pr.b, pr.x0, pr.n_chains, T, seed=0, eps=1e-6, store=np.float32)
+    err = np.abs(tr - rtr).max(axis=(0, 2))
+    ok = err < 1e-4
+    assert ok.mean() > 0.98, np.sort(err)[-10:]
+    s.close()
+
+
+def test_thin_trace_and_checkpoint_resume(E):
+    pr = synth.box_halfspace(n_chains=300)
+    a = E.Sampler(pr.A, pr.b, pr.x0, pr.n_chains, seed=9, precision=32)
+    full, _ = a.run(12, thin=3)
+    b = E.Sampler(pr.A, pr.b, pr.x0, pr.n_chains, seed=9, precision=32)
+    half, _ = b.run(6, thin=3)
+    x, step = b.state()
+    assert step == 6
+    c = E.Sampler(pr.A, pr.b, pr.x0, pr.n_chains, seed=9, precision=32)
+    c.set_state(x, step)
+    rest, _ = c.run(6, thin=3)
+    assert torch.equal(full[:2], half) and torch.equal(full[2:], rest)
+    # same seed, same trace; rerun is bit-identical
+    d = E.Sampler(pr.A, pr.b, pr.x0, pr.n_chains, seed=9, precision=32)
+    again, _ = d.run(12, thin=3)
+    assert torch.equal(full, again)
+    for s in (a, b, c, d):
+        s.close()
+
+
+def test_iterates_stay_feasible(E):
+    pr = synth.box_halfspace(n_chains=512)
+    s = E.Sampler(pr.A, pr.b, pr.x0, pr.n_chains, seed=2, precision=32)
+    tr, nrej = s.run(50)
+    X = tr.double().cpu().numpy()
+    slack = pr.b - X @ pr.A.T
+    bound = 2 * pr.d * 2.0 ** -24 * (np.abs(X) @ np.abs(pr.A).T)
+    assert (slack >= -bound).all()
+    assert s.rejections().sum() == nrej
+    s.close()
+
+
+def test_errors_are_reported(E):
+    pr = synth.small_fp64()
+    with pytest.raises(E.EssError) as ei:
+        E.Sampler(pr.A, pr.b, np.full(pr.d, 50.0), 4, precision=64)
+    assert ei.value.status == E.ESS_ERR_INFEASIBLE_START and "chain 0" in str(ei.value)
+    with pytest.raises(E.EssError) as ei:
+        E.Sampler(np.zeros((5000, 3)), np.ones(5000), np.zeros(3), 2)
+    assert ei.value.status == E.ESS_ERR_UNSUPPORTED
+    with pytest.raises(E.EssError) as ei:
+        E.Sampler(pr.A, pr.b, pr.x0, 4, precision=16)
+    assert ei.value.status == E.ESS_ERR_INVALID_ARG
+    prob = E.EssProblem(3, 2, 4, 32, None, None, None, 0, 0.0, 0)
+    with pytest.raises(E.EssError):
+        E.ess_init(prob)
