@@ -1,0 +1,160 @@
+#!/usr/bin/env python
+"""Throughput of linear elliptical slice sampling on one MI355X.
+
+Workload (timed): the GP-classification-style truncation, d = 1000,
+m = 2000 (1000 rows S L from the Cholesky factor of an RBF kernel with
+lengthscale 0.2 on 1000 points in [0,1]^2, S a random +-1 diagonal, b = 0.1,
+plus 1000 random halfspaces), 1024 chains, float32 storage and matrix-core
+projections, float64 roots and interval ends, trim eps 1e-6, Philox seed 0.
+One step = one transition of every chain (Algorithm 1 of arXiv 2407.10449):
+draw, project, roots, sort + cumulative max, theta, move, safeguard check.
+Inputs are resident in HBM before the timed region starts.
+
+Prints one JSON line.  `roofline` covers the dominant kernel (the projection
+GEMM), timed with HIP events on the library's stream during the timed region;
+`cpu_baseline` is the float64 CPU oracle on a bounded sample of the same
+workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ESS chain-steps/s at d=1000,m=2000; batched+warm-start vs plain ESS/s, 1 GPU"
+PEAK_FP32_MFMA_TFLOPS = 157.3
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "proj_gemm_f32_gp_rbf_traffic.txt")
+
+
+def kernel_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2407_10449_amd", "csrc", "gemm.hpp"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per projection launch from the committed counter summary, or
+    None when the kernel source changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("gemm_source_sha256_16") != kernel_source_digest():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(pr, seconds, n_chains=64):
+    """The oracle (float64 numpy, BLAS threads as configured) on n_chains of the
+    same problem, stepping until `seconds` of CPU work have passed."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import ess as ref
+    x = np.broadcast_to(pr.x0, (n_chains, pr.d)).copy()
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        _, x, _ = ref.run(pr.A, pr.b, x, n_chains, 1, seed=0, eps=1e-6, store=np.float32,
+                          start_step=steps)
+        steps += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    dt = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    return {"value": n_chains * steps / dt, "unit": "chain-steps/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"gp_rbf d={pr.d} m={pr.m}: {n_chains} chains x {steps} steps "
+                      f"({dt:.1f} s, float64 numpy oracle)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: chains shard across GPUs with no per-step traffic, "
+              "and this build runs and reports a single MI355X only (use --gpus 1).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2407_10449_amd as E
+    import synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    E.lib()
+    pr = synth.gp_rbf()
+    C, d, m = pr.n_chains, pr.d, pr.m
+    s = E.Sampler(pr.A, pr.b, pr.x0, C, seed=0, precision=32, trim_eps=1e-6)
+    E.ess_run(s.ctx, args.warmup, 1, None, False)
+    torch.cuda.synchronize()
+
+    E.ess_profile(s.ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    E.ess_run(s.ctx, args.steps, 1, None, False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    proj_ms, proj_n = E.ess_profile_read(s.ctx, E.ESS_KERNEL_PROJECT)
+    samp_ms, samp_n = E.ess_profile_read(s.ctx, E.ESS_KERNEL_SAMPLE)
+    other_ms, other_n = E.ess_profile_read(s.ctx, E.ESS_KERNEL_OTHER)
+    E.ess_profile(s.ctx, False)
+    rej = int(s.rejections().sum())
+    s.close()
+
+    value = C * args.steps / dt
+    flops_per_launch = 4.0 * m * d * C           # A x' and A nu for every chain
+    proj_avg_s = proj_ms / max(proj_n, 1) / 1e3
+    achieved = flops_per_launch / proj_avg_s / 1e12 if proj_n else None
+    traffic = measured_traffic()
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "chain-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "gp_rbf", "d": d, "m": m, "chains": C,
+                   "storage": "f32", "roots": "f64", "trim_eps": 1e-6, "seed": 0},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS,
+                     "unit": "TFLOP/s",
+                     "frac": (achieved / PEAK_FP32_MFMA_TFLOPS) if achieved else None,
+                     "traffic": traffic,
+                     "kernel": "proj_gemm_f32 (A x' and A nu, 4 m d C flop per launch)"},
+        "kernels_ms_per_step": {"project": proj_ms / max(proj_n, 1),
+                                "sample": samp_ms / max(samp_n, 1),
+                                "other_total": other_ms},
+        "rejections": rej,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(pr, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -47,6 +47,11 @@ typedef enum {
 
 /* ess_problem.flags */
 #define ESS_X0_BROADCAST 1u   /* x0 holds one d-vector used by every chain */
+#define ESS_PER_CHAIN_B 4u    /* b holds n_chains x m values: chain c samples the
+                                 polytope {A x <= b_c} (a family sharing A) */
+#define ESS_SORT_FULL 2u      /* build every chain's active intervals with a full
+                                 sort of all crossing rows instead of the bucketed
+                                 sort (same intervals; for comparison) */
 
 /* A whitened problem: N(0, I_d) truncated to {x : A x <= b} (Section 1).
  * The polytope must have a non-empty interior; x0 must be strictly inside
@@ -59,7 +64,7 @@ typedef struct {
     int32_t precision;    /* 32: float storage and projections, float64 roots,
                              interval ends and sampling; 64: float64 throughout */
     const void* A;        /* device, m x d row-major, T                       */
-    const double* b;      /* device, m                                        */
+    const double* b;      /* device, m (n_chains x m with ESS_PER_CHAIN_B)    */
     const void* x0;       /* device, n_chains x d (or d with ESS_X0_BROADCAST), T */
     uint64_t seed;        /* Philox key                                       */
     double trim_eps;      /* >= 0, radians; every active interval [l, u] becomes
@@ -72,6 +77,18 @@ typedef struct {
  * new context at step 0.  ESS_ERR_INFEASIBLE_START names the first offending
  * chain and row in ess_last_error(). */
 ess_status ess_init(const ess_problem* problem, void* stream, ess_ctx** out);
+
+/* Many independent problems in one context (a batch of polytopes of uneven
+ * d and m).  problems[p] is read as for ess_init; precision must be 32 and
+ * ESS_SORT_FULL is not offered.  Problem p's chains use p as the Philox problem
+ * word.  Every step of ess_run advances all chains of all problems with one
+ * persistent launch: the projection tiles of every problem, then every chain,
+ * each chain starting once its problem's tiles are done.
+ * For a batched context, state and trace arrays hold the problems one after
+ * another, each as n_chains x d (float); ess_rejections lists chains in the same
+ * order.  ess_transition_explicit and ess_draw return ESS_ERR_UNSUPPORTED. */
+ess_status ess_init_batched(const ess_problem* problems, int32_t n_problems, void* stream,
+                            ess_ctx** out);
 
 /* One transition of Algorithm 1 for every chain.  x_out (nullable): n_chains x d,
  * T, receives the state after the step. */
@@ -116,6 +133,20 @@ ess_status ess_transition_explicit(ess_ctx* ctx, const void* x, const void* nu,
 /* The random numbers step `step` uses: nu (n_chains x d, T, nullable) and the
  * theta uniforms u (n_chains double, nullable).  Does not change the context. */
 ess_status ess_draw(ess_ctx* ctx, uint64_t step, void* nu, double* u);
+
+/* Kernel timing for measurement.  While enabled, every launch made by ess_run
+ * is bracketed by a pair of HIP events on the context's stream; ess_profile_read
+ * synchronises the stream and returns, for one kernel kind, the summed duration
+ * (host, milliseconds) and the number of launches since profiling was enabled
+ * or last read.  Kinds: ESS_KERNEL_PROJECT (projection GEMMs covering both the
+ * proposals and the next directions), ESS_KERNEL_SAMPLE (per-chain roots, sort,
+ * sweep, theta and move), ESS_KERNEL_OTHER (everything else). */
+#define ESS_KERNEL_PROJECT 0
+#define ESS_KERNEL_SAMPLE 1
+#define ESS_KERNEL_OTHER 2
+#define ESS_KERNEL_BATCHED 3   /* the persistent step of a batched context */
+ess_status ess_profile(ess_ctx* ctx, int enable);
+ess_status ess_profile_read(ess_ctx* ctx, int kind, double* total_ms, int64_t* count);
 
 void ess_destroy(ess_ctx* ctx);
 

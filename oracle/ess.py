@@ -167,7 +167,8 @@ def sample_theta(lo, hi, u):
 def transition(A, b, x, nu, u, eps=0.0, pq=None, store=np.float64):
     """One transition for C chains.
 
-    A (m, d), b (m,), x (C, d), nu (C, d), u (C,).  If pq = (P, Q) (each
+    A (m, d), b (m,) or (C, m) (one polytope per chain), x (C, d), nu (C, d),
+    u (C,).  If pq = (P, Q) (each
     (C, m)) is given, those projections are used instead of A x and A nu.
     The proposal is rounded to `store` before the feasibility check, as the
     code under test stores it.
@@ -183,7 +184,8 @@ def transition(A, b, x, nu, u, eps=0.0, pq=None, store=np.float64):
         P, Q = x @ A.T, nu @ A.T
     else:
         P, Q = (np.asarray(t, dtype=np.float64) for t in pq)
-    alpha, beta, _ = roots(P, Q, b[None, :])
+    bb = b[None, :] if b.ndim == 1 else b
+    alpha, beta, _ = roots(P, Q, bb)
     lo, hi = alg3_candidates(alpha, beta)
     lo, hi = trim(lo, hi, eps)
     C = x.shape[0]
@@ -196,7 +198,7 @@ def transition(A, b, x, nu, u, eps=0.0, pq=None, store=np.float64):
     ct, st = np.cos(theta), np.sin(theta)
     x_prop = x * ct[:, None] + nu * st[:, None]
     x_prop = x_prop.astype(store).astype(np.float64)
-    viol = (x_prop @ A.T > b[None, :]).any(axis=1)
+    viol = (x_prop @ A.T > bb).any(axis=1)
     rejected = viol | (total <= 0.0)
     x_new = np.where(rejected[:, None], x, x_prop)
     return dict(x_new=x_new, rejected=rejected, theta=theta, total=total,

@@ -23,6 +23,8 @@ ESS_ERR_HIP = 3
 ESS_ERR_OOM = 4
 ESS_ERR_UNSUPPORTED = 5
 ESS_X0_BROADCAST = 1
+ESS_SORT_FULL = 2
+ESS_PER_CHAIN_B = 4
 
 STATUS_NAMES = {0: "ESS_OK", 1: "ESS_ERR_INVALID_ARG", 2: "ESS_ERR_INFEASIBLE_START",
                 3: "ESS_ERR_HIP", 4: "ESS_ERR_OOM", 5: "ESS_ERR_UNSUPPORTED"}
@@ -46,6 +48,8 @@ _LIB = None
 _P = ctypes.c_void_p
 _SIGS = {
     "ess_init": ([ctypes.POINTER(EssProblem), _P, ctypes.POINTER(_P)], ctypes.c_int),
+    "ess_init_batched": ([ctypes.POINTER(EssProblem), ctypes.c_int32, _P, ctypes.POINTER(_P)],
+                         ctypes.c_int),
     "ess_step": ([_P, _P], ctypes.c_int),
     "ess_run": ([_P, ctypes.c_int64, ctypes.c_int64, _P, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "ess_get_state": ([_P, _P, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
@@ -53,6 +57,9 @@ _SIGS = {
     "ess_rejections": ([_P, _P], ctypes.c_int),
     "ess_transition_explicit": ([_P] * 10, ctypes.c_int),
     "ess_draw": ([_P, ctypes.c_uint64, _P, _P], ctypes.c_int),
+    "ess_profile": ([_P, ctypes.c_int], ctypes.c_int),
+    "ess_profile_read": ([_P, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                          ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "ess_destroy": ([_P], None),
     "ess_last_error": ([], ctypes.c_char_p),
 }
@@ -96,6 +103,14 @@ def ess_init(problem, stream=None):
     return ctx
 
 
+def ess_init_batched(problems, stream=None):
+    """problems: a sequence of EssProblem."""
+    arr = (EssProblem * len(problems))(*problems)
+    ctx = ctypes.c_void_p()
+    _check(lib().ess_init_batched(arr, len(problems), _stream_handle(stream), ctypes.byref(ctx)))
+    return ctx
+
+
 def ess_step(ctx, x_out=None):
     _check(lib().ess_step(ctx, _ptr(x_out)))
 
@@ -134,6 +149,24 @@ def ess_draw(ctx, step, nu=None, u=None):
     _check(lib().ess_draw(ctx, int(step), _ptr(nu), _ptr(u)))
 
 
+ESS_KERNEL_PROJECT = 0
+ESS_KERNEL_SAMPLE = 1
+ESS_KERNEL_OTHER = 2
+ESS_KERNEL_BATCHED = 3
+
+
+def ess_profile(ctx, enable):
+    _check(lib().ess_profile(ctx, int(bool(enable))))
+
+
+def ess_profile_read(ctx, kind):
+    """(total milliseconds, launch count) of one kernel kind since the last read."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    _check(lib().ess_profile_read(ctx, int(kind), ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
 def ess_destroy(ctx):
     if ctx:
         lib().ess_destroy(ctx)
@@ -149,7 +182,7 @@ class Sampler:
     are copied to the device in the working precision before ess_init."""
 
     def __init__(self, A, b, x0, n_chains, seed=0, precision=32, trim_eps=None,
-                 device="cuda", stream=None):
+                 device="cuda", stream=None, full_sort=False):
         import torch
         self.torch = torch
         self.dtype = torch.float32 if precision == 32 else torch.float64
@@ -164,7 +197,9 @@ class Sampler:
             self.device, torch.float64).contiguous()
         x0 = torch.as_tensor(np.asarray(x0) if not torch.is_tensor(x0) else x0).to(
             self.device, self.dtype).contiguous()
-        flags = ESS_X0_BROADCAST if x0.dim() == 1 else 0
+        flags = (ESS_X0_BROADCAST if x0.dim() == 1 else 0) | (ESS_SORT_FULL if full_sort else 0)
+        if self.b.dim() == 2:       # one right-hand side per chain
+            flags |= ESS_PER_CHAIN_B
         if trim_eps is None:
             trim_eps = 1e-6 if precision == 32 else 0.0
         self.trim_eps = float(trim_eps)
@@ -218,6 +253,74 @@ class Sampler:
         ess_transition_explicit(self.ctx, x, nu, u, out["x_new"], out["intervals"],
                                 out["n_intervals"], out["theta"], out["rejected"], out["pq"])
         return out
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            ess_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchedSampler:
+    """Owns one batched ess_ctx over several problems (float32).
+
+    problems: sequence of dicts with keys A, b, x0, n_chains and optionally
+    seed and trim_eps.  State and trace tensors hold the problems one after
+    another, each as n_chains x d; `split` cuts them per problem."""
+
+    def __init__(self, problems, device="cuda", stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.keep = []
+        probs = []
+        self.shapes = []
+        for pr in problems:
+            A = torch.as_tensor(np.asarray(pr["A"])).to(self.device, torch.float32).contiguous()
+            b = torch.as_tensor(np.asarray(pr["b"])).to(self.device, torch.float64).contiguous()
+            x0 = torch.as_tensor(np.asarray(pr["x0"])).to(self.device, torch.float32).contiguous()
+            m, d = A.shape
+            C = int(pr["n_chains"])
+            flags = ESS_X0_BROADCAST if x0.dim() == 1 else 0
+            probs.append(EssProblem(d, m, C, 32, A.data_ptr(), b.data_ptr(), x0.data_ptr(),
+                                    int(pr.get("seed", 0)), float(pr.get("trim_eps", 1e-6)), flags))
+            self.keep += [A, b, x0]
+            self.shapes.append((C, d))
+        self.n_state = sum(C * d for C, d in self.shapes)
+        self.n_chains = sum(C for C, _ in self.shapes)
+        self.ctx = ess_init_batched(probs, stream)
+
+    def split(self, flat):
+        """(..., sum C d) -> list of (..., C, d) views, one per problem."""
+        out, off = [], 0
+        for C, d in self.shapes:
+            out.append(flat[..., off:off + C * d].reshape(*flat.shape[:-1], C, d))
+            off += C * d
+        return out
+
+    def run(self, n_steps, thin=1, keep_trace=True, count_rejections=True):
+        t = self.torch
+        tr = (t.empty(n_steps // thin, self.n_state, device=self.device, dtype=t.float32)
+              if keep_trace and n_steps // thin else None)
+        nrej = ess_run(self.ctx, n_steps, thin, tr, count_rejections)
+        return tr, nrej
+
+    def state(self):
+        x = self.torch.empty(self.n_state, device=self.device, dtype=self.torch.float32)
+        step = ess_get_state(self.ctx, x)
+        return x, step
+
+    def set_state(self, x, step):
+        x = self.torch.as_tensor(x).to(self.device, self.torch.float32).contiguous()
+        ess_set_state(self.ctx, x, step)
+
+    def rejections(self):
+        return ess_rejections(self.ctx, self.n_chains)
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -10,8 +10,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <memory>
+#include <numeric>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -20,6 +23,7 @@
 #include "gemm.hpp"
 #include "philox.hpp"
 #include "sample.hpp"
+#include "batched.hpp"
 
 using namespace ess;
 
@@ -62,12 +66,21 @@ __global__ void broadcast_rows(const T* __restrict__ src, T* __restrict__ dst, i
 
 }  // namespace
 
+constexpr int kMaxGroups = 4;
+
+// A contiguous block of chains with its own stream during ess_run: chains
+// [c0, c0 + n) valid, padded to Cg (a multiple of every projection tile width).
+struct Group {
+    int c0, n, Cg;
+};
+
 struct ess_ctx {
     int d = 0, m = 0, C = 0, prec = 32, esz = 4;
     int dp = 0, mp = 0, Cp = 0;
     uint64_t seed = 0;
     double eps = 0.0;
     uint32_t flags = 0;
+    int bstride = 0;   // 0: one b for every chain; m: a b per chain (ESS_PER_CHAIN_B)
     hipStream_t st = nullptr;
     void* A = nullptr;
     double* b = nullptr;
@@ -79,10 +92,50 @@ struct ess_ctx {
     int* sel = nullptr;
     int* flag = nullptr;
     long long* rej = nullptr;
+    int* fb_list = nullptr;    // chains handed to the full-sort path
+    int* fb_count = nullptr;   // [2 per group]: list lengths by step parity
     uint64_t step = 0;
     int bm = 128, bn = 128, group_m = 4;
     int nmax = 512;
+    // chain groups: each runs its own sample -> project pipeline on its own
+    // stream, so one group's matrix-core work overlaps another's vector work
+    int G = 1;
+    hipStream_t gs[kMaxGroups] = {};
+    hipEvent_t fork = nullptr, join[kMaxGroups] = {};
     std::vector<void*> allocs;
+    // kernel timing (ess_profile)
+    bool profiling = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_open;
+    double prof_ms[4] = {0, 0, 0, 0};
+    long long prof_n[4] = {0, 0, 0, 0};
+    // many problems advanced together (ess_init_batched)
+    struct Batch {
+        int n = 0, NT = 0, NC = 0, rpt = 1, nb = 256, nmax = 512, grid = 256;
+        long long state_elems = 0;   // sum of C d (caller layout)
+        int chains_padded = 0;
+        std::vector<ProbDesc> h;
+        ProbDesc* descs = nullptr;
+        int4* tiles = nullptr;
+        int2* chains = nullptr;
+        float* A = nullptr;
+        float* X = nullptr;
+        float* Xprop = nullptr;
+        float* N = nullptr;
+        float* P = nullptr;
+        float* Q = nullptr;
+        double* b = nullptr;
+        int* counters = nullptr;   // queue[2], fb_count[2], error[1], done[2 n]
+        int* fb_list = nullptr;
+        int2* caller_chains = nullptr;   // chains in the caller's problem order
+    };
+    std::unique_ptr<Batch> batch;
+
+    Group whole() const { return Group{0, C, Cp}; }
+    Group group(int g) const {
+        const int Cg = Cp / G, c0 = g * Cg;
+        return Group{c0, std::max(0, std::min(C - c0, Cg)), Cg};
+    }
 };
 
 namespace {
@@ -94,13 +147,57 @@ ess_status dalloc(ess_ctx* c, void** p, size_t bytes) {
     return ESS_OK;
 }
 
-ProjOut proj_out(const ess_ctx* c, int p_direct, int strict) {
+hipEvent_t take_event(ess_ctx* c) {
+    if (!c->ev_pool.empty()) {
+        hipEvent_t e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Brackets the launches issued by `fn` on stream st with an event pair when
+// profiling.
+template <typename F>
+ess_status timed(ess_ctx* c, int kind, hipStream_t st, F&& fn) {
+    if (!c->profiling) return fn();
+    hipEvent_t a = take_event(c), b = take_event(c);
+    if (!a || !b) return fail(ESS_ERR_HIP, "hipEventCreate failed");
+    HIP_TRY(hipEventRecord(a, st));
+    ess_status s = fn();
+    HIP_TRY(hipEventRecord(b, st));
+    c->ev_open.push_back({kind, {a, b}});
+    return s;
+}
+
+ess_status drain_events(ess_ctx* c) {
+    if (c->ev_open.empty()) return ESS_OK;
+    HIP_TRY(hipStreamSynchronize(c->st));
+    for (auto& e : c->ev_open) {
+        HIP_TRY(hipEventSynchronize(e.second.second));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e.second.first, e.second.second));
+        c->prof_ms[e.first] += ms;
+        c->prof_n[e.first] += 1;
+        c->ev_pool.push_back(e.second.first);
+        c->ev_pool.push_back(e.second.second);
+    }
+    c->ev_open.clear();
+    return ESS_OK;
+}
+
+ProjOut proj_out(const ess_ctx* c, const Group& g, int p_direct, int strict) {
     ProjOut o;
     o.m = c->m;
     o.C = c->C;
     o.Cp = c->Cp;
     o.mp = c->mp;
+    o.c0 = g.c0;
+    o.Cg = g.Cg;
     o.b = c->b;
+    o.bstride = c->bstride;
     o.P = c->P;
     o.Q = c->Q;
     o.sel = c->sel;
@@ -113,39 +210,43 @@ ProjOut proj_out(const ess_ctx* c, int p_direct, int strict) {
 enum Cols { COLS_X = 0, COLS_NU = 1, COLS_BOTH = 2 };
 
 template <int BM, int BN>
-void launch_f32(const ess_ctx* c, const void* B0, int cols, const ProjOut& o) {
-    const int tiles_m = c->mp / BM, half = c->Cp / BN;
+void launch_f32(const ess_ctx* c, const Group& g, hipStream_t st, const float* B0, int cols,
+                const ProjOut& o) {
+    const int tiles_m = c->mp / BM, half = g.Cg / BN;
     const int tn0 = (cols == COLS_NU) ? half : 0;
     const int tiles_n = (cols == COLS_BOTH) ? 2 * half : half;
-    hipLaunchKernelGGL((proj_gemm_f32<BM, BN>), dim3(tiles_m * tiles_n), dim3(256), 0, c->st,
-                       static_cast<const float*>(c->A), static_cast<const float*>(B0),
-                       static_cast<const float*>(c->N), c->dp, tiles_m, tiles_n, tn0,
+    const float* B1 = static_cast<const float*>(c->N) + static_cast<size_t>(g.c0) * c->dp;
+    hipLaunchKernelGGL((proj_gemm_f32<BM, BN>), dim3(tiles_m * tiles_n), dim3(256), 0, st,
+                       static_cast<const float*>(c->A), B0, B1, c->dp, tiles_m, tiles_n, tn0,
                        c->group_m, o);
 }
 
-// Projections of the columns selected by `cols`: B0 rows (x or x') and/or the
-// current nu rows.
-ess_status launch_proj(const ess_ctx* c, const void* B0, int cols, int p_direct, int strict) {
-    const ProjOut o = proj_out(c, p_direct, strict);
+// Projections of group g's columns selected by `cols`: rows of Y (x or x')
+// and/or the current nu rows.
+ess_status launch_proj(const ess_ctx* c, const Group& g, hipStream_t st, const void* Y, int cols,
+                       int p_direct, int strict) {
+    const ProjOut o = proj_out(c, g, p_direct, strict);
+    const size_t off = static_cast<size_t>(g.c0) * c->dp;
     if (c->prec == 32) {
-        if (c->bm == 128 && c->bn == 128) launch_f32<128, 128>(c, B0, cols, o);
-        else if (c->bm == 128 && c->bn == 64) launch_f32<128, 64>(c, B0, cols, o);
-        else if (c->bm == 64 && c->bn == 128) launch_f32<64, 128>(c, B0, cols, o);
-        else launch_f32<64, 64>(c, B0, cols, o);
+        const float* B0 = static_cast<const float*>(Y) + off;
+        if (c->bm == 128 && c->bn == 128) launch_f32<128, 128>(c, g, st, B0, cols, o);
+        else if (c->bm == 128 && c->bn == 64) launch_f32<128, 64>(c, g, st, B0, cols, o);
+        else if (c->bm == 64 && c->bn == 128) launch_f32<64, 128>(c, g, st, B0, cols, o);
+        else launch_f32<64, 64>(c, g, st, B0, cols, o);
     } else {
-        const int tiles_m = c->mp / 64, half = c->Cp / 64;
+        const int tiles_m = c->mp / 64, half = g.Cg / 64;
         const int tn0 = (cols == COLS_NU) ? half : 0;
         const int tiles_n = (cols == COLS_BOTH) ? 2 * half : half;
-        hipLaunchKernelGGL((proj_gemm_f64<64, 64>), dim3(tiles_m * tiles_n), dim3(256), 0, c->st,
-                           static_cast<const double*>(c->A), static_cast<const double*>(B0),
-                           static_cast<const double*>(c->N), c->dp, tiles_m, tiles_n, tn0,
+        hipLaunchKernelGGL((proj_gemm_f64<64, 64>), dim3(tiles_m * tiles_n), dim3(256), 0, st,
+                           static_cast<const double*>(c->A), static_cast<const double*>(Y) + off,
+                           static_cast<const double*>(c->N) + off, c->dp, tiles_m, tiles_n, tn0,
                            c->group_m, o);
     }
     HIP_TRY(hipGetLastError());
     return ESS_OK;
 }
 
-SampleArgs sample_args(const ess_ctx* c) {
+SampleArgs sample_args(const ess_ctx* c, const Group& g, int gi) {
     SampleArgs a;
     std::memset(&a, 0, sizeof(a));
     a.d = c->d;
@@ -154,8 +255,10 @@ SampleArgs sample_args(const ess_ctx* c) {
     a.Cp = c->Cp;
     a.dp = c->dp;
     a.mp = c->mp;
+    a.c0 = g.c0;
     a.problem = 0;
     a.b = c->b;
+    a.bstride = c->bstride;
     a.P = c->P;
     a.Q = c->Q;
     a.X = c->X;
@@ -166,41 +269,62 @@ SampleArgs sample_args(const ess_ctx* c) {
     a.rej = c->rej;
     a.eps = c->eps;
     a.seed = c->seed;
+    a.fb_list = c->fb_list + g.c0;
+    a.fb_count = c->fb_count + 2 * gi;
+    a.force_full = (c->flags & ESS_SORT_FULL) ? 1 : 0;
     return a;
 }
 
+// Bucket path over the group's chains, then the full-sort path over the
+// chains it handed over (usually none: the second launch then exits at once).
 template <typename T>
-void launch_sample_t(const ess_ctx* c, const SampleArgs& a) {
-    const dim3 g(c->C), b(256);
+void launch_sample_t(const ess_ctx* c, const Group& g, hipStream_t st, const SampleArgs& a) {
+    const dim3 grid(g.n), b(256);
+    const int rpt = (c->m + 255) / 256;
+    if (rpt <= 1) hipLaunchKernelGGL((sample_bucket_kernel<T, 1, 256>), grid, b, 0, st, a);
+    else if (rpt <= 2) hipLaunchKernelGGL((sample_bucket_kernel<T, 2, 2048>), grid, b, 0, st, a);
+    else if (rpt <= 4) hipLaunchKernelGGL((sample_bucket_kernel<T, 4, 2048>), grid, b, 0, st, a);
+    else if (rpt <= 8) hipLaunchKernelGGL((sample_bucket_kernel<T, 8, 2048>), grid, b, 0, st, a);
+    else hipLaunchKernelGGL((sample_bucket_kernel<T, 16, 2048>), grid, b, 0, st, a);
+    const dim3 fg(std::min(g.n, 768));
     switch (c->nmax) {
-        case 512: hipLaunchKernelGGL((sample_kernel<T, 512>), g, b, 0, c->st, a); break;
-        case 1024: hipLaunchKernelGGL((sample_kernel<T, 1024>), g, b, 0, c->st, a); break;
-        case 2048: hipLaunchKernelGGL((sample_kernel<T, 2048>), g, b, 0, c->st, a); break;
-        default: hipLaunchKernelGGL((sample_kernel<T, 4096>), g, b, 0, c->st, a); break;
+        case 512: hipLaunchKernelGGL((fallback_kernel<T, 512>), fg, b, 0, st, a); break;
+        case 1024: hipLaunchKernelGGL((fallback_kernel<T, 1024>), fg, b, 0, st, a); break;
+        case 2048: hipLaunchKernelGGL((fallback_kernel<T, 2048>), fg, b, 0, st, a); break;
+        default: hipLaunchKernelGGL((fallback_kernel<T, 4096>), fg, b, 0, st, a); break;
     }
 }
 
-ess_status launch_sample(const ess_ctx* c, const SampleArgs& a) {
-    if (c->prec == 32) launch_sample_t<float>(c, a);
-    else launch_sample_t<double>(c, a);
+ess_status launch_sample(const ess_ctx* c, const Group& g, hipStream_t st, const SampleArgs& a) {
+    if (c->prec == 32) launch_sample_t<float>(c, g, st, a);
+    else launch_sample_t<double>(c, g, st, a);
     HIP_TRY(hipGetLastError());
     return ESS_OK;
 }
 
-ess_status launch_commit(const ess_ctx* c, const SampleArgs& a) {
-    if (c->prec == 32) hipLaunchKernelGGL((commit_kernel<float>), dim3(c->C), dim3(256), 0, c->st, a);
-    else hipLaunchKernelGGL((commit_kernel<double>), dim3(c->C), dim3(256), 0, c->st, a);
+ess_status clear_fallback_lists(const ess_ctx* c, hipStream_t st, int gi) {
+    hipLaunchKernelGGL(zero_ints, dim3(1), dim3(64), 0, st, c->fb_count + 2 * gi, 2);
     HIP_TRY(hipGetLastError());
     return ESS_OK;
 }
 
-ess_status launch_draw(const ess_ctx* c, uint64_t step, void* dst, long long ld, double* u) {
+ess_status launch_commit(const ess_ctx* c, const Group& g, hipStream_t st, const SampleArgs& a) {
+    if (c->prec == 32) hipLaunchKernelGGL((commit_kernel<float>), dim3(g.n), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((commit_kernel<double>), dim3(g.n), dim3(256), 0, st, a);
+    HIP_TRY(hipGetLastError());
+    return ESS_OK;
+}
+
+// nu of `step` for chains [c0, c0 + n) into dst rows (leading dimension ld),
+// and/or their theta uniforms.
+ess_status launch_draw(const ess_ctx* c, int c0, int n, hipStream_t st, uint64_t step, void* dst,
+                       long long ld, double* u) {
     if (c->prec == 32)
-        hipLaunchKernelGGL((draw_kernel<float>), dim3(c->C), dim3(256), 0, c->st, c->seed,
-                           static_cast<uint32_t>(step), 0u, c->d, static_cast<float*>(dst), ld, u);
+        hipLaunchKernelGGL((draw_kernel<float>), dim3(n), dim3(256), 0, st, c->seed,
+                           static_cast<uint32_t>(step), 0u, c->d, static_cast<float*>(dst), ld, u, c0);
     else
-        hipLaunchKernelGGL((draw_kernel<double>), dim3(c->C), dim3(256), 0, c->st, c->seed,
-                           static_cast<uint32_t>(step), 0u, c->d, static_cast<double*>(dst), ld, u);
+        hipLaunchKernelGGL((draw_kernel<double>), dim3(n), dim3(256), 0, st, c->seed,
+                           static_cast<uint32_t>(step), 0u, c->d, static_cast<double*>(dst), ld, u, c0);
     HIP_TRY(hipGetLastError());
     return ESS_OK;
 }
@@ -224,17 +348,18 @@ ess_status copy_rows_out(const ess_ctx* c, void* dst, const void* src) {
 // projection buffers and a strict feasibility check (a_i^T x < b_i).
 ess_status set_state_from_X(ess_ctx* c, const char* what) {
     HIP_TRY(hipMemsetAsync(c->flag, 0, sizeof(int) * c->Cp, c->st));
-    ESS_TRY(launch_proj(c, c->X, COLS_X, 1, 1));
+    ESS_TRY(launch_proj(c, c->whole(), c->st, c->X, COLS_X, 1, 1));
     std::vector<int> fl(c->C);
     HIP_TRY(hipMemcpyAsync(fl.data(), c->flag, sizeof(int) * c->C, hipMemcpyDeviceToHost, c->st));
     HIP_TRY(hipStreamSynchronize(c->st));
     for (int ch = 0; ch < c->C; ++ch) {
         if (!fl[ch]) continue;
-        std::vector<int> sel(1);
-        HIP_TRY(hipMemcpy(sel.data(), c->sel + ch, sizeof(int), hipMemcpyDeviceToHost));
+        int sel = 0;
+        HIP_TRY(hipMemcpy(&sel, c->sel + ch, sizeof(int), hipMemcpyDeviceToHost));
         std::vector<double> bh(c->m), ph(c->m);
-        HIP_TRY(hipMemcpy(bh.data(), c->b, sizeof(double) * c->m, hipMemcpyDeviceToHost));
-        const size_t off = (static_cast<size_t>(sel[0]) * c->Cp + ch) * c->mp;
+        HIP_TRY(hipMemcpy(bh.data(), c->b + static_cast<size_t>(ch) * c->bstride,
+                          sizeof(double) * c->m, hipMemcpyDeviceToHost));
+        const size_t off = (static_cast<size_t>(sel) * c->Cp + ch) * c->mp;
         if (c->prec == 32) {
             std::vector<float> pf(c->m);
             HIP_TRY(hipMemcpy(pf.data(), static_cast<float*>(c->P) + off, sizeof(float) * c->m,
@@ -261,12 +386,319 @@ ess_status check_ctx(const ess_ctx* c) {
 }
 
 ess_status sum_rejections(const ess_ctx* c, long long& total) {
-    std::vector<long long> r(c->C);
-    HIP_TRY(hipMemcpyAsync(r.data(), c->rej, sizeof(long long) * c->C, hipMemcpyDeviceToHost,
-                           c->st));
+    const int n = c->batch ? c->batch->chains_padded : c->C;
+    std::vector<long long> r(n);
+    HIP_TRY(hipMemcpyAsync(r.data(), c->rej, sizeof(long long) * n, hipMemcpyDeviceToHost, c->st));
     HIP_TRY(hipStreamSynchronize(c->st));
     total = 0;
     for (long long v : r) total += v;
+    return ESS_OK;
+}
+
+// Issues n_steps transitions of every group; groups run on their own streams
+// between a fork and a join event on the caller's stream.
+ess_status issue_run(ess_ctx* c, int64_t n_steps, int64_t thin, void* trace) {
+    const size_t trace_row = static_cast<size_t>(c->C) * c->d * c->esz;
+    const bool split = c->G > 1;
+    hipStream_t sts[kMaxGroups];
+    Group gr[kMaxGroups];
+    for (int g = 0; g < c->G; ++g) {
+        sts[g] = split ? c->gs[g] : c->st;
+        gr[g] = split ? c->group(g) : c->whole();
+    }
+    if (split) {
+        HIP_TRY(hipEventRecord(c->fork, c->st));
+        for (int g = 0; g < c->G; ++g) HIP_TRY(hipStreamWaitEvent(sts[g], c->fork, 0));
+    }
+    SampleArgs a[kMaxGroups];
+    for (int g = 0; g < c->G; ++g) {
+        if (gr[g].n == 0) continue;
+        ESS_TRY(clear_fallback_lists(c, sts[g], g));
+        ESS_TRY(timed(c, ESS_KERNEL_OTHER, sts[g], [&] {
+            return launch_draw(c, gr[g].c0, gr[g].n, sts[g], c->step, c->N, c->dp, nullptr);
+        }));
+        ESS_TRY(timed(c, ESS_KERNEL_OTHER, sts[g],
+                      [&] { return launch_proj(c, gr[g], sts[g], c->Xprop, COLS_NU, 0, 0); }));
+        a[g] = sample_args(c, gr[g], g);
+    }
+    for (int64_t s = 0; s < n_steps; ++s) {
+        const bool both = s + 1 < n_steps;
+        for (int g = 0; g < c->G; ++g) {
+            if (gr[g].n == 0) continue;
+            a[g].step = static_cast<uint32_t>(c->step + s);
+            a[g].has_pending = s > 0;
+            a[g].gen_next = both;
+            a[g].trace = (trace && s > 0 && s % thin == 0)
+                             ? static_cast<char*>(trace) + (s / thin - 1) * trace_row
+                             : nullptr;
+            ESS_TRY(timed(c, ESS_KERNEL_SAMPLE, sts[g],
+                          [&] { return launch_sample(c, gr[g], sts[g], a[g]); }));
+            ESS_TRY(timed(c, both ? ESS_KERNEL_PROJECT : ESS_KERNEL_OTHER, sts[g], [&] {
+                return launch_proj(c, gr[g], sts[g], c->Xprop, both ? COLS_BOTH : COLS_X, 0, 0);
+            }));
+        }
+    }
+    for (int g = 0; g < c->G; ++g) {
+        if (gr[g].n == 0) continue;
+        SampleArgs f = sample_args(c, gr[g], g);
+        f.trace = (trace && n_steps % thin == 0)
+                      ? static_cast<char*>(trace) + (n_steps / thin - 1) * trace_row
+                      : nullptr;
+        ESS_TRY(timed(c, ESS_KERNEL_OTHER, sts[g], [&] { return launch_commit(c, gr[g], sts[g], f); }));
+    }
+    if (split) {
+        for (int g = 0; g < c->G; ++g) {
+            HIP_TRY(hipEventRecord(c->join[g], sts[g]));
+            HIP_TRY(hipStreamWaitEvent(c->st, c->join[g], 0));
+        }
+    }
+    return ESS_OK;
+}
+
+// ---------------------------------------------------------------- batched
+BatchArgs batch_args(const ess_ctx* c) {
+    const ess_ctx::Batch& B = *c->batch;
+    BatchArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.n_probs = B.n;
+    a.NT = B.NT;
+    a.NC = B.NC;
+    a.descs = B.descs;
+    a.tiles = B.tiles;
+    a.chains = B.chains;
+    a.A = B.A;
+    a.b = B.b;
+    a.X = B.X;
+    a.Xprop = B.Xprop;
+    a.N = B.N;
+    a.P = B.P;
+    a.Q = B.Q;
+    a.sel = c->sel;
+    a.flag = c->flag;
+    a.rej = c->rej;
+    a.queue = B.counters;
+    a.fb_count = B.counters + 2;
+    a.error = B.counters + 4;
+    a.done = B.counters + 5;
+    a.fb_list = B.fb_list;
+    return a;
+}
+
+template <int RPT, int NB>
+void launch_step_t(const ess_ctx* c, const BatchArgs& a) {
+    hipLaunchKernelGGL((batched_step_kernel<RPT, NB>), dim3(c->batch->grid), dim3(256), 0, c->st, a);
+}
+
+ess_status launch_batched_step(const ess_ctx* c, const BatchArgs& a) {
+    const ess_ctx::Batch& B = *c->batch;
+    if (B.nb == 256) launch_step_t<1, 256>(c, a);
+    else if (B.rpt <= 2) launch_step_t<2, 2048>(c, a);
+    else if (B.rpt <= 4) launch_step_t<4, 2048>(c, a);
+    else if (B.rpt <= 8) launch_step_t<8, 2048>(c, a);
+    else launch_step_t<16, 2048>(c, a);
+    HIP_TRY(hipGetLastError());
+    return ESS_OK;
+}
+
+ess_status launch_batched_fallback(const ess_ctx* c, const BatchArgs& a) {
+    const dim3 g(std::min(c->batch->NC, 768)), b(256);
+    switch (c->batch->nmax) {
+        case 512: hipLaunchKernelGGL((batched_fallback_kernel<512>), g, b, 0, c->st, a); break;
+        case 1024: hipLaunchKernelGGL((batched_fallback_kernel<1024>), g, b, 0, c->st, a); break;
+        case 2048: hipLaunchKernelGGL((batched_fallback_kernel<2048>), g, b, 0, c->st, a); break;
+        default: hipLaunchKernelGGL((batched_fallback_kernel<4096>), g, b, 0, c->st, a); break;
+    }
+    HIP_TRY(hipGetLastError());
+    return ESS_OK;
+}
+
+// A x for the rows in X (p_direct) with the strict start check, then the flags.
+ess_status batched_set_state_from_X(ess_ctx* c, const char* what) {
+    ess_ctx::Batch& B = *c->batch;
+    HIP_TRY(hipMemsetAsync(c->flag, 0, sizeof(int) * B.chains_padded, c->st));
+    BatchArgs a = batch_args(c);
+    a.Xprop = B.X;    // tiles read the committed rows
+    a.cols = 0;
+    a.p_direct = 1;
+    a.strict = 1;
+    hipLaunchKernelGGL(batched_proj_kernel, dim3(B.NT), dim3(256), 0, c->st, a);
+    HIP_TRY(hipGetLastError());
+    std::vector<int> fl(B.chains_padded);
+    HIP_TRY(hipMemcpyAsync(fl.data(), c->flag, sizeof(int) * B.chains_padded, hipMemcpyDeviceToHost,
+                           c->st));
+    HIP_TRY(hipStreamSynchronize(c->st));
+    for (int p = 0; p < B.n; ++p)
+        for (int ch = 0; ch < B.h[p].C; ++ch)
+            if (fl[B.h[p].chain_off + ch]) {
+                HIP_TRY(hipMemsetAsync(c->flag, 0, sizeof(int) * B.chains_padded, c->st));
+                return fail(ESS_ERR_INFEASIBLE_START,
+                            "%s: problem %d chain %d is not strictly feasible", what, p, ch);
+            }
+    return ESS_OK;
+}
+
+ess_status batched_run(ess_ctx* c, int64_t n_steps, int64_t thin, void* trace) {
+    ess_ctx::Batch& B = *c->batch;
+    const int ncnt = 5 + 2 * B.n;
+    hipLaunchKernelGGL(zero_ints_n, dim3(std::min((ncnt + 255) / 256, 64)), dim3(256), 0, c->st,
+                       B.counters, ncnt);
+    HIP_TRY(hipGetLastError());
+    BatchArgs a = batch_args(c);
+    a.step = static_cast<uint32_t>(c->step);
+    ESS_TRY(timed(c, ESS_KERNEL_OTHER, c->st, [&] {
+        hipLaunchKernelGGL(batched_draw_kernel, dim3(B.NC), dim3(256), 0, c->st, a);
+        HIP_TRY(hipGetLastError());
+        return ESS_OK;
+    }));
+    const size_t row = static_cast<size_t>(B.state_elems);
+    for (int64_t s = 0; s <= n_steps; ++s) {
+        a.step = static_cast<uint32_t>(c->step + s);
+        a.has_pending = s > 0;
+        a.do_sample = s < n_steps;
+        a.gen_next = s + 1 < n_steps;
+        a.cols = (s == 0) ? 1 : (s == n_steps ? 0 : 2);
+        a.p_direct = 0;
+        a.strict = 0;
+        a.trace = (trace && s > 0 && s % thin == 0)
+                      ? static_cast<float*>(trace) + (s / thin - 1) * row
+                      : nullptr;
+        ESS_TRY(timed(c, ESS_KERNEL_BATCHED, c->st, [&] { return launch_batched_step(c, a); }));
+        if (a.do_sample)
+            ESS_TRY(timed(c, ESS_KERNEL_OTHER, c->st, [&] { return launch_batched_fallback(c, a); }));
+    }
+    int err = 0;
+    HIP_TRY(hipMemcpyAsync(&err, B.counters + 4, sizeof(int), hipMemcpyDeviceToHost, c->st));
+    HIP_TRY(hipStreamSynchronize(c->st));
+    if (err) return fail(ESS_ERR_HIP, "batched step: a chain waited past its spin limit");
+    return ESS_OK;
+}
+
+ess_status batched_init(ess_ctx* c, const ess_problem* pr, int n) {
+    c->batch.reset(new ess_ctx::Batch());
+    ess_ctx::Batch& B = *c->batch;
+    B.n = n;
+    B.h.resize(n);
+    long long a_off = 0, b_off = 0, x_off = 0, p_off = 0, q_off = 0, t_off = 0;
+    int chain_off = 0, max_m = 1;
+    for (int p = 0; p < n; ++p) {
+        ProbDesc& d = B.h[p];
+        d.d = pr[p].d;
+        d.m = pr[p].m;
+        d.C = pr[p].n_chains;
+        d.dp = round_up(d.d, 32);
+        d.mp = round_up(d.m, kBatchBM);
+        d.Cp = round_up(d.C, kBatchBN);
+        d.ntiles = (d.mp / kBatchBM) * (2 * d.Cp / kBatchBN);
+        d.chain_off = chain_off;
+        d.a_off = a_off;
+        d.b_off = b_off;
+        d.x_off = x_off;
+        d.p_off = p_off;
+        d.q_off = q_off;
+        d.t_off = t_off;
+        d.eps = pr[p].trim_eps;
+        d.seed = pr[p].seed;
+        a_off += static_cast<long long>(d.mp) * d.dp;
+        b_off += d.m;
+        x_off += static_cast<long long>(d.Cp) * d.dp;
+        p_off += 2ll * d.Cp * d.mp;
+        q_off += static_cast<long long>(d.Cp) * d.mp;
+        t_off += static_cast<long long>(d.C) * d.d;
+        chain_off += d.Cp;
+        max_m = std::max(max_m, d.m);
+    }
+    B.state_elems = t_off;
+    B.chains_padded = chain_off;
+    B.rpt = (max_m + 255) / 256;
+    B.nb = max_m <= 256 ? 256 : 2048;
+    B.nmax = 512;
+    while (B.nmax < max_m) B.nmax <<= 1;
+    // queue order: problems with the most projection work first, so their
+    // long tiles start early; chains follow in the same problem order
+    std::vector<int> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return static_cast<long long>(B.h[x].mp) * B.h[x].dp * B.h[x].Cp >
+               static_cast<long long>(B.h[y].mp) * B.h[y].dp * B.h[y].Cp;
+    });
+    std::vector<int4> tiles;
+    std::vector<int2> chains;
+    for (int p : order) {
+        const ProbDesc& d = B.h[p];
+        for (int tm = 0; tm < d.mp / kBatchBM; ++tm)
+            for (int tn = 0; tn < 2 * d.Cp / kBatchBN; ++tn) tiles.push_back(make_int4(p, tm, tn, 0));
+    }
+    for (int p : order)
+        for (int ch = 0; ch < B.h[p].C; ++ch) chains.push_back(make_int2(p, ch));
+    // the caller's chain order (problem by problem) for the state/trace copies
+    std::vector<int2> caller_chains;
+    for (int p = 0; p < n; ++p)
+        for (int ch = 0; ch < B.h[p].C; ++ch) caller_chains.push_back(make_int2(p, ch));
+    B.NT = static_cast<int>(tiles.size());
+    B.NC = static_cast<int>(chains.size());
+
+    ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.descs), sizeof(ProbDesc) * n));
+    ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.tiles), sizeof(int4) * B.NT));
+    ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.chains), sizeof(int2) * B.NC));
+    ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.A), sizeof(float) * a_off));
+    ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.b), sizeof(double) * b_off));
+    ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.X), sizeof(float) * x_off));
+    ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.Xprop), sizeof(float) * x_off));
+    ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.N), sizeof(float) * x_off));
+    ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.P), sizeof(float) * p_off));
+    ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.Q), sizeof(float) * q_off));
+    ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.counters), sizeof(int) * (5 + 2 * n)));
+    ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.fb_list), sizeof(int) * B.NC));
+    ESS_TRY(dalloc(c, reinterpret_cast<void**>(&c->sel), sizeof(int) * chain_off));
+    ESS_TRY(dalloc(c, reinterpret_cast<void**>(&c->flag), sizeof(int) * chain_off));
+    ESS_TRY(dalloc(c, reinterpret_cast<void**>(&c->rej), sizeof(long long) * chain_off));
+    HIP_TRY(hipMemcpyAsync(B.descs, B.h.data(), sizeof(ProbDesc) * n, hipMemcpyHostToDevice, c->st));
+    HIP_TRY(hipMemcpyAsync(B.tiles, tiles.data(), sizeof(int4) * B.NT, hipMemcpyHostToDevice, c->st));
+    HIP_TRY(hipMemcpyAsync(B.chains, caller_chains.data(), sizeof(int2) * B.NC,
+                           hipMemcpyHostToDevice, c->st));
+    for (int p = 0; p < n; ++p) {
+        const ProbDesc& d = B.h[p];
+        HIP_TRY(hipMemcpy2DAsync(B.A + d.a_off, sizeof(float) * d.dp, pr[p].A, sizeof(float) * d.d,
+                                 sizeof(float) * d.d, d.m, hipMemcpyDefault, c->st));
+        HIP_TRY(hipMemcpyAsync(B.b + d.b_off, pr[p].b, sizeof(double) * d.m, hipMemcpyDefault, c->st));
+        if (pr[p].flags & ESS_X0_BROADCAST) {
+            hipLaunchKernelGGL((broadcast_rows<float>), dim3(d.C), dim3(256), 0, c->st,
+                               static_cast<const float*>(pr[p].x0), B.X + d.x_off, d.d, d.dp);
+            HIP_TRY(hipGetLastError());
+        } else {
+            HIP_TRY(hipMemcpy2DAsync(B.X + d.x_off, sizeof(float) * d.dp, pr[p].x0,
+                                     sizeof(float) * d.d, sizeof(float) * d.d, d.C,
+                                     hipMemcpyDefault, c->st));
+        }
+    }
+    // the state check walks the caller order; the step kernel walks the queue order
+    ESS_TRY(batched_set_state_from_X(c, "ess_init_batched"));
+    HIP_TRY(hipMemcpyAsync(B.chains, chains.data(), sizeof(int2) * B.NC, hipMemcpyHostToDevice, c->st));
+    int dev = 0, cus = 0, occ = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const void* fn = nullptr;
+    if (B.nb == 256) fn = reinterpret_cast<const void*>(&batched_step_kernel<1, 256>);
+    else if (B.rpt <= 2) fn = reinterpret_cast<const void*>(&batched_step_kernel<2, 2048>);
+    else if (B.rpt <= 4) fn = reinterpret_cast<const void*>(&batched_step_kernel<4, 2048>);
+    else if (B.rpt <= 8) fn = reinterpret_cast<const void*>(&batched_step_kernel<8, 2048>);
+    else fn = reinterpret_cast<const void*>(&batched_step_kernel<16, 2048>);
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, 256, 0));
+    B.grid = std::max(1, cus * std::max(1, occ));
+    // keep the caller-order table for state copies
+    B.caller_chains = nullptr;
+    ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.caller_chains), sizeof(int2) * B.NC));
+    HIP_TRY(hipMemcpyAsync(B.caller_chains, caller_chains.data(), sizeof(int2) * B.NC,
+                           hipMemcpyHostToDevice, c->st));
+    return ESS_OK;
+}
+
+ess_status batched_copy_state(const ess_ctx* c, const float* src, float* dst, int to_library) {
+    BatchArgs a = batch_args(c);
+    a.chains = c->batch->caller_chains;
+    hipLaunchKernelGGL(batched_copy_rows, dim3(c->batch->NC), dim3(256), 0, c->st, a, src, dst,
+                       to_library);
+    HIP_TRY(hipGetLastError());
     return ESS_OK;
 }
 
@@ -301,9 +733,16 @@ ess_status ess_init(const ess_problem* pr, void* stream, ess_ctx** out) {
     c->seed = pr->seed;
     c->eps = pr->trim_eps;
     c->flags = pr->flags;
+    c->bstride = (pr->flags & ESS_PER_CHAIN_B) ? pr->m : 0;
     c->st = static_cast<hipStream_t>(stream);
+    // two chain groups when there are enough chains to fill the GPU twice over
+    c->G = (c->prec == 32 && c->C >= 512) ? 2 : 1;
+    if (const char* e = std::getenv("ESS_CHAIN_GROUPS")) {
+        const int g = std::atoi(e);
+        if (g >= 1 && g <= kMaxGroups) c->G = g;
+    }
     c->mp = round_up(c->m, 128);
-    c->Cp = round_up(c->C, 128);
+    c->Cp = round_up(c->C, 128 * c->G);
     c->dp = round_up(c->d, 32);
     if (c->prec == 32) {
         c->bm = c->m > 1024 ? 128 : 64;
@@ -323,21 +762,36 @@ ess_status ess_init(const ess_problem* pr, void* stream, ess_ctx** out) {
     const size_t rows = static_cast<size_t>(c->Cp) * c->dp * c->esz;
     ess_status s;
     if ((s = dalloc(c, &c->A, static_cast<size_t>(c->mp) * c->dp * c->esz)) != ESS_OK ||
-        (s = dalloc(c, reinterpret_cast<void**>(&c->b), sizeof(double) * c->m)) != ESS_OK ||
+        (s = dalloc(c, reinterpret_cast<void**>(&c->b),
+                    sizeof(double) * c->m * (c->bstride ? c->C : 1))) != ESS_OK ||
         (s = dalloc(c, &c->X, rows)) != ESS_OK || (s = dalloc(c, &c->Xprop, rows)) != ESS_OK ||
         (s = dalloc(c, &c->N, rows)) != ESS_OK ||
         (s = dalloc(c, &c->P, 2 * static_cast<size_t>(c->Cp) * c->mp * c->esz)) != ESS_OK ||
         (s = dalloc(c, &c->Q, static_cast<size_t>(c->Cp) * c->mp * c->esz)) != ESS_OK ||
         (s = dalloc(c, reinterpret_cast<void**>(&c->sel), sizeof(int) * c->Cp)) != ESS_OK ||
         (s = dalloc(c, reinterpret_cast<void**>(&c->flag), sizeof(int) * c->Cp)) != ESS_OK ||
-        (s = dalloc(c, reinterpret_cast<void**>(&c->rej), sizeof(long long) * c->Cp)) != ESS_OK)
+        (s = dalloc(c, reinterpret_cast<void**>(&c->rej), sizeof(long long) * c->Cp)) != ESS_OK ||
+        (s = dalloc(c, reinterpret_cast<void**>(&c->fb_list), sizeof(int) * c->Cp)) != ESS_OK ||
+        (s = dalloc(c, reinterpret_cast<void**>(&c->fb_count), sizeof(int) * 2 * kMaxGroups)) != ESS_OK)
         return bail(s);
+    if (c->G > 1) {
+        hipError_t ee = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
+        for (int g = 0; g < c->G && ee == hipSuccess; ++g) {
+            ee = hipStreamCreateWithFlags(&c->gs[g], hipStreamNonBlocking);
+            if (ee == hipSuccess) ee = hipEventCreateWithFlags(&c->join[g], hipEventDisableTiming);
+        }
+        if (ee != hipSuccess) {
+            fail(ESS_ERR_HIP, "creating group streams: %s", hipGetErrorString(ee));
+            return bail(ESS_ERR_HIP);
+        }
+    }
 
     hipError_t e = hipMemcpy2DAsync(c->A, static_cast<size_t>(c->dp) * c->esz, pr->A,
                                     static_cast<size_t>(c->d) * c->esz,
                                     static_cast<size_t>(c->d) * c->esz, c->m, hipMemcpyDefault, c->st);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(c->b, pr->b, sizeof(double) * c->m, hipMemcpyDefault, c->st);
+        e = hipMemcpyAsync(c->b, pr->b, sizeof(double) * c->m * (c->bstride ? c->C : 1),
+                           hipMemcpyDefault, c->st);
     if (e == hipSuccess) {
         if (pr->flags & ESS_X0_BROADCAST) {
             if (c->prec == 32)
@@ -363,10 +817,45 @@ ess_status ess_init(const ess_problem* pr, void* stream, ess_ctx** out) {
     return ESS_OK;
 }
 
+ess_status ess_profile(ess_ctx* c, int enable) {
+    g_err.clear();
+    ESS_TRY(check_ctx(c));
+    ESS_TRY(drain_events(c));
+    c->profiling = enable != 0;
+    for (int k = 0; k < 4; ++k) {
+        c->prof_ms[k] = 0.0;
+        c->prof_n[k] = 0;
+    }
+    return ESS_OK;
+}
+
+ess_status ess_profile_read(ess_ctx* c, int kind, double* total_ms, int64_t* count) {
+    g_err.clear();
+    ESS_TRY(check_ctx(c));
+    if (kind < 0 || kind > 3) return fail(ESS_ERR_INVALID_ARG, "unknown kernel kind %d", kind);
+    ESS_TRY(drain_events(c));
+    if (total_ms) *total_ms = c->prof_ms[kind];
+    if (count) *count = c->prof_n[kind];
+    c->prof_ms[kind] = 0.0;
+    c->prof_n[kind] = 0;
+    return ESS_OK;
+}
+
 void ess_destroy(ess_ctx* c) {
     if (!c) return;
     if (c->st) (void)hipStreamSynchronize(c->st);
     else (void)hipDeviceSynchronize();
+    for (auto& e : c->ev_open) {
+        c->ev_pool.push_back(e.second.first);
+        c->ev_pool.push_back(e.second.second);
+    }
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    for (int g = 0; g < kMaxGroups; ++g) {
+        if (c->gs[g]) (void)hipStreamSynchronize(c->gs[g]);
+        if (c->gs[g]) (void)hipStreamDestroy(c->gs[g]);
+        if (c->join[g]) (void)hipEventDestroy(c->join[g]);
+    }
+    if (c->fork) (void)hipEventDestroy(c->fork);
     for (void* p : c->allocs) (void)hipFree(p);
     delete c;
 }
@@ -380,25 +869,8 @@ ess_status ess_run(ess_ctx* c, int64_t n_steps, int64_t thin, void* trace, int64
     long long before = 0;
     if (n_rejected) ESS_TRY(sum_rejections(c, before));
     if (n_steps > 0) {
-        const size_t trace_row = static_cast<size_t>(c->C) * c->d * c->esz;
-        ESS_TRY(launch_draw(c, c->step, c->N, c->dp, nullptr));
-        ESS_TRY(launch_proj(c, c->Xprop, COLS_NU, 0, 0));
-        SampleArgs a = sample_args(c);
-        for (int64_t s = 0; s < n_steps; ++s) {
-            a.step = static_cast<uint32_t>(c->step + s);
-            a.has_pending = s > 0;
-            a.gen_next = s + 1 < n_steps;
-            a.trace = (trace && s > 0 && s % thin == 0)
-                          ? static_cast<char*>(trace) + (s / thin - 1) * trace_row
-                          : nullptr;
-            ESS_TRY(launch_sample(c, a));
-            ESS_TRY(launch_proj(c, c->Xprop, s + 1 < n_steps ? COLS_BOTH : COLS_X, 0, 0));
-        }
-        SampleArgs f = sample_args(c);
-        f.trace = (trace && n_steps % thin == 0)
-                      ? static_cast<char*>(trace) + (n_steps / thin - 1) * trace_row
-                      : nullptr;
-        ESS_TRY(launch_commit(c, f));
+        if (c->batch) ESS_TRY(batched_run(c, n_steps, thin, trace));
+        else ESS_TRY(issue_run(c, n_steps, thin, trace));
         c->step += static_cast<uint64_t>(n_steps);
     }
     if (n_rejected) {
@@ -411,14 +883,17 @@ ess_status ess_run(ess_ctx* c, int64_t n_steps, int64_t thin, void* trace, int64
 
 ess_status ess_step(ess_ctx* c, void* x_out) {
     ESS_TRY(ess_run(c, 1, 1, nullptr, nullptr));
-    if (x_out) ESS_TRY(copy_rows_out(c, x_out, c->X));
+    if (x_out) ESS_TRY(ess_get_state(c, x_out, nullptr));
     return ESS_OK;
 }
 
 ess_status ess_get_state(ess_ctx* c, void* x_out, uint64_t* step_out) {
     g_err.clear();
     ESS_TRY(check_ctx(c));
-    if (x_out) ESS_TRY(copy_rows_out(c, x_out, c->X));
+    if (x_out) {
+        if (c->batch) ESS_TRY(batched_copy_state(c, c->batch->X, static_cast<float*>(x_out), 0));
+        else ESS_TRY(copy_rows_out(c, x_out, c->X));
+    }
     if (step_out) *step_out = c->step;
     return ESS_OK;
 }
@@ -428,8 +903,13 @@ ess_status ess_set_state(ess_ctx* c, const void* x_in, uint64_t step) {
     ESS_TRY(check_ctx(c));
     if (!x_in) return fail(ESS_ERR_INVALID_ARG, "null state");
     if (step >= (1ull << 32)) return fail(ESS_ERR_UNSUPPORTED, "the step counter is limited to 2^32");
-    ESS_TRY(copy_rows_in(c, c->X, x_in));
-    ESS_TRY(set_state_from_X(c, "ess_set_state"));
+    if (c->batch) {
+        ESS_TRY(batched_copy_state(c, static_cast<const float*>(x_in), c->batch->X, 1));
+        ESS_TRY(batched_set_state_from_X(c, "ess_set_state"));
+    } else {
+        ESS_TRY(copy_rows_in(c, c->X, x_in));
+        ESS_TRY(set_state_from_X(c, "ess_set_state"));
+    }
     c->step = step;
     return ESS_OK;
 }
@@ -438,8 +918,58 @@ ess_status ess_rejections(ess_ctx* c, int64_t* per_chain) {
     g_err.clear();
     ESS_TRY(check_ctx(c));
     if (!per_chain) return fail(ESS_ERR_INVALID_ARG, "null output");
+    if (c->batch) {
+        const ess_ctx::Batch& B = *c->batch;
+        std::vector<long long> r(B.chains_padded);
+        HIP_TRY(hipMemcpyAsync(r.data(), c->rej, sizeof(long long) * B.chains_padded,
+                               hipMemcpyDeviceToHost, c->st));
+        HIP_TRY(hipStreamSynchronize(c->st));
+        long long k = 0;
+        for (int p = 0; p < B.n; ++p)
+            for (int ch = 0; ch < B.h[p].C; ++ch) per_chain[k++] = r[B.h[p].chain_off + ch];
+        return ESS_OK;
+    }
     HIP_TRY(hipMemcpyAsync(per_chain, c->rej, sizeof(long long) * c->C, hipMemcpyDeviceToHost, c->st));
     HIP_TRY(hipStreamSynchronize(c->st));
+    return ESS_OK;
+}
+
+ess_status ess_init_batched(const ess_problem* pr, int32_t n_problems, void* stream, ess_ctx** out) {
+    g_err.clear();
+    if (!pr || !out) return fail(ESS_ERR_INVALID_ARG, "null problems or output pointer");
+    *out = nullptr;
+    if (n_problems < 1 || n_problems > (1 << 23))
+        return fail(ESS_ERR_INVALID_ARG, "n_problems must lie in [1, 2^23] (got %d)", n_problems);
+    long long total_chains = 0;
+    for (int p = 0; p < n_problems; ++p) {
+        const ess_problem& q = pr[p];
+        if (!q.A || !q.b || !q.x0) return fail(ESS_ERR_INVALID_ARG, "problem %d: null A, b or x0", p);
+        if (q.d < 1 || q.m < 1 || q.n_chains < 1)
+            return fail(ESS_ERR_INVALID_ARG, "problem %d: d, m and n_chains must be >= 1", p);
+        if (q.precision != 32)
+            return fail(ESS_ERR_UNSUPPORTED, "problem %d: batched problems run in precision 32", p);
+        if (!(q.trim_eps >= 0.0) || q.trim_eps > 1.0)
+            return fail(ESS_ERR_INVALID_ARG, "problem %d: trim_eps must lie in [0, 1]", p);
+        if (q.m > 4096) return fail(ESS_ERR_UNSUPPORTED, "problem %d: m = %d exceeds 4096", p, q.m);
+        if (q.d > (1 << 20)) return fail(ESS_ERR_UNSUPPORTED, "problem %d: d too large", p);
+        if (q.flags & ESS_SORT_FULL)
+            return fail(ESS_ERR_UNSUPPORTED, "problem %d: ESS_SORT_FULL is not offered for batches", p);
+        total_chains += q.n_chains;
+    }
+    if (total_chains > (1 << 24)) return fail(ESS_ERR_UNSUPPORTED, "too many chains in the batch");
+    ess_ctx* c = new ess_ctx();
+    c->prec = 32;
+    c->esz = 4;
+    c->st = static_cast<hipStream_t>(stream);
+    c->C = static_cast<int>(total_chains);
+    ess_status s = batched_init(c, pr, n_problems);
+    if (s != ESS_OK) {
+        std::string keep = g_err;
+        ess_destroy(c);
+        g_err = keep;
+        return s;
+    }
+    *out = c;
     return ESS_OK;
 }
 
@@ -448,23 +978,26 @@ ess_status ess_transition_explicit(ess_ctx* c, const void* x, const void* nu, co
                                    double* theta, int32_t* rejected, void* pq) {
     g_err.clear();
     ESS_TRY(check_ctx(c));
+    if (c->batch) return fail(ESS_ERR_UNSUPPORTED, "explicit transitions take single-problem contexts");
     if (!x || !nu || !u || !x_new) return fail(ESS_ERR_INVALID_ARG, "null x, nu, u or x_new");
     ESS_TRY(copy_rows_in(c, c->X, x));
     ESS_TRY(set_state_from_X(c, "ess_transition_explicit"));
     ESS_TRY(copy_rows_in(c, c->N, nu));
-    ESS_TRY(launch_proj(c, c->Xprop, COLS_NU, 0, 0));
-    SampleArgs a = sample_args(c);
+    const Group w = c->whole();
+    ESS_TRY(clear_fallback_lists(c, c->st, 0));
+    ESS_TRY(launch_proj(c, w, c->st, c->Xprop, COLS_NU, 0, 0));
+    SampleArgs a = sample_args(c, w, 0);
     a.step = static_cast<uint32_t>(c->step);
     a.u_explicit = u;
     a.intervals = intervals;
     a.n_intervals = n_intervals;
     a.theta_out = theta;
     a.pq_out = pq;
-    ESS_TRY(launch_sample(c, a));
-    ESS_TRY(launch_proj(c, c->Xprop, COLS_X, 0, 0));
-    SampleArgs f = sample_args(c);
+    ESS_TRY(launch_sample(c, w, c->st, a));
+    ESS_TRY(launch_proj(c, w, c->st, c->Xprop, COLS_X, 0, 0));
+    SampleArgs f = sample_args(c, w, 0);
     f.rejected_out = rejected;
-    ESS_TRY(launch_commit(c, f));
+    ESS_TRY(launch_commit(c, w, c->st, f));
     ESS_TRY(copy_rows_out(c, x_new, c->X));
     return ESS_OK;
 }
@@ -472,8 +1005,9 @@ ess_status ess_transition_explicit(ess_ctx* c, const void* x, const void* nu, co
 ess_status ess_draw(ess_ctx* c, uint64_t step, void* nu, double* u) {
     g_err.clear();
     ESS_TRY(check_ctx(c));
+    if (c->batch) return fail(ESS_ERR_UNSUPPORTED, "ess_draw takes single-problem contexts");
     if (step >= (1ull << 32)) return fail(ESS_ERR_UNSUPPORTED, "the step counter is limited to 2^32");
-    return launch_draw(c, step, nu, c->d, u);
+    return launch_draw(c, 0, c->C, c->st, step, nu, c->d, u);
 }
 
 }  // extern "C"

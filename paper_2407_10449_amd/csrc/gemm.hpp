@@ -1,11 +1,12 @@
 // Constraint projections for a block of chains: out[c][i] = a_i^T y_c.
 //
-// One launch covers a "virtual" chain axis of length 2 * Cp: columns
-// [0, Cp) read the proposals x' (their projections A x' are the safeguard
-// check of Section 3.3 and, once accepted, the next step's A x_t), columns
-// [Cp, 2 Cp) read the next ellipse directions nu (their projections A nu are
-// the q_i of the trigonometric equation, Section 2).  The paper notes both
-// products are the O(md) part of a step (Section 2.2).
+// One launch covers a group of Cg chains starting at chain c0, as a "virtual"
+// column axis of length 2 Cg: columns [0, Cg) read the proposals x' (their
+// projections A x' are the safeguard check of Section 3.3 and, once accepted,
+// the next step's A x_t), columns [Cg, 2 Cg) read the next ellipse directions
+// nu (their projections A nu are the q_i of the trigonometric equation,
+// Section 2).  The paper notes both products are the O(md) part of a step
+// (Section 2.2).  B0 and B1 point at the group's first row.
 //
 // Layout (all padded by the host so no tile ever leaves its buffers):
 //   A  [mp][dp]  row-major, rows >= m and columns >= d are zero
@@ -20,7 +21,9 @@ namespace ess {
 
 struct ProjOut {
     int m, C, Cp, mp;
-    const double* b;
+    int c0, Cg;       // the group's first chain and its (padded) size
+    const double* b;  // b of chain c starts at b + c * bstride
+    int bstride;      // 0: one b for all chains, m: one b per chain
     void* P;          // [2][Cp][mp]: the committed projections live in P[sel[c]]
     void* Q;          // [Cp][mp]
     const int* sel;   // [Cp]
@@ -33,8 +36,8 @@ struct ProjOut {
 template <typename T>
 __device__ __forceinline__ void proj_store4(const ProjOut& o, int n, int i0, T v0, T v1, T v2,
                                             T v3) {
-    if (n < o.Cp) {
-        const int c = n;
+    if (n < o.Cg) {
+        const int c = o.c0 + n;
         const int s = o.sel[c];
         const int buf = o.p_direct ? s : 1 - s;
         T* dst = static_cast<T*>(o.P) + (static_cast<size_t>(buf) * o.Cp + c) * o.mp + i0;
@@ -51,14 +54,14 @@ __device__ __forceinline__ void proj_store4(const ProjOut& o, int n, int i0, T v
                 const int i = i0 + r;
                 if (i < o.m) {
                     const double pv = static_cast<double>(vv[r]);
-                    const double bi = o.b[i];
+                    const double bi = o.b[static_cast<size_t>(c) * o.bstride + i];
                     bad |= o.strict ? (pv >= bi) : (pv > bi);
                 }
             }
             if (bad) o.flag[c] = 1;   // every writer stores the same value
         }
     } else {
-        const int c = n - o.Cp;
+        const int c = o.c0 + n - o.Cg;
         T* dst = static_cast<T*>(o.Q) + static_cast<size_t>(c) * o.mp + i0;
         if constexpr (sizeof(T) == 4) {
             *reinterpret_cast<float4*>(dst) = make_float4(v0, v1, v2, v3);
@@ -99,27 +102,29 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // are padded to 36 floats, which spreads the 16 rows of one read over
 // distinct banks.
 template <int BM, int BN>
-__global__ __launch_bounds__(256) void proj_gemm_f32(const float* __restrict__ A,
-                                                     const float* __restrict__ B0,
-                                                     const float* __restrict__ B1, int K,
-                                                     int tiles_m, int tiles_n, int tn0,
-                                                     int group_m, ProjOut o) {
-    constexpr int BK = 32, LK = BK + 4;
+struct GemmLds {
+    static constexpr int BK = 32, LK = BK + 4;
+    float As[2][BM * LK];
+    float Bs[2][BN * LK];
+};
+
+// One BM x BN output tile at (m0, n0) of the group described by `o`; B0 / B1
+// point at the group's first x' / nu row.  All 256 threads call it; the tile
+// ends with the block synchronised.
+template <int BM, int BN>
+__device__ __forceinline__ void gemm_tile_f32(const float* __restrict__ A,
+                                              const float* __restrict__ B0,
+                                              const float* __restrict__ B1, int K, int m0, int n0,
+                                              const ProjOut& o, GemmLds<BM, BN>& L) {
+    constexpr int BK = GemmLds<BM, BN>::BK, LK = GemmLds<BM, BN>::LK;
     constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 16, TN = WN / 16;
     constexpr int ALD = BM * BK / 4 / 256, BLD = BN * BK / 4 / 256;
     static_assert(ALD >= 1 && BLD >= 1, "tile too small for 256 threads");
-    __shared__ __attribute__((aligned(16))) float As[2][BM * LK];
-    __shared__ __attribute__((aligned(16))) float Bs[2][BN * LK];
-
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    int tm, tn;
-    tile_coords(blockIdx.x, tiles_m, tiles_n, group_m, tm, tn);
-    tn += tn0;
-    const int m0 = tm * BM, n0 = tn * BN;
     const float* Ab = A + static_cast<size_t>(m0) * K;
-    const float* Bb = (n0 < o.Cp) ? B0 + static_cast<size_t>(n0) * K
-                                  : B1 + static_cast<size_t>(n0 - o.Cp) * K;
+    const float* Bb = (n0 < o.Cg) ? B0 + static_cast<size_t>(n0) * K
+                                  : B1 + static_cast<size_t>(n0 - o.Cg) * K;
 
     f32x4 ra[ALD], rb[BLD];
     auto gload = [&](int k0) {
@@ -138,12 +143,12 @@ __global__ __launch_bounds__(256) void proj_gemm_f32(const float* __restrict__ A
 #pragma unroll
         for (int i = 0; i < ALD; ++i) {
             const int idx = tid + i * 256, row = idx >> 3, kq = idx & 7;
-            *reinterpret_cast<f32x4*>(&As[buf][row * LK + kq * 4]) = ra[i];
+            *reinterpret_cast<f32x4*>(&L.As[buf][row * LK + kq * 4]) = ra[i];
         }
 #pragma unroll
         for (int i = 0; i < BLD; ++i) {
             const int idx = tid + i * 256, row = idx >> 3, kq = idx & 7;
-            *reinterpret_cast<f32x4*>(&Bs[buf][row * LK + kq * 4]) = rb[i];
+            *reinterpret_cast<f32x4*>(&L.Bs[buf][row * LK + kq * 4]) = rb[i];
         }
     };
 
@@ -167,11 +172,11 @@ __global__ __launch_bounds__(256) void proj_gemm_f32(const float* __restrict__ A
 #pragma unroll
             for (int i = 0; i < TM; ++i)
                 af[i] = *reinterpret_cast<const f32x4*>(
-                    &As[buf][(wm * WM + i * 16 + (lane & 15)) * LK + kofs]);
+                    &L.As[buf][(wm * WM + i * 16 + (lane & 15)) * LK + kofs]);
 #pragma unroll
             for (int j = 0; j < TN; ++j)
                 bf[j] = *reinterpret_cast<const f32x4*>(
-                    &Bs[buf][(wn * WN + j * 16 + (lane & 15)) * LK + kofs]);
+                    &L.Bs[buf][(wn * WN + j * 16 + (lane & 15)) * LK + kofs]);
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
@@ -196,6 +201,28 @@ __global__ __launch_bounds__(256) void proj_gemm_f32(const float* __restrict__ A
         }
 }
 
+// float32 projections on the matrix cores (v_mfma_f32_16x16x4_f32), float32
+// accumulation.  256 threads = 2 x 2 waves, each wave owns a (BM/2) x (BN/2)
+// block of 16 x 16 MFMA tiles.  K advances 32 at a time through a double-
+// buffered LDS tile.  Inside each group of 16 k, lane l supplies the four k
+// values 4 (l / 16) .. 4 (l / 16) + 3 of its row as one 16-byte LDS read, and
+// MFMA number kk uses element kk: A and B use the same k for the same (lane
+// group, kk), so the contraction covers all 16 k exactly once.  Rows in LDS
+// are padded to 36 floats, which spreads the 16 rows of one read over
+// distinct banks.
+template <int BM, int BN>
+__global__ __launch_bounds__(256) void proj_gemm_f32(const float* __restrict__ A,
+                                                     const float* __restrict__ B0,
+                                                     const float* __restrict__ B1, int K,
+                                                     int tiles_m, int tiles_n, int tn0,
+                                                     int group_m, ProjOut o) {
+    __shared__ __attribute__((aligned(16))) GemmLds<BM, BN> lds;
+    int tm, tn;
+    tile_coords(blockIdx.x, tiles_m, tiles_n, group_m, tm, tn);
+    tn += tn0;
+    gemm_tile_f32<BM, BN>(A, B0, B1, K, tm * BM, tn * BN, o, lds);
+}
+
 // float64 projections on the vector ALUs (MI355X runs float64 FMA on the
 // vector units at the same rate as its float64 matrix cores).  64 x 64 tile,
 // each thread a 4 x 4 block: rows 4 ty .. 4 ty + 3, columns tx + 16 u.
@@ -215,8 +242,8 @@ __global__ __launch_bounds__(256) void proj_gemm_f64(const double* __restrict__ 
     tn += tn0;
     const int m0 = tm * BM, n0 = tn * BN;
     const double* Ab = A + static_cast<size_t>(m0) * K;
-    const double* Bb = (n0 < o.Cp) ? B0 + static_cast<size_t>(n0) * K
-                                   : B1 + static_cast<size_t>(n0 - o.Cp) * K;
+    const double* Bb = (n0 < o.Cg) ? B0 + static_cast<size_t>(n0) * K
+                                   : B1 + static_cast<size_t>(n0 - o.Cg) * K;
     double acc[4][4] = {};
     for (int k0 = 0; k0 < K; k0 += BK) {
 #pragma unroll

@@ -1,8 +1,7 @@
 // Per-chain part of one transition: commit the previous proposal, solve every
-// constraint's intersection angles, build the active intervals with a sort and
-// a cumulative max, draw theta, move, and draw the next ellipse direction.
-//
-// One 256-thread workgroup per chain; the chain's angles live in LDS.
+// constraint's intersection angles, build the active intervals, draw theta,
+// move, and draw the next ellipse direction.  One 256-thread workgroup per
+// chain.
 //
 // Roots (Appendix B): p = a_i^T x, q = a_i^T nu, r = hypot(p, q),
 // tau = atan2(q, p), phi = acos(b / r); the ellipse leaves the halfspace on the
@@ -12,18 +11,34 @@
 // pads them with alpha = beta = 0, which only adds zero-length candidates and
 // leaves every cumulative max unchanged, so they are dropped here instead.
 //
-// Active intervals (Algorithm 3 / Proposition 1): sort the alphas, carry the
-// betas; with gamma the running max of the betas in that order, the candidates
-// are [0, alpha_(1)], [gamma_(k-1), alpha_(k)] for k = 2..n and
-// [gamma_(n), 2 pi]; a candidate with its upper end below its lower end is
+// Active intervals (Algorithm 3 / Proposition 1): order the rows by alpha
+// (ties by row index) and let gamma be the running max of beta in that order;
+// the candidates are [0, alpha_(1)], [gamma_(k-1), alpha_(k)] for k = 2..n and
+// [gamma_(n), 2 pi]; a candidate whose upper end lies below its lower end is
 // empty.  Trimming (Section 3.3) moves real ends inward by eps; the ends at 0
-// and 2 pi are the seam through x_t and stay.
+// and 2 pi are the seam through x_t and stay.  theta is drawn by inverse CDF
+// over the candidates in ascending order.
 //
-// Sort keys: alpha is mapped monotonically to a 48-bit fixed-point turn
-// fraction floor(alpha * 2^48 / 2 pi) and packed above the 16-bit slot index,
-// so a single 64-bit compare orders the pairs.  Two alphas closer than
-// 2 pi * 2^-48 (2.2e-14 rad) may come out in either order, which moves the
-// union by at most their distance.
+// Two ways to produce the same non-empty candidates:
+//
+// * bucket path (sample_bucket_kernel): alpha is bucketed by angle into NB
+//   equal arcs (a monotone map, so buckets are a first pass of the sort), with
+//   the max beta of every bucket.  An exclusive max-scan over buckets gives
+//   G[b], the running max of beta over all rows of earlier buckets.  A row with
+//   alpha < G[its bucket] has gamma_(k-1) >= G > alpha: its candidate is empty
+//   whatever the order inside the bucket, and the cumulative max leaving the
+//   bucket does not depend on that order either.  Only the remaining rows
+//   ("survivors", typically a handful) need their exact predecessor max inside
+//   their own bucket, found by comparing against the bucket's rows in float64.
+//   The survivors' candidates are then ranked by (alpha, row) and summed in
+//   ascending order.
+// * full path (fallback_kernel): a bitonic sort of all crossing rows in LDS,
+//   for chains with more than SMAX survivors (adversarial inputs such as many
+//   nested arcs in one bucket) or when the full sort is requested.  Keys are
+//   alpha mapped monotonically to a 48-bit fixed-point turn fraction
+//   floor(alpha * 2^48 / 2 pi) above a 16-bit slot index, so one 64-bit
+//   compare orders them; two alphas closer than 2 pi * 2^-48 (2.2e-14 rad)
+//   may swap, which moves the union by at most their distance.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -34,8 +49,10 @@ namespace ess {
 
 struct SampleArgs {
     int d, m, C, Cp, dp, mp;
+    int c0;               // first chain of this launch (block b handles chain c0 + b)
     uint32_t problem;
-    const double* b;      // [m]
+    const double* b;      // [m], or [C][m] when bstride = m
+    int bstride;
     const void* P;        // [2][Cp][mp] T
     const void* Q;        // [Cp][mp] T
     void* X;              // [Cp][dp] T, committed state
@@ -56,10 +73,14 @@ struct SampleArgs {
     double* theta_out;    // nullable: [C]
     void* pq_out;         // nullable: [2][C][m] T
     int* rejected_out;    // nullable: [C] (commit kernel)
+    int* fb_list;         // [C]: chains handed to the full path this step
+    int* fb_count;        // [2]: list length, indexed by step parity
+    int force_full;       // 1: every chain takes the full path
 };
 
 constexpr double kKeyScale = 281474976710656.0 / kTwoPi;   // 2^48 / (2 pi)
 constexpr uint64_t kKeyMax = (1ull << 48) - 1;
+constexpr int SMAX = 128;   // survivors the bucket path resolves in place
 
 __device__ __forceinline__ bool solve_roots(double p, double q, double bi, double& al,
                                             double& be) {
@@ -84,9 +105,15 @@ __device__ __forceinline__ uint64_t sort_key(double alpha, int slot) {
     return (q << 16) | static_cast<uint64_t>(slot);
 }
 
+// bit pattern of a non-negative double: integer order equals numeric order
+__device__ __forceinline__ unsigned long long obits(double v) {
+    return static_cast<unsigned long long>(__double_as_longlong(v));
+}
+__device__ __forceinline__ double ofloat(unsigned long long v) {
+    return __longlong_as_double(static_cast<long long>(v));
+}
+
 // ---- block-wide helpers (256 threads = 4 waves of 64) ----
-// Position of this thread's element among the block's true predicates, and
-// the block total.
 __device__ __forceinline__ int block_count_prefix(bool pred, int* s_w, int& total) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const unsigned long long mask = __ballot(pred);
@@ -153,47 +180,106 @@ __device__ __forceinline__ void bitonic_sort_lds(uint64_t* key, int n2) {
     }
 }
 
-// Accept or reject the pending proposal of chain c (Section 3.3: a proposal
+// Everything the per-chain code touches for one chain: its problem's sizes and
+// right-hand side, its rows of the state, proposal, direction and projection
+// buffers, its bookkeeping entries, and optional outputs.
+template <typename T>
+struct ChainRef {
+    int d, m;
+    uint32_t chain, problem, step;   // Philox counter words (chain index within its problem)
+    int gen_next;
+    double eps;
+    uint64_t seed;
+    const double* b;
+    const T* P0;          // committed projections of buffer s start at P0 + s * pstride
+    size_t pstride;
+    const T* q;
+    T* x;
+    T* xp;
+    T* nu;
+    int* sel;
+    int* flag;
+    long long* rej;
+    T* trace;             // nullable
+    const double* u;      // nullable: explicit uniform
+    double* intervals;    // nullable: (m + 1) x 2
+    int* n_intervals;     // nullable
+    double* theta_out;    // nullable
+    T* p_out;             // nullable
+    T* q_out;             // nullable
+    int* rejected_out;    // nullable
+};
+
+template <typename T>
+__device__ __forceinline__ ChainRef<T> make_ref(const SampleArgs& a, int c) {
+    ChainRef<T> r;
+    r.d = a.d;
+    r.m = a.m;
+    r.chain = static_cast<uint32_t>(c);
+    r.problem = a.problem;
+    r.step = a.step;
+    r.gen_next = a.gen_next;
+    r.eps = a.eps;
+    r.seed = a.seed;
+    r.b = a.b + static_cast<size_t>(c) * a.bstride;
+    r.P0 = static_cast<const T*>(a.P) + static_cast<size_t>(c) * a.mp;
+    r.pstride = static_cast<size_t>(a.Cp) * a.mp;
+    r.q = static_cast<const T*>(a.Q) + static_cast<size_t>(c) * a.mp;
+    r.x = static_cast<T*>(a.X) + static_cast<size_t>(c) * a.dp;
+    r.xp = static_cast<T*>(a.Xprop) + static_cast<size_t>(c) * a.dp;
+    r.nu = static_cast<T*>(a.N) + static_cast<size_t>(c) * a.dp;
+    r.sel = a.sel + c;
+    r.flag = a.flag + c;
+    r.rej = a.rej + c;
+    r.trace = a.trace ? static_cast<T*>(a.trace) + static_cast<size_t>(c) * a.d : nullptr;
+    r.u = a.u_explicit ? a.u_explicit + c : nullptr;
+    r.intervals = a.intervals ? a.intervals + static_cast<size_t>(c) * (a.m + 1) * 2 : nullptr;
+    r.n_intervals = a.n_intervals ? a.n_intervals + c : nullptr;
+    r.theta_out = a.theta_out ? a.theta_out + c : nullptr;
+    r.p_out = a.pq_out ? static_cast<T*>(a.pq_out) + static_cast<size_t>(c) * a.m : nullptr;
+    r.q_out = a.pq_out ? static_cast<T*>(a.pq_out) + (static_cast<size_t>(a.C) + c) * a.m : nullptr;
+    r.rejected_out = a.rejected_out ? a.rejected_out + c : nullptr;
+    return r;
+}
+
+// Accept or reject the chain's pending proposal (Section 3.3: a proposal
 // violating some constraint is dropped and the chain stays).  Returns the
 // buffer index of the chain's committed projections.
 template <typename T>
-__device__ __forceinline__ int commit_chain(const SampleArgs& a, int c) {
-    const int fl = a.flag[c];
-    const int s = a.sel[c];
+__device__ __forceinline__ int commit_chain(const ChainRef<T>& r) {
+    const int fl = *r.flag;
+    const int s = *r.sel;
     __syncthreads();   // all reads of flag / sel precede the writes below
     const int snew = fl ? s : (s ^ 1);
     if (threadIdx.x == 0) {
-        if (fl) a.rej[c] += 1;
-        a.sel[c] = snew;
-        a.flag[c] = 0;
-        if (a.rejected_out) a.rejected_out[c] = fl;
+        if (fl) *r.rej += 1;
+        *r.sel = snew;
+        *r.flag = 0;
+        if (r.rejected_out) *r.rejected_out = fl;
     }
-    T* x = static_cast<T*>(a.X) + static_cast<size_t>(c) * a.dp;
-    const T* xp = static_cast<const T*>(a.Xprop) + static_cast<size_t>(c) * a.dp;
-    T* tr = a.trace ? static_cast<T*>(a.trace) + static_cast<size_t>(c) * a.d : nullptr;
-    for (int k = threadIdx.x; k < a.d; k += 256) {
+    for (int k = threadIdx.x; k < r.d; k += blockDim.x) {
         T v;
         if (!fl) {
-            v = xp[k];
-            x[k] = v;
+            v = r.xp[k];
+            r.x[k] = v;
         } else {
-            v = x[k];
+            v = r.x[k];
         }
-        if (tr) tr[k] = v;
+        if (r.trace) r.trace[k] = v;
     }
     return snew;
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void commit_kernel(SampleArgs a) {
-    commit_chain<T>(a, blockIdx.x);
+    commit_chain<T>(make_ref<T>(a, a.c0 + blockIdx.x));
 }
 
-// nu for `step` into dst[c * ld + k], k < d (chains 0 .. C-1).
+// nu for `step` into dst[c * ld + k], k < d (chains c0 .. c0 + gridDim.x - 1).
 template <typename T>
 __global__ __launch_bounds__(256) void draw_kernel(uint64_t seed, uint32_t step, uint32_t problem,
-                                                   int d, T* dst, long long ld, double* u) {
-    const int c = blockIdx.x;
+                                                   int d, T* dst, long long ld, double* u, int c0) {
+    const int c = c0 + blockIdx.x;
     const Rng rng(seed);
     T* row = dst ? dst + static_cast<size_t>(c) * ld : nullptr;
     if (row) {
@@ -207,70 +293,94 @@ __global__ __launch_bounds__(256) void draw_kernel(uint64_t seed, uint32_t step,
     if (u && threadIdx.x == 0) u[c] = rng.theta_uniform(c, step, problem);
 }
 
-template <typename T, int NMAX>
-__global__ __launch_bounds__(256) void sample_kernel(SampleArgs a) {
-    __shared__ double s_alpha[NMAX];
-    __shared__ double s_beta[NMAX];
-    __shared__ uint64_t s_key[NMAX];
-    __shared__ double s_red[4];
-    __shared__ int s_cnt[4];
-    __shared__ double s_bcast[2];
-    __shared__ int s_kstar;
-    __shared__ double s_theta[2];
+template <typename T>
+__device__ __forceinline__ double theta_uniform(const ChainRef<T>& r) {
+    return r.u ? *r.u : Rng(r.seed).theta_uniform(r.chain, r.step, r.problem);
+}
 
-    const int c = blockIdx.x;
+// Move along the ellipse, x' = x cos(theta) + nu sin(theta), then (optionally)
+// replace nu by the next step's draw.  Called by all threads of the block.
+template <typename T>
+__device__ __forceinline__ void move_chain(const ChainRef<T>& r, double theta) {
+    if (threadIdx.x == 0 && r.theta_out) *r.theta_out = theta;
+    double sd, cd;
+    sincos(theta, &sd, &cd);
+    const T ct = static_cast<T>(cd), st = static_cast<T>(sd);
+    for (int k = threadIdx.x; k < r.d; k += blockDim.x) r.xp[k] = r.x[k] * ct + r.nu[k] * st;
+    if (r.gen_next) {
+        __syncthreads();   // every read of this step's nu is done
+        const Rng rng(r.seed);
+        for (int j = threadIdx.x; 2 * j < r.d; j += blockDim.x) {
+            double z0, z1;
+            rng.normal_pair(j, r.chain, r.step + 1, r.problem, z0, z1);
+            r.nu[2 * j] = static_cast<T>(z0);
+            if (2 * j + 1 < r.d) r.nu[2 * j + 1] = static_cast<T>(z1);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Full path: bitonic sort of every crossing row, then the sweep.
+// ---------------------------------------------------------------------------
+struct FullLds {
+    double* alpha;
+    double* beta;
+    uint64_t* key;
+    double* red;      // [4]
+    int* cnt;         // [4]
+    double* bcast;    // [2]
+    int* kstar;       // [1]
+    double* theta;    // [1]
+};
+
+template <typename T>
+__device__ void full_chain(const ChainRef<T>& r, int sel, const FullLds& L) {
     const int tid = threadIdx.x;
-    int sel = a.sel[c];
-    if (a.has_pending) sel = commit_chain<T>(a, c);
-
-    // ---- roots of every constraint; keep the rows the ellipse crosses ----
-    const T* Pc = static_cast<const T*>(a.P) + (static_cast<size_t>(sel) * a.Cp + c) * a.mp;
-    const T* Qc = static_cast<const T*>(a.Q) + static_cast<size_t>(c) * a.mp;
+    const T* Pc = r.P0 + static_cast<size_t>(sel) * r.pstride;
     int n = 0;
-    for (int i0 = 0; i0 < a.m; i0 += 256) {
+    for (int i0 = 0; i0 < r.m; i0 += 256) {
         const int i = i0 + tid;
         double al = 0.0, be = 0.0;
         bool hit = false;
-        if (i < a.m) {
-            const T p = Pc[i], q = Qc[i];
-            hit = solve_roots(static_cast<double>(p), static_cast<double>(q), a.b[i], al, be);
-            if (a.pq_out) {
-                T* pq = static_cast<T*>(a.pq_out);
-                pq[static_cast<size_t>(c) * a.m + i] = p;
-                pq[(static_cast<size_t>(a.C) + c) * a.m + i] = q;
+        if (i < r.m) {
+            const T p = Pc[i], q = r.q[i];
+            hit = solve_roots(static_cast<double>(p), static_cast<double>(q), r.b[i], al, be);
+            if (r.p_out) {
+                r.p_out[i] = p;
+                r.q_out[i] = q;
             }
         }
         int tot;
-        const int pos = block_count_prefix(hit, s_cnt, tot);
+        const int pos = block_count_prefix(hit, L.cnt, tot);
         if (hit) {
             const int slot = n + pos;
-            s_alpha[slot] = al;
-            s_beta[slot] = be;
-            s_key[slot] = sort_key(al, slot);
+            L.alpha[slot] = al;
+            L.beta[slot] = be;
+            L.key[slot] = sort_key(al, slot);
         }
         n += tot;
     }
     int n2 = 512;
     while (n2 < n) n2 <<= 1;
-    for (int k = n + tid; k < n2; k += 256) s_key[k] = ~0ull;
+    for (int k = n + tid; k < n2; k += 256) L.key[k] = ~0ull;
     __syncthreads();
-    bitonic_sort_lds(s_key, n2);
+    bitonic_sort_lds(L.key, n2);
 
-    // ---- sweep: running max of beta in alpha order, candidate lengths ----
+    // sweep: running max of beta in alpha order, candidate lengths
     const int per = n2 >> 8;
     const int k0 = tid * per;
     const int k1 = min(k0 + per, n);
-    const double eps = a.eps;
+    const double eps = r.eps;
     double tmax = 0.0;
-    for (int k = k0; k < k1; ++k) tmax = fmax(tmax, s_beta[s_key[k] & 0xFFFF]);
-    const double g_in = block_excl_scan(tmax, 0.0, MaxOp(), s_red);
+    for (int k = k0; k < k1; ++k) tmax = fmax(tmax, L.beta[L.key[k] & 0xFFFF]);
+    const double g_in = block_excl_scan(tmax, 0.0, MaxOp(), L.red);
     const bool owns_last = (tid == 255);
 
     auto cand = [&](int k, double& g, double& lo, double& hi) {
-        const int slot = static_cast<int>(s_key[k] & 0xFFFF);
+        const int slot = static_cast<int>(L.key[k] & 0xFFFF);
         lo = g;
-        hi = s_alpha[slot];
-        g = fmax(g, s_beta[slot]);
+        hi = L.alpha[slot];
+        g = fmax(g, L.beta[slot]);
         if (lo > 0.0) lo += eps;
         if (hi < kTwoPi) hi -= eps;
     };
@@ -292,15 +402,14 @@ __global__ __launch_bounds__(256) void sample_kernel(SampleArgs a) {
         last_len = fmax(kTwoPi - last_lo, 0.0);
         tsum += last_len;
     }
-    const double s_in = block_excl_scan(tsum, 0.0, SumOp(), s_red);
-    if (owns_last) s_bcast[0] = s_in + tsum;
-    if (tid == 0) s_kstar = 0x7FFFFFFF;
+    const double s_in = block_excl_scan(tsum, 0.0, SumOp(), L.red);
+    if (owns_last) L.bcast[0] = s_in + tsum;
+    if (tid == 0) *L.kstar = 0x7FFFFFFF;
     __syncthreads();
-    const double total = s_bcast[0];
-    const double u = a.u_explicit ? a.u_explicit[c] : Rng(a.seed).theta_uniform(c, a.step, a.problem);
-    const double s = u * total;
+    const double total = L.bcast[0];
+    const double s = theta_uniform(r) * total;
 
-    // ---- theta: first candidate whose running sum exceeds s (inverse CDF) ----
+    // theta: first candidate whose running sum exceeds s (inverse CDF)
     double my_theta = 0.0, last_hi = 0.0;
     int my_k = 0x7FFFFFFF, last_k = -1;
     if (total > 0.0) {
@@ -327,29 +436,29 @@ __global__ __launch_bounds__(256) void sample_kernel(SampleArgs a) {
             last_k = n;
             last_hi = kTwoPi;
         }
-        if (my_k != 0x7FFFFFFF) atomicMin(&s_kstar, my_k);
+        if (my_k != 0x7FFFFFFF) atomicMin(L.kstar, my_k);
     }
     __syncthreads();
-    const int kstar = s_kstar;
-    __syncthreads();   // every thread has read s_kstar before it is reused
+    const int kstar = *L.kstar;
+    __syncthreads();   // every thread has read kstar before it is reused
     if (total > 0.0) {
         if (kstar == 0x7FFFFFFF) {
             // s rounded up to the total: take the upper end of the last piece
-            if (tid == 0) s_kstar = -1;
+            if (tid == 0) *L.kstar = -1;
             __syncthreads();
-            if (last_k >= 0) atomicMax(&s_kstar, last_k);
+            if (last_k >= 0) atomicMax(L.kstar, last_k);
             __syncthreads();
-            if (last_k >= 0 && last_k == s_kstar) s_theta[0] = last_hi;
+            if (last_k >= 0 && last_k == *L.kstar) L.theta[0] = last_hi;
         } else if (my_k == kstar) {
-            s_theta[0] = my_theta;
+            L.theta[0] = my_theta;
         }
     } else if (tid == 0) {
-        s_theta[0] = 0.0;
-        a.flag[c] = 1;   // empty active set: stay, counted as a rejection
+        L.theta[0] = 0.0;
+        *r.flag = 1;   // empty active set: stay, counted as a rejection
     }
 
-    // ---- optional: the non-empty trimmed intervals, ascending ----
-    if (a.intervals) {
+    // optional: the non-empty trimmed intervals, ascending
+    if (r.intervals) {
         int cnt = 0;
         {
             double g = g_in;
@@ -360,52 +469,242 @@ __global__ __launch_bounds__(256) void sample_kernel(SampleArgs a) {
             }
             if (owns_last) cnt += (last_len > 0.0);
         }
-        const double base = block_excl_scan(static_cast<double>(cnt), 0.0, SumOp(), s_red);
+        const double base = block_excl_scan(static_cast<double>(cnt), 0.0, SumOp(), L.red);
         int w = static_cast<int>(base);
-        double* out = a.intervals + static_cast<size_t>(c) * (a.m + 1) * 2;
         double g = g_in;
         for (int k = k0; k < k1; ++k) {
             double lo, hi;
             cand(k, g, lo, hi);
             if (hi - lo > 0.0) {
-                out[2 * w] = lo;
-                out[2 * w + 1] = hi;
+                r.intervals[2 * w] = lo;
+                r.intervals[2 * w + 1] = hi;
                 ++w;
             }
         }
         if (owns_last) {
             if (last_len > 0.0) {
-                out[2 * w] = last_lo;
-                out[2 * w + 1] = kTwoPi;
+                r.intervals[2 * w] = last_lo;
+                r.intervals[2 * w + 1] = kTwoPi;
                 ++w;
             }
-            if (a.n_intervals) a.n_intervals[c] = w;
+            if (r.n_intervals) *r.n_intervals = w;
         }
     }
     __syncthreads();
-    const double theta = s_theta[0];
-    if (tid == 0 && a.theta_out) a.theta_out[c] = theta;
+    move_chain<T>(r, L.theta[0]);
+}
 
-    // ---- move along the ellipse: x' = x cos(theta) + nu sin(theta) ----
-    double sd, cd;
-    sincos(theta, &sd, &cd);
-    const T ct = static_cast<T>(cd), st = static_cast<T>(sd);
-    const T* x = static_cast<const T*>(a.X) + static_cast<size_t>(c) * a.dp;
-    T* xp = static_cast<T*>(a.Xprop) + static_cast<size_t>(c) * a.dp;
-    T* nu = static_cast<T*>(a.N) + static_cast<size_t>(c) * a.dp;
-    for (int k = tid; k < a.d; k += 256) xp[k] = x[k] * ct + nu[k] * st;
+#define ESS_FULL_LDS(NMAX)                                  \
+    __shared__ double s_alpha[NMAX];                        \
+    __shared__ double s_beta[NMAX];                         \
+    __shared__ uint64_t s_key[NMAX];                        \
+    __shared__ double s_red[4];                             \
+    __shared__ int s_cnt[4];                                \
+    __shared__ double s_bcast[2];                           \
+    __shared__ int s_kstar;                                 \
+    __shared__ double s_theta[2];                           \
+    const FullLds full_lds{s_alpha, s_beta, s_key, s_red, s_cnt, s_bcast, &s_kstar, s_theta};
 
-    // ---- the next step's ellipse direction ----
-    if (a.gen_next) {
-        __syncthreads();   // every read of this step's nu is done
-        const Rng rng(a.seed);
-        for (int j = tid; 2 * j < a.d; j += 256) {
-            double z0, z1;
-            rng.normal_pair(j, c, a.step + 1, a.problem, z0, z1);
-            nu[2 * j] = static_cast<T>(z0);
-            if (2 * j + 1 < a.d) nu[2 * j + 1] = static_cast<T>(z1);
+// Chains the bucket path handed over (a.fb_list[0 .. fb_count[step & 1])),
+// processed by a grid-stride loop.  The bucket kernel of the next step clears
+// this count; the host clears both counts when a call starts.
+template <typename T, int NMAX>
+__global__ __launch_bounds__(256) void fallback_kernel(SampleArgs a) {
+    ESS_FULL_LDS(NMAX)
+    const int count = a.fb_count[a.step & 1];
+    for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
+        const ChainRef<T> r = make_ref<T>(a, a.fb_list[idx]);
+        full_chain<T>(r, *r.sel, full_lds);
+        __syncthreads();
+    }
+}
+
+__global__ void zero_ints(int* p, int n) {
+    if (static_cast<int>(threadIdx.x) < n) p[threadIdx.x] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Bucket path.  RPT rows per thread (m <= 256 RPT), NB angle buckets.
+// ---------------------------------------------------------------------------
+template <int NB>
+struct BucketLds {
+    unsigned long long G[NB];          // bucket max beta, then prefix max
+    double sa[SMAX], sb[SMAX];         // survivors: alpha, beta
+    int si[SMAX], sk[SMAX];            // survivors: row, bucket
+    unsigned long long sm[SMAX];       // survivors: in-bucket predecessor max
+    double lo[SMAX + 1], hi[SMAX + 1];
+    double red[4];
+    double gtot;
+    int scount;
+    double theta;
+};
+
+// Returns false when the chain has more than SMAX survivors: nothing has been
+// moved and the caller hands the chain to the full path.
+template <typename T, int RPT, int NB>
+__device__ bool bucket_chain(const ChainRef<T>& r, int sel, BucketLds<NB>& L) {
+    const int tid = threadIdx.x;
+    constexpr double kBucket = NB / kTwoPi;
+    for (int b = tid; b < NB; b += 256) L.G[b] = 0ull;
+    if (tid == 0) L.scount = 0;
+
+    // roots of this thread's rows (row i = tid + 256 r); beta = 0 marks no crossing
+    const T* Pc = r.P0 + static_cast<size_t>(sel) * r.pstride;
+    double al[RPT], be[RPT];
+    int bk[RPT];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int i = tid + 256 * j;
+        al[j] = 0.0;
+        be[j] = 0.0;
+        bk[j] = 0;
+        if (i < r.m) {
+            const T p = Pc[i], q = r.q[i];
+            double x0, x1;
+            if (solve_roots(static_cast<double>(p), static_cast<double>(q), r.b[i], x0, x1)) {
+                al[j] = x0;
+                be[j] = x1;
+                bk[j] = min(static_cast<int>(x0 * kBucket), NB - 1);
+            }
+            if (r.p_out) {
+                r.p_out[i] = p;
+                r.q_out[i] = q;
+            }
         }
     }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < RPT; ++j)
+        if (be[j] > 0.0) atomicMax(&L.G[bk[j]], obits(be[j]));
+    __syncthreads();
+
+    // exclusive prefix max over buckets, in place: G[b] = max beta of rows in
+    // buckets < b (0 if none); thread t owns buckets [t NB/256, (t+1) NB/256)
+    constexpr int BPT = NB / 256;
+    double tmax = 0.0;
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) tmax = fmax(tmax, ofloat(L.G[tid * BPT + j]));
+    const double g_in = block_excl_scan(tmax, 0.0, MaxOp(), L.red);
+    {
+        double run = g_in;
+#pragma unroll
+        for (int j = 0; j < BPT; ++j) {
+            const double v = ofloat(L.G[tid * BPT + j]);
+            L.G[tid * BPT + j] = obits(run);
+            run = fmax(run, v);
+        }
+        if (tid == 255) L.gtot = run;   // gamma_n: max beta over all rows
+    }
+    __syncthreads();
+
+    // survivors: rows whose candidate can be non-empty
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        if (be[j] > 0.0 && al[j] >= ofloat(L.G[bk[j]])) {
+            const int k = atomicAdd(&L.scount, 1);
+            if (k < SMAX) {
+                L.sa[k] = al[j];
+                L.sb[k] = be[j];
+                L.si[k] = tid + 256 * j;
+                L.sk[k] = bk[j];
+                L.sm[k] = 0ull;
+            }
+        }
+    }
+    __syncthreads();
+    const int S = L.scount;
+    if (S > SMAX) return false;
+
+    // exact predecessor max inside each survivor's bucket (ties by row index)
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        if (be[j] > 0.0) {
+            const int i = tid + 256 * j;
+            for (int s = 0; s < S; ++s) {
+                if (L.sk[s] == bk[j] && (al[j] < L.sa[s] || (al[j] == L.sa[s] && i < L.si[s])))
+                    atomicMax(&L.sm[s], obits(be[j]));
+            }
+        }
+    }
+    __syncthreads();
+
+    // the survivors' candidates, placed in ascending (alpha, row) order
+    const double eps = r.eps;
+    if (tid < S) {
+        const double alpha = L.sa[tid];
+        const int row = L.si[tid];
+        int rank = 0;
+        for (int s = 0; s < S; ++s) {
+            const double o = L.sa[s];
+            rank += (o < alpha) || (o == alpha && L.si[s] < row);
+        }
+        double lo = fmax(ofloat(L.G[L.sk[tid]]), ofloat(L.sm[tid]));
+        double hi = alpha;
+        if (lo > 0.0) lo += eps;
+        if (hi < kTwoPi) hi -= eps;
+        L.lo[rank] = lo;
+        L.hi[rank] = hi;
+    }
+    if (tid == 0) {
+        const double g = L.gtot;
+        L.lo[S] = g > 0.0 ? g + eps : g;
+        L.hi[S] = kTwoPi;
+    }
+    __syncthreads();
+
+    // inverse CDF over the S + 1 candidates in order (a sequential sum, so the
+    // running sums are those of a left-to-right cumulative sum)
+    if (tid == 0) {
+        double total = 0.0;
+        for (int k = 0; k <= S; ++k) total += fmax(L.hi[k] - L.lo[k], 0.0);
+        double theta = 0.0;
+        if (total > 0.0) {
+            const double s = theta_uniform(r) * total;
+            double run = 0.0;
+            int last = -1;
+            bool found = false;
+            for (int k = 0; k <= S; ++k) {
+                const double len = fmax(L.hi[k] - L.lo[k], 0.0);
+                if (len > 0.0) {
+                    last = k;
+                    if (!found && run + len > s) {
+                        theta = fmax(L.lo[k], fmin(L.lo[k] + (s - run), L.hi[k]));
+                        found = true;
+                    }
+                }
+                run += len;
+            }
+            if (!found) theta = L.hi[last];
+        } else {
+            *r.flag = 1;   // empty active set: stay, counted as a rejection
+        }
+        L.theta = theta;
+        if (r.intervals) {
+            int w = 0;
+            for (int k = 0; k <= S; ++k) {
+                if (L.hi[k] - L.lo[k] > 0.0) {
+                    r.intervals[2 * w] = L.lo[k];
+                    r.intervals[2 * w + 1] = L.hi[k];
+                    ++w;
+                }
+            }
+            if (r.n_intervals) *r.n_intervals = w;
+        }
+    }
+    __syncthreads();
+    move_chain<T>(r, L.theta);
+    return true;
+}
+
+template <typename T, int RPT, int NB>
+__global__ __launch_bounds__(256) void sample_bucket_kernel(SampleArgs a) {
+    __shared__ BucketLds<NB> lds;
+    const int c = a.c0 + blockIdx.x;
+    const ChainRef<T> r = make_ref<T>(a, c);
+    const int sel = a.has_pending ? commit_chain<T>(r) : *r.sel;
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.fb_count[(a.step + 1) & 1] = 0;   // next step's list
+    const bool done = !a.force_full && bucket_chain<T, RPT, NB>(r, sel, lds);
+    if (!done && threadIdx.x == 0) a.fb_list[atomicAdd(a.fb_count + (a.step & 1), 1)] = c;
 }
 
 }  // namespace ess

@@ -1,0 +1,79 @@
+"""Batched contexts: many uneven polytopes in one persistent launch per step."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import ess as ref_ess
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def E():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2407_10449_amd as E
+    E.lib()
+    return E
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def problems(n, chains, seed=4):
+    probs = synth.batched_uneven(rng_seed=seed, n_problems=n, chains_per_problem=chains)
+    return [dict(A=p.A, b=p.b, x0=p.x0, n_chains=p.n_chains, seed=100 + i, trim_eps=1e-6)
+            for i, p in enumerate(probs)]
+
+
+def test_batched_matches_oracle_first_steps(E):
+    """Each problem's chains follow the oracle's Philox stream (problem word p)."""
+    probs = problems(10, 16)
+    say("[batched] shapes", [(p["A"].shape, p["n_chains"]) for p in probs])
+    s = E.BatchedSampler(probs)
+    T = 3
+    tr, _ = s.run(T)
+    per = s.split(tr.cpu().numpy())
+    s.close()
+    for p, (pr, g) in enumerate(zip(probs, per)):
+        rtr, _, _ = ref_ess.run(pr["A"].astype(np.float32).astype(np.float64), pr["b"], pr["x0"],
+                                pr["n_chains"], T, seed=pr["seed"], eps=1e-6, store=np.float32,
+                                problem=p)
+        err = np.abs(g - rtr).max(axis=(0, 2))
+        assert (err < 1e-4).mean() >= 0.9, (p, np.sort(err)[-4:])
+
+
+def test_batched_checkpoint_and_determinism(E):
+    probs = problems(6, 8, seed=7)
+    a = E.BatchedSampler(probs)
+    full, _ = a.run(8, thin=2)
+    b = E.BatchedSampler(probs)
+    half, _ = b.run(4, thin=2)
+    x, step = b.state()
+    c = E.BatchedSampler(probs)
+    c.set_state(x, step)
+    rest, _ = c.run(4, thin=2)
+    assert torch.equal(full[:2], half) and torch.equal(full[2:], rest)
+    d = E.BatchedSampler(probs)
+    again, _ = d.run(8, thin=2)
+    assert torch.equal(full, again)
+    for s in (a, b, c, d):
+        s.close()
+
+
+def test_batched_full_workload_stays_feasible(E):
+    """256 polytopes, d log-uniform in [16, 512], m = d U{1..4}, 64 chains each."""
+    probs = problems(256, 64)
+    s = E.BatchedSampler(probs)
+    tr, nrej = s.run(20, thin=5)
+    per = s.split(tr.double().cpu().numpy())
+    s.close()
+    for pr, g in zip(probs, per):
+        slack = pr["b"] - g @ pr["A"].T
+        bound = 2 * pr["A"].shape[1] * 2.0 ** -24 * (np.abs(g) @ np.abs(pr["A"]).T)
+        assert (slack >= -bound).all()
+    assert nrej <= 1e-4 * 256 * 64 * 20

@@ -201,3 +201,75 @@ def test_errors_are_reported(E):
     prob = E.EssProblem(3, 2, 4, 32, None, None, None, 0, 0.0, 0)
     with pytest.raises(E.EssError):
         E.ess_init(prob)
+
+
+def arcs_problem(alpha, beta):
+    """d = 2 rows whose forbidden arcs on the ellipse through x = e1, nu = e2
+    are exactly (alpha_i, beta_i): a_i = (cos tau, sin tau), b_i = cos phi with
+    tau, phi the arc's centre and half-width (Appendix B read backwards)."""
+    tau = 0.5 * (alpha + beta)
+    phi = 0.5 * (beta - alpha)
+    A = np.stack([np.cos(tau), np.sin(tau)], axis=1)
+    return A, np.cos(phi)
+
+
+def run_arcs(E, alpha, beta, precision, full_sort=False, C=8):
+    A, b = arcs_problem(alpha, beta)
+    npdt = np.float32 if precision == 32 else np.float64
+    x = np.tile(np.array([1.0, 0.0], npdt), (C, 1))
+    nu = np.tile(np.array([0.0, 1.0], npdt), (C, 1))
+    u = (np.arange(C) + 0.5) / C
+    s = E.Sampler(A, b, x, C, seed=0, precision=precision, trim_eps=0.0, full_sort=full_sort)
+    g = {k: v.cpu().numpy() for k, v in s.transition_explicit(x, nu, u).items()}
+    s.close()
+    Ab = A.astype(npdt).astype(np.float64)
+    ref = ref_ess.transition(Ab, b, x.astype(np.float64), nu.astype(np.float64), u, store=npdt)
+    return Ab, b, x.astype(np.float64), nu, u, g, ref
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_sorting_reduction_takes_full_path(E, precision):
+    """Section 3.1's reduction: every row ends a gap, so 300 survivors overflow
+    the bucket path and the chain is sorted in full.  Arcs are kept wider than
+    float32 rounding of A can blur (about 3.5e-4 rad)."""
+    rng = np.random.default_rng(7)
+    c = 0.1 + 5.9 * (np.arange(300) + rng.uniform(0.2, 0.4, 300)) / 300
+    Ab, b, x, nu, u, g, ref = run_arcs(E, c, c + 0.005, precision)
+    assert (g["n_intervals"] == 301).all(), g["n_intervals"]
+    fails, _ = compare_transition(Ab, b, x, nu, u, g, ref)
+    assert not fails, fails[:5]
+
+
+@pytest.mark.parametrize("precision,m", [(32, 7), (64, 14)])
+def test_appendix_d_nested_arcs_in_one_bucket(E, precision, m):
+    """Appendix D's worst case, I_i = [0, 3^-i] U [2 3^-i, 1] (scaled by 2 pi),
+    placed at pi / 2 so the arcs are well conditioned: the nested arcs share a
+    bucket and the in-bucket refinement must recover all m + 1 intervals."""
+    i = np.arange(1, m + 1)
+    al = 2 * np.pi * 3.0 ** -i
+    Ab, b, x, nu, u, g, ref = run_arcs(E, 0.5 * np.pi + al, 0.5 * np.pi + 2 * al, precision)
+    assert (g["n_intervals"] == m + 1).all(), g["n_intervals"]
+    fails, _ = compare_transition(Ab, b, x, nu, u, g, ref)
+    assert not fails, fails[:5]
+
+
+@pytest.mark.parametrize("name,d,m,C,precision,eps", CASES[:4], ids=[c[0] for c in CASES[:4]])
+def test_full_sort_path_matches_bucket_path(E, name, d, m, C, precision, eps):
+    rng = np.random.default_rng(d * 7 + m)
+    A = rng.standard_normal((m, d)) / math.sqrt(d)
+    b = rng.uniform(0.5, 1.5, m)
+    npdt = np.float32 if precision == 32 else np.float64
+    x = synth.random_states(rng, A, b, C, scale=0.7, margin=1e-3).astype(npdt)
+    nu = rng.standard_normal(x.shape).astype(npdt)
+    u = rng.uniform(size=C)
+    outs = []
+    for full in (False, True):
+        s = E.Sampler(A, b, x, C, seed=5, precision=precision, trim_eps=eps, full_sort=full)
+        outs.append({k: v.cpu().numpy() for k, v in s.transition_explicit(x, nu, u).items()})
+        s.close()
+    a, f = outs
+    assert np.array_equal(a["n_intervals"], f["n_intervals"])
+    assert np.abs(a["intervals"] - f["intervals"]).max() <= 1e-13
+    assert np.abs(a["theta"] - f["theta"]).max() <= 1e-12
+    assert np.array_equal(a["rejected"], f["rejected"])
+    assert np.abs(a["x_new"] - f["x_new"]).max() <= 1e-6
