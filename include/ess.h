@@ -109,6 +109,14 @@ ess_status ess_get_state(ess_ctx* ctx, void* x_out, uint64_t* step_out);
  * (x, s), bit for bit. */
 ess_status ess_set_state(ess_ctx* ctx, const void* x_in, uint64_t step);
 
+/* Gated start (the learned warm start's feasibility gate): every chain whose
+ * candidate row (n_chains x d, T) is strictly feasible, a_i^T x < b_i for all i,
+ * starts there; every other chain starts at its fallback row (n_chains x d, T),
+ * which must be strictly feasible.  accepted (host, nullable, n_chains int32)
+ * receives 1 where the candidate was taken.  Sets the step counter. */
+ess_status ess_set_state_gated(ess_ctx* ctx, const void* x_candidate, const void* x_fallback,
+                               uint64_t step, int32_t* accepted);
+
 /* Per-chain rejection counters since ess_init (host, n_chains int64). */
 ess_status ess_rejections(ess_ctx* ctx, int64_t* per_chain);
 
@@ -149,6 +157,31 @@ ess_status ess_profile(ess_ctx* ctx, int enable);
 ess_status ess_profile_read(ess_ctx* ctx, int kind, double* total_ms, int64_t* count);
 
 void ess_destroy(ess_ctx* ctx);
+
+/* ---- The warm-start network ------------------------------------------------
+ * A fully connected network y = W_L g(... g(W_1 x + c_1) ...) + c_L with the
+ * exact GELU g(z) = z Phi(z) between layers, run on the matrix cores in
+ * bfloat16 with float32 accumulation; float32 master weights, trained with the
+ * mean squared error over all outputs and Adam (Kingma & Ba).  The flat
+ * parameter vector holds W_0 (w1 x w0, row-major), c_0, W_1, c_1, ...
+ * All arrays are device float32 unless marked host. */
+typedef struct ess_mlp ess_mlp;
+ess_status ess_mlp_create(int32_t n_layers, const int32_t* widths /* host, n_layers + 1 */,
+                          void* stream, ess_mlp** out);
+int64_t ess_mlp_num_params(const ess_mlp* net);
+/* Copies parameters in (and resets the Adam moments) or out. */
+ess_status ess_mlp_set_params(ess_mlp* net, const float* params);
+ess_status ess_mlp_get_params(ess_mlp* net, float* params);
+/* out (batch x w_L) = network(in (batch x w_0)). */
+ess_status ess_mlp_forward(ess_mlp* net, const float* in, int32_t batch, float* out);
+/* Forward and backward on one batch; keeps the gradients for ess_mlp_adam.
+ * grads (nullable) receives them in the flat layout; loss (host, nullable) the
+ * mean squared error. */
+ess_status ess_mlp_gradients(ess_mlp* net, const float* in, const float* target, int32_t batch,
+                             float* grads, double* loss);
+/* One Adam step with the gradients of the last ess_mlp_gradients call. */
+ess_status ess_mlp_adam(ess_mlp* net, double lr, double beta1, double beta2, double eps);
+void ess_mlp_destroy(ess_mlp* net);
 
 /* Message for the last failed call on this thread ("" if none). */
 const char* ess_last_error(void);

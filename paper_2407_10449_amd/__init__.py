@@ -60,6 +60,17 @@ _SIGS = {
     "ess_profile": ([_P, ctypes.c_int], ctypes.c_int),
     "ess_profile_read": ([_P, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                           ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "ess_set_state_gated": ([_P, _P, _P, ctypes.c_uint64, _P], ctypes.c_int),
+    "ess_mlp_create": ([ctypes.c_int32, _P, _P, ctypes.POINTER(_P)], ctypes.c_int),
+    "ess_mlp_num_params": ([_P], ctypes.c_int64),
+    "ess_mlp_set_params": ([_P, _P], ctypes.c_int),
+    "ess_mlp_get_params": ([_P, _P], ctypes.c_int),
+    "ess_mlp_forward": ([_P, _P, ctypes.c_int32, _P], ctypes.c_int),
+    "ess_mlp_gradients": ([_P, _P, _P, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_double)],
+                          ctypes.c_int),
+    "ess_mlp_adam": ([_P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double],
+                     ctypes.c_int),
+    "ess_mlp_destroy": ([_P], None),
     "ess_destroy": ([_P], None),
     "ess_last_error": ([], ctypes.c_char_p),
 }
@@ -130,6 +141,52 @@ def ess_get_state(ctx, x_out=None):
 
 def ess_set_state(ctx, x_in, step):
     _check(lib().ess_set_state(ctx, _ptr(x_in), int(step)))
+
+
+def ess_set_state_gated(ctx, x_candidate, x_fallback, step, n_chains):
+    acc = np.zeros(n_chains, dtype=np.int32)
+    _check(lib().ess_set_state_gated(ctx, _ptr(x_candidate), _ptr(x_fallback), int(step),
+                                     acc.ctypes.data_as(ctypes.c_void_p)))
+    return acc
+
+
+def ess_mlp_create(widths, stream=None):
+    w = (ctypes.c_int32 * len(widths))(*widths)
+    net = ctypes.c_void_p()
+    _check(lib().ess_mlp_create(len(widths) - 1, w, _stream_handle(stream), ctypes.byref(net)))
+    return net
+
+
+def ess_mlp_num_params(net):
+    return int(lib().ess_mlp_num_params(net))
+
+
+def ess_mlp_set_params(net, params):
+    _check(lib().ess_mlp_set_params(net, _ptr(params)))
+
+
+def ess_mlp_get_params(net, params):
+    _check(lib().ess_mlp_get_params(net, _ptr(params)))
+
+
+def ess_mlp_forward(net, inp, out):
+    _check(lib().ess_mlp_forward(net, _ptr(inp), int(inp.shape[0]), _ptr(out)))
+
+
+def ess_mlp_gradients(net, inp, target, grads=None, want_loss=True):
+    loss = ctypes.c_double(0.0)
+    _check(lib().ess_mlp_gradients(net, _ptr(inp), _ptr(target), int(inp.shape[0]), _ptr(grads),
+                                   ctypes.byref(loss) if want_loss else None))
+    return loss.value if want_loss else None
+
+
+def ess_mlp_adam(net, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    _check(lib().ess_mlp_adam(net, float(lr), float(beta1), float(beta2), float(eps)))
+
+
+def ess_mlp_destroy(net):
+    if net:
+        lib().ess_mlp_destroy(net)
 
 
 def ess_rejections(ctx, n_chains):
@@ -232,6 +289,12 @@ class Sampler:
     def rejections(self):
         return ess_rejections(self.ctx, self.n_chains)
 
+    def set_state_gated(self, x_candidate, x_fallback, step=0):
+        t = self.torch
+        xc = t.as_tensor(x_candidate).to(self.device, self.dtype).contiguous()
+        xf = t.as_tensor(x_fallback).to(self.device, self.dtype).contiguous()
+        return ess_set_state_gated(self.ctx, xc, xf, step, self.n_chains)
+
     def draw(self, step):
         nu = self._empty(self.n_chains, self.d)
         u = self._empty(self.n_chains, dtype=self.torch.float64)
@@ -326,6 +389,83 @@ class BatchedSampler:
         if getattr(self, "ctx", None):
             ess_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Mlp:
+    """The warm-start network (bfloat16 matrix-core kernels, float32 masters)."""
+
+    def __init__(self, widths, params=None, seed=0, device="cuda", stream=None):
+        import torch
+        self.torch = torch
+        self.widths = list(widths)
+        self.device = torch.device(device)
+        self.net = ess_mlp_create(self.widths, stream)
+        self.n_params = ess_mlp_num_params(self.net)
+        if params is None:
+            params = self.init_params(seed)
+        self.set_params(params)
+
+    def init_params(self, seed):
+        """Glorot-uniform weights, zero biases (host numpy, seeded)."""
+        rng = np.random.default_rng(seed)
+        parts = []
+        for i, o in zip(self.widths[:-1], self.widths[1:]):
+            lim = np.sqrt(6.0 / (i + o))
+            parts += [rng.uniform(-lim, lim, size=o * i), np.zeros(o)]
+        return np.concatenate(parts).astype(np.float32)
+
+    def unflatten(self, flat):
+        """flat -> [(W (out, in), c (out,))] (numpy)."""
+        flat = np.asarray(flat)
+        out, off = [], 0
+        for i, o in zip(self.widths[:-1], self.widths[1:]):
+            W = flat[off:off + o * i].reshape(o, i)
+            off += o * i
+            c = flat[off:off + o]
+            off += o
+            out.append((W, c))
+        return out
+
+    def set_params(self, flat):
+        t = self.torch
+        p = t.as_tensor(np.asarray(flat, dtype=np.float32)).to(self.device).contiguous()
+        ess_mlp_set_params(self.net, p)
+
+    def params(self):
+        p = self.torch.empty(self.n_params, device=self.device, dtype=self.torch.float32)
+        ess_mlp_get_params(self.net, p)
+        return p
+
+    def forward(self, inp):
+        t = self.torch
+        inp = t.as_tensor(inp).to(self.device, t.float32).contiguous()
+        out = t.empty(inp.shape[0], self.widths[-1], device=self.device, dtype=t.float32)
+        ess_mlp_forward(self.net, inp, out)
+        return out
+
+    def gradients(self, inp, target):
+        t = self.torch
+        inp = t.as_tensor(inp).to(self.device, t.float32).contiguous()
+        target = t.as_tensor(target).to(self.device, t.float32).contiguous()
+        g = t.empty(self.n_params, device=self.device, dtype=t.float32)
+        loss = ess_mlp_gradients(self.net, inp, target, g)
+        return g, loss
+
+    def train_step(self, inp, target, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        loss = ess_mlp_gradients(self.net, inp, target, None, want_loss=False)
+        ess_mlp_adam(self.net, lr, beta1, beta2, eps)
+        return loss
+
+    def close(self):
+        if getattr(self, "net", None):
+            ess_mlp_destroy(self.net)
+            self.net = None
 
     def __del__(self):
         try:

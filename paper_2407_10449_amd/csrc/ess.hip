@@ -15,6 +15,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <cmath>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -24,6 +25,7 @@
 #include "philox.hpp"
 #include "sample.hpp"
 #include "batched.hpp"
+#include "mlp.hpp"
 
 using namespace ess;
 
@@ -94,6 +96,7 @@ struct ess_ctx {
     long long* rej = nullptr;
     int* fb_list = nullptr;    // chains handed to the full-sort path
     int* fb_count = nullptr;   // [2 per group]: list lengths by step parity
+    int* accepted = nullptr;   // [Cp]: gated starts taken
     uint64_t step = 0;
     int bm = 128, bn = 128, group_m = 4;
     int nmax = 512;
@@ -702,6 +705,207 @@ ess_status batched_copy_state(const ess_ctx* c, const float* src, float* dst, in
     return ESS_OK;
 }
 
+// ---------------------------------------------------------------- network
+}  // namespace
+
+struct ess_mlp {
+    int L = 0;                      // layers
+    std::vector<int> w;             // widths, L + 1
+    std::vector<long long> w_off, c_off;   // offsets of W_l and c_l in the flat vector
+    long long n_params = 0, n_weights = 0;
+    hipStream_t st = nullptr;
+    float* params = nullptr;        // flat: W_0, c_0, W_1, c_1, ...
+    float* grads = nullptr;
+    float* m = nullptr;
+    float* v = nullptr;
+    uint16_t* wb = nullptr;         // bfloat16 copies of the weights (same offsets minus biases)
+    std::vector<long long> wb_off;
+    long long adam_t = 0;
+    int cap = 0;                    // batch capacity of the activation buffers
+    uint16_t* xin = nullptr;        // [cap][w0]
+    std::vector<float*> z;          // hidden pre-activations [cap][w_{l+1}]
+    std::vector<uint16_t*> h;       // hidden activations, bfloat16
+    float* y = nullptr;             // [cap][wL]
+    float* dzf = nullptr;           // [cap][max width]
+    uint16_t* dzb = nullptr;
+    float* dzf2 = nullptr;
+    uint16_t* dzb2 = nullptr;
+    double* partial = nullptr;      // [256]
+    std::vector<void*> allocs;
+};
+
+namespace {
+
+ess_status mlp_alloc(ess_mlp* n, void** p, size_t bytes) {
+    HIP_TRY(hipMalloc(p, bytes));
+    n->allocs.push_back(*p);
+    HIP_TRY(hipMemsetAsync(*p, 0, bytes, n->st));
+    return ESS_OK;
+}
+
+ess_status mlp_reserve(ess_mlp* n, int batch) {
+    if (batch <= n->cap) return ESS_OK;
+    if (n->cap > 0) HIP_TRY(hipStreamSynchronize(n->st));   // old buffers may still be in use
+    auto drop = [&](void* q) {
+        if (!q) return;
+        (void)hipFree(q);
+        n->allocs.erase(std::remove(n->allocs.begin(), n->allocs.end(), q), n->allocs.end());
+    };
+    drop(n->xin); drop(n->y); drop(n->dzf); drop(n->dzb); drop(n->dzf2); drop(n->dzb2);
+    for (auto* q : n->z) drop(q);
+    for (auto* q : n->h) drop(q);
+    n->z.assign(n->L - 1, nullptr);
+    n->h.assign(n->L - 1, nullptr);
+    const int wmax = *std::max_element(n->w.begin(), n->w.end());
+    ESS_TRY(mlp_alloc(n, reinterpret_cast<void**>(&n->xin), sizeof(uint16_t) * batch * n->w[0]));
+    for (int l = 0; l + 1 < n->L; ++l) {
+        ESS_TRY(mlp_alloc(n, reinterpret_cast<void**>(&n->z[l]), sizeof(float) * batch * n->w[l + 1]));
+        ESS_TRY(mlp_alloc(n, reinterpret_cast<void**>(&n->h[l]), sizeof(uint16_t) * batch * n->w[l + 1]));
+    }
+    ESS_TRY(mlp_alloc(n, reinterpret_cast<void**>(&n->y), sizeof(float) * batch * n->w[n->L]));
+    ESS_TRY(mlp_alloc(n, reinterpret_cast<void**>(&n->dzf), sizeof(float) * batch * wmax));
+    ESS_TRY(mlp_alloc(n, reinterpret_cast<void**>(&n->dzb), sizeof(uint16_t) * batch * wmax));
+    ESS_TRY(mlp_alloc(n, reinterpret_cast<void**>(&n->dzf2), sizeof(float) * batch * wmax));
+    ESS_TRY(mlp_alloc(n, reinterpret_cast<void**>(&n->dzb2), sizeof(uint16_t) * batch * wmax));
+    n->cap = batch;
+    return ESS_OK;
+}
+
+ess_status mlp_gemm(const ess_mlp* n, const MlpGemm& g) {
+    const int tiles = ((g.M + 63) / 64) * ((g.N + 63) / 64);
+    hipLaunchKernelGGL(mlp_gemm_kernel, dim3(tiles), dim3(256), 0, n->st, g);
+    HIP_TRY(hipGetLastError());
+    return ESS_OK;
+}
+
+ess_status mlp_refresh_bf16(const ess_mlp* n) {
+    for (int l = 0; l < n->L; ++l) {
+        const long long cnt = static_cast<long long>(n->w[l + 1]) * n->w[l];
+        hipLaunchKernelGGL(to_bf16_kernel, dim3(std::min<long long>((cnt + 255) / 256, 1024)),
+                           dim3(256), 0, n->st, n->params + n->w_off[l], n->wb + n->wb_off[l], cnt);
+    }
+    HIP_TRY(hipGetLastError());
+    return ESS_OK;
+}
+
+ess_status mlp_forward(ess_mlp* n, const float* in, int B) {
+    ESS_TRY(mlp_reserve(n, B));
+    const long long cnt = static_cast<long long>(B) * n->w[0];
+    hipLaunchKernelGGL(to_bf16_kernel, dim3(std::min<long long>((cnt + 255) / 256, 1024)), dim3(256),
+                       0, n->st, in, n->xin, cnt);
+    HIP_TRY(hipGetLastError());
+    const uint16_t* hprev = n->xin;
+    for (int l = 0; l < n->L; ++l) {
+        const int din = n->w[l], dout = n->w[l + 1];
+        MlpGemm g{};
+        g.M = B;
+        g.N = dout;
+        g.K = din;
+        g.A = hprev;
+        g.sa0 = din;
+        g.sa1 = 1;
+        g.B = n->wb + n->wb_off[l];   // B(k, j) = W_l[j][k]
+        g.sb0 = 1;
+        g.sb1 = din;
+        g.bias = n->params + n->c_off[l];
+        g.ldo = dout;
+        if (l + 1 < n->L) {
+            g.mode = EPI_HIDDEN;
+            g.out_f = n->z[l];
+            g.out_b = n->h[l];
+            hprev = n->h[l];
+        } else {
+            g.mode = EPI_OUTPUT;
+            g.out_f = n->y;
+        }
+        ESS_TRY(mlp_gemm(n, g));
+    }
+    return ESS_OK;
+}
+
+ess_status mlp_backward(ess_mlp* n, const float* target, int B, double* loss) {
+    const int L = n->L, dout = n->w[L];
+    const long long cnt = static_cast<long long>(B) * dout;
+    const int nb = static_cast<int>(std::min<long long>((cnt + 255) / 256, 256));
+    hipLaunchKernelGGL(mse_grad_kernel, dim3(nb), dim3(256), 0, n->st, n->y, target, cnt, n->dzf,
+                       n->dzb, n->partial);
+    HIP_TRY(hipGetLastError());
+    float* dzf = n->dzf;
+    uint16_t* dzb = n->dzb;
+    float* dzf_next = n->dzf2;
+    uint16_t* dzb_next = n->dzb2;
+    for (int l = L - 1; l >= 0; --l) {
+        const int din = n->w[l], dw = n->w[l + 1];
+        const uint16_t* hin = l > 0 ? n->h[l - 1] : n->xin;
+        MlpGemm g{};   // dW_l[i][j] = sum_b dZ[b][i] H[b][j]
+        g.M = dw;
+        g.N = din;
+        g.K = B;
+        g.A = dzb;
+        g.sa0 = 1;
+        g.sa1 = dw;
+        g.B = hin;
+        g.sb0 = din;
+        g.sb1 = 1;
+        g.mode = EPI_STORE;
+        g.out_f = n->grads + n->w_off[l];
+        g.ldo = din;
+        ESS_TRY(mlp_gemm(n, g));
+        hipLaunchKernelGGL(colsum_kernel, dim3((dw + 255) / 256), dim3(256), 0, n->st, dzf, B, dw, dw,
+                           n->grads + n->c_off[l]);
+        HIP_TRY(hipGetLastError());
+        if (l > 0) {
+            MlpGemm d{};   // dZ_{l-1} = (dZ_l W_l) * gelu'(Z_{l-1})
+            d.M = B;
+            d.N = din;
+            d.K = dw;
+            d.A = dzb;
+            d.sa0 = dw;
+            d.sa1 = 1;
+            d.B = n->wb + n->wb_off[l];   // B(k, j) = W_l[k][j]
+            d.sb0 = din;
+            d.sb1 = 1;
+            d.mode = EPI_DGELU;
+            d.zin = n->z[l - 1];
+            d.out_f = dzf_next;
+            d.out_b = dzb_next;
+            d.ldo = din;
+            ESS_TRY(mlp_gemm(n, d));
+            std::swap(dzf, dzf_next);
+            std::swap(dzb, dzb_next);
+        }
+    }
+    if (loss) {
+        std::vector<double> part(nb);
+        HIP_TRY(hipMemcpyAsync(part.data(), n->partial, sizeof(double) * nb, hipMemcpyDeviceToHost, n->st));
+        HIP_TRY(hipStreamSynchronize(n->st));
+        double s = 0.0;
+        for (double v : part) s += v;
+        *loss = s / static_cast<double>(cnt);
+    }
+    return ESS_OK;
+}
+
+// Start states for every chain: the candidate row where it is strictly
+// feasible, the fallback row elsewhere.
+__global__ __launch_bounds__(256) void gate_rows_kernel(const int* __restrict__ flag,
+                                                        const void* fallback, void* X, int d, int dp,
+                                                        int esz, int* accepted) {
+    const int c = blockIdx.x;
+    const int bad = flag[c];
+    if (threadIdx.x == 0) accepted[c] = !bad;
+    if (!bad) return;
+    if (esz == 4) {
+        const float* src = static_cast<const float*>(fallback) + static_cast<size_t>(c) * d;
+        float* dst = static_cast<float*>(X) + static_cast<size_t>(c) * dp;
+        for (int k = threadIdx.x; k < d; k += 256) dst[k] = src[k];
+    } else {
+        const double* src = static_cast<const double*>(fallback) + static_cast<size_t>(c) * d;
+        double* dst = static_cast<double*>(X) + static_cast<size_t>(c) * dp;
+        for (int k = threadIdx.x; k < d; k += 256) dst[k] = src[k];
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -772,6 +976,7 @@ ess_status ess_init(const ess_problem* pr, void* stream, ess_ctx** out) {
         (s = dalloc(c, reinterpret_cast<void**>(&c->flag), sizeof(int) * c->Cp)) != ESS_OK ||
         (s = dalloc(c, reinterpret_cast<void**>(&c->rej), sizeof(long long) * c->Cp)) != ESS_OK ||
         (s = dalloc(c, reinterpret_cast<void**>(&c->fb_list), sizeof(int) * c->Cp)) != ESS_OK ||
+        (s = dalloc(c, reinterpret_cast<void**>(&c->accepted), sizeof(int) * c->Cp)) != ESS_OK ||
         (s = dalloc(c, reinterpret_cast<void**>(&c->fb_count), sizeof(int) * 2 * kMaxGroups)) != ESS_OK)
         return bail(s);
     if (c->G > 1) {
@@ -1008,6 +1213,129 @@ ess_status ess_draw(ess_ctx* c, uint64_t step, void* nu, double* u) {
     if (c->batch) return fail(ESS_ERR_UNSUPPORTED, "ess_draw takes single-problem contexts");
     if (step >= (1ull << 32)) return fail(ESS_ERR_UNSUPPORTED, "the step counter is limited to 2^32");
     return launch_draw(c, 0, c->C, c->st, step, nu, c->d, u);
+}
+
+
+ess_status ess_set_state_gated(ess_ctx* c, const void* x_candidate, const void* x_fallback,
+                               uint64_t step, int32_t* accepted) {
+    g_err.clear();
+    ESS_TRY(check_ctx(c));
+    if (c->batch) return fail(ESS_ERR_UNSUPPORTED, "gated starts take single-problem contexts");
+    if (!x_candidate || !x_fallback) return fail(ESS_ERR_INVALID_ARG, "null candidate or fallback");
+    if (step >= (1ull << 32)) return fail(ESS_ERR_UNSUPPORTED, "the step counter is limited to 2^32");
+    ESS_TRY(copy_rows_in(c, c->X, x_candidate));
+    HIP_TRY(hipMemsetAsync(c->flag, 0, sizeof(int) * c->Cp, c->st));
+    ESS_TRY(launch_proj(c, c->whole(), c->st, c->X, COLS_X, 1, 1));   // strict check
+    hipLaunchKernelGGL(gate_rows_kernel, dim3(c->C), dim3(256), 0, c->st, c->flag, x_fallback, c->X,
+                       c->d, c->dp, c->esz, c->accepted);
+    HIP_TRY(hipGetLastError());
+    std::vector<int> acc(c->C);
+    HIP_TRY(hipMemcpyAsync(acc.data(), c->accepted, sizeof(int) * c->C, hipMemcpyDeviceToHost, c->st));
+    ESS_TRY(set_state_from_X(c, "ess_set_state_gated (fallback rows)"));
+    if (accepted)
+        for (int i = 0; i < c->C; ++i) accepted[i] = acc[i];
+    c->step = step;
+    return ESS_OK;
+}
+
+ess_status ess_mlp_create(int32_t n_layers, const int32_t* widths, void* stream, ess_mlp** out) {
+    g_err.clear();
+    if (!out || !widths || n_layers < 1 || n_layers > 16)
+        return fail(ESS_ERR_INVALID_ARG, "need 1..16 layers, widths and an output pointer");
+    *out = nullptr;
+    for (int l = 0; l <= n_layers; ++l)
+        if (widths[l] < 1 || widths[l] > 65536)
+            return fail(ESS_ERR_INVALID_ARG, "width %d out of range", widths[l]);
+    ess_mlp* n = new ess_mlp();
+    n->L = n_layers;
+    n->w.assign(widths, widths + n_layers + 1);
+    n->st = static_cast<hipStream_t>(stream);
+    long long off = 0, woff = 0;
+    for (int l = 0; l < n_layers; ++l) {
+        n->w_off.push_back(off);
+        n->wb_off.push_back(woff);
+        off += static_cast<long long>(n->w[l + 1]) * n->w[l];
+        woff += static_cast<long long>(n->w[l + 1]) * n->w[l];
+        n->c_off.push_back(off);
+        off += n->w[l + 1];
+    }
+    n->n_params = off;
+    n->n_weights = woff;
+    ess_status s;
+    if ((s = mlp_alloc(n, reinterpret_cast<void**>(&n->params), sizeof(float) * off)) != ESS_OK ||
+        (s = mlp_alloc(n, reinterpret_cast<void**>(&n->grads), sizeof(float) * off)) != ESS_OK ||
+        (s = mlp_alloc(n, reinterpret_cast<void**>(&n->m), sizeof(float) * off)) != ESS_OK ||
+        (s = mlp_alloc(n, reinterpret_cast<void**>(&n->v), sizeof(float) * off)) != ESS_OK ||
+        (s = mlp_alloc(n, reinterpret_cast<void**>(&n->wb), sizeof(uint16_t) * woff)) != ESS_OK ||
+        (s = mlp_alloc(n, reinterpret_cast<void**>(&n->partial), sizeof(double) * 256)) != ESS_OK) {
+        std::string keep = g_err;
+        ess_mlp_destroy(n);
+        g_err = keep;
+        return s;
+    }
+    *out = n;
+    return ESS_OK;
+}
+
+int64_t ess_mlp_num_params(const ess_mlp* n) { return n ? n->n_params : 0; }
+
+ess_status ess_mlp_set_params(ess_mlp* n, const float* params) {
+    g_err.clear();
+    if (!n || !params) return fail(ESS_ERR_INVALID_ARG, "null network or parameters");
+    HIP_TRY(hipMemcpyAsync(n->params, params, sizeof(float) * n->n_params, hipMemcpyDefault, n->st));
+    HIP_TRY(hipMemsetAsync(n->m, 0, sizeof(float) * n->n_params, n->st));
+    HIP_TRY(hipMemsetAsync(n->v, 0, sizeof(float) * n->n_params, n->st));
+    n->adam_t = 0;
+    return mlp_refresh_bf16(n);
+}
+
+ess_status ess_mlp_get_params(ess_mlp* n, float* params) {
+    g_err.clear();
+    if (!n || !params) return fail(ESS_ERR_INVALID_ARG, "null network or parameters");
+    HIP_TRY(hipMemcpyAsync(params, n->params, sizeof(float) * n->n_params, hipMemcpyDefault, n->st));
+    return ESS_OK;
+}
+
+ess_status ess_mlp_forward(ess_mlp* n, const float* in, int32_t batch, float* out) {
+    g_err.clear();
+    if (!n || !in || !out || batch < 1) return fail(ESS_ERR_INVALID_ARG, "bad forward arguments");
+    ESS_TRY(mlp_forward(n, in, batch));
+    HIP_TRY(hipMemcpyAsync(out, n->y, sizeof(float) * batch * n->w[n->L], hipMemcpyDefault, n->st));
+    return ESS_OK;
+}
+
+ess_status ess_mlp_gradients(ess_mlp* n, const float* in, const float* target, int32_t batch,
+                             float* grads, double* loss) {
+    g_err.clear();
+    if (!n || !in || !target || batch < 1) return fail(ESS_ERR_INVALID_ARG, "bad gradient arguments");
+    ESS_TRY(mlp_forward(n, in, batch));
+    ESS_TRY(mlp_backward(n, target, batch, loss));
+    if (grads)
+        HIP_TRY(hipMemcpyAsync(grads, n->grads, sizeof(float) * n->n_params, hipMemcpyDefault, n->st));
+    return ESS_OK;
+}
+
+ess_status ess_mlp_adam(ess_mlp* n, double lr, double beta1, double beta2, double eps) {
+    g_err.clear();
+    if (!n || !(lr > 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps >= 0))
+        return fail(ESS_ERR_INVALID_ARG, "bad Adam settings");
+    n->adam_t += 1;
+    const double c1 = 1.0 / (1.0 - std::pow(beta1, static_cast<double>(n->adam_t)));
+    const double c2 = 1.0 / (1.0 - std::pow(beta2, static_cast<double>(n->adam_t)));
+    hipLaunchKernelGGL(adam_kernel, dim3(std::min<long long>((n->n_params + 255) / 256, 2048)),
+                       dim3(256), 0, n->st, n->params, n->grads, n->m, n->v, n->n_params,
+                       static_cast<float>(lr), static_cast<float>(beta1), static_cast<float>(beta2),
+                       static_cast<float>(eps), static_cast<float>(c1), static_cast<float>(c2));
+    HIP_TRY(hipGetLastError());
+    return mlp_refresh_bf16(n);
+}
+
+void ess_mlp_destroy(ess_mlp* n) {
+    if (!n) return;
+    if (n->st) (void)hipStreamSynchronize(n->st);
+    else (void)hipDeviceSynchronize();
+    for (void* p : n->allocs) (void)hipFree(p);
+    delete n;
 }
 
 }  // extern "C"
