@@ -79,6 +79,124 @@ def cpu_baseline(pr, seconds, n_chains=64):
                       f"({dt:.1f} s, float64 numpy oracle)"}
 
 
+def bench_batched(E, torch, steps=50, plain_steps=10):
+    """256 uneven polytopes x 64 chains: one persistent launch per step, against
+    one context per problem run one after another."""
+    import synth
+    probs = synth.batched_uneven()
+    spec = [dict(A=p.A, b=p.b, x0=p.x0, n_chains=p.n_chains, seed=i, trim_eps=1e-6)
+            for i, p in enumerate(probs)]
+    C = sum(p.n_chains for p in probs)
+    s = E.BatchedSampler(spec)
+    E.ess_run(s.ctx, 5, 1, None, False)
+    torch.cuda.synchronize()
+    E.ess_profile(s.ctx, True)
+    t0 = time.perf_counter()
+    E.ess_run(s.ctx, steps, 1, None, False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    k_ms, k_n = E.ess_profile_read(s.ctx, E.ESS_KERNEL_BATCHED)
+    s.close()
+    singles = [E.Sampler(p.A, p.b, p.x0, p.n_chains, seed=i, precision=32)
+               for i, p in enumerate(probs)]
+    for q in singles:
+        E.ess_run(q.ctx, 2, 1, None, False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for q in singles:
+        E.ess_run(q.ctx, plain_steps, 1, None, False)
+    torch.cuda.synchronize()
+    dt1 = time.perf_counter() - t1
+    for q in singles:
+        q.close()
+    flops = sum(4.0 * p.m * p.d * p.n_chains for p in probs)
+    return {"workload": "batched_uneven: 256 polytopes, d log-uniform [16,512], m = d U{1..4}, 64 chains each",
+            "chain_steps_per_s": C * steps / dt,
+            "ms_per_step": dt * 1e3 / steps,
+            "persistent_step_ms": k_ms / max(k_n, 1),
+            "projection_tflops_in_step": flops / (k_ms / max(k_n, 1) / 1e3) / 1e12 if k_n else None,
+            "per_problem_chain_steps_per_s": C * plain_steps / dt1,
+            "speedup_vs_per_problem": (C * steps / dt) / (C * plain_steps / dt1)}
+
+
+def bench_warm_start(E, torch, log):
+    """ESS/s: batched (one context over all problems of the family) with the
+    learned warm start, against plain per-problem contexts started at 0."""
+    import numpy as np
+    import synth
+    from paper_2407_10449_amd import diagnostics as D
+    from paper_2407_10449_amd import warmstart as W
+    A, b0, draw = synth.warm_family()
+    m, d = A.shape
+    rng = np.random.default_rng(21)
+    train_b, eval_b = draw(rng, 10000), draw(rng, 32)
+    X, Y, t_gen = W.generate_pairs(E, A, train_b, chains_per_b=1, burn=200, n_keep=10, thin=10)
+    net = E.Mlp((m, 512, 512, d), seed=0)
+    hist, t_train = W.train(net, X, Y, epochs=10, batch=1024, lr=1e-3)
+    ref_mean, ref_sd = W.reference_moments(E, A, eval_b, chains=64, burn=300, steps=1200, thin=4)
+    chains, T = 64, 120
+    mon = np.random.default_rng(0).choice(d, 64, replace=False)
+
+    def ess_total(tr, burn):
+        x = tr[burn:]
+        tot, worst = 0.0, 1e30
+        for j in range(len(eval_b)):
+            xj = x[:, j * chains:(j + 1) * chains, :]
+            e = D.min_ess(xj, mon)
+            tot += e
+            worst = min(worst, e)
+        return tot, worst
+
+    # plain per-problem: one context per b, x0 = 0
+    ctxs = [E.Sampler(A, b, np.zeros(d), chains, seed=100 + j, precision=32)
+            for j, b in enumerate(eval_b)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    trs = [q.run(T, count_rejections=False)[0] for q in ctxs]
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    plain_tr = torch.cat(trs, dim=1).double().cpu().numpy()
+    for q in ctxs:
+        q.close()
+    # batched + warm start: one context with a b per chain, gated network start
+    B = np.repeat(eval_b, chains, axis=0)
+    s = E.Sampler(A, B, np.zeros(d), B.shape[0], seed=7, precision=32)
+    bdev = torch.tensor(eval_b, dtype=torch.float32, device="cuda")
+    zeros = torch.zeros(B.shape[0], d, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xhat = net.forward(bdev).repeat_interleave(chains, dim=0)
+    acc = s.set_state_gated(xhat, zeros)
+    warm_tr_t, _ = s.run(T, count_rejections=False)
+    torch.cuda.synchronize()
+    t_warm = time.perf_counter() - t0
+    warm_tr = warm_tr_t.double().cpu().numpy()
+    s.close()
+    net.close()
+    x0w = (xhat.cpu().numpy() * acc[:, None])[None]
+    cp = W.burn_in_curve(np.concatenate([np.zeros((1, B.shape[0], d)), plain_tr]), 32, chains,
+                         ref_mean, ref_sd)
+    cw = W.burn_in_curve(np.concatenate([x0w, warm_tr]), 32, chains, ref_mean, ref_sd)
+    bp, bw = max(W.burn_in_steps(cp), 1), max(W.burn_in_steps(cw), 1)
+    ess_p, worst_p = ess_total(plain_tr, bp)
+    ess_w, worst_w = ess_total(warm_tr, bw)
+    # accuracy: posterior means after burn-in against the long reference
+    def max_z(tr, burn):
+        x = tr[burn:].reshape(tr.shape[0] - burn, 32, chains, d).mean(axis=(0, 2))
+        return float(np.abs(x - ref_mean).max() / (ref_sd.mean() / np.sqrt(chains * (tr.shape[0] - burn))) )
+    out = {"workload": "warm_family d=256 m=768, 32 held-out b x 64 chains, 120 steps",
+           "train_pairs": int(X.shape[0]), "train_gen_s": t_gen, "train_s": t_train,
+           "train_mse_first_last": [hist[0], hist[-1]],
+           "gate_accepted": float(acc.mean()),
+           "burn_in_steps": {"plain": bp, "warm": bw},
+           "plain_per_problem": {"ess": ess_p, "min_ess": worst_p, "wall_s": t_plain, "ess_per_s": ess_p / t_plain},
+           "batched_warm": {"ess": ess_w, "min_ess": worst_w, "wall_s": t_warm, "ess_per_s": ess_w / t_warm},
+           "ess_per_s_ratio": (ess_w / t_warm) / (ess_p / t_plain),
+           "accuracy_max_z_vs_reference": {"plain": max_z(plain_tr, bp), "warm": max_z(warm_tr, bw)}}
+    log(f"warm start: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +204,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched and warm-start measurements")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -151,6 +271,10 @@ def main():
                                 "other_total": other_ms},
         "rejections": rej,
     }
+    if not args.no_extras:
+        log = lambda msg: print(msg, file=sys.stderr, flush=True)
+        out["batched"] = bench_batched(E, torch)
+        out["warm_start"] = bench_warm_start(E, torch, log)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pr, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -49,6 +49,8 @@ typedef enum {
 #define ESS_X0_BROADCAST 1u   /* x0 holds one d-vector used by every chain */
 #define ESS_PER_CHAIN_B 4u    /* b holds n_chains x m values: chain c samples the
                                  polytope {A x <= b_c} (a family sharing A) */
+#define ESS_EAGER 8u          /* ess_run launches kernel by kernel instead of
+                                 replaying a captured HIP graph */
 #define ESS_SORT_FULL 2u      /* build every chain's active intervals with a full
                                  sort of all crossing rows instead of the bucketed
                                  sort (same intervals; for comparison) */
@@ -94,7 +96,12 @@ ess_status ess_init_batched(const ess_problem* problems, int32_t n_problems, voi
  * T, receives the state after the step. */
 ess_status ess_step(ess_ctx* ctx, void* x_out);
 
-/* n_steps transitions.  Every thin-th state is written to trace (nullable):
+/* n_steps transitions.  The first call with a given (n_steps, thin, trace)
+ * captures the launches into a HIP graph; later calls with the same shape
+ * replay it (unless ESS_EAGER or profiling is on).  A trace buffer that is
+ * freed and reallocated at the same address is fine; the graph only stores
+ * the pointer.
+ * Every thin-th state is written to trace (nullable):
  * (n_steps / thin) x n_chains x d, T.  n_rejected (host, nullable) receives the
  * number of proposals rejected by the safeguard during this call (summed over
  * chains; a zero-length active set counts as a rejection). */
@@ -141,6 +148,17 @@ ess_status ess_transition_explicit(ess_ctx* ctx, const void* x, const void* nu,
 /* The random numbers step `step` uses: nu (n_chains x d, T, nullable) and the
  * theta uniforms u (n_chains double, nullable).  Does not change the context. */
 ess_status ess_draw(ess_ctx* ctx, uint64_t step, void* nu, double* u);
+
+/* Autotuner.  Times each candidate configuration on this context for
+ * 2 x steps_per_trial steps (single problem: chain groups x projection tile
+ * shape x XCD band height; batched: persistent grid size), keeps the fastest,
+ * and stores it in a JSON cache keyed by GPU architecture and problem shape
+ * ($ESS_TUNE_CACHE, default ~/.cache/ess_tune.json), which later contexts of
+ * the same shape load at init.  The chains' state and step counter are
+ * restored afterwards.  report (host, nullable) receives one line per trial.
+ * Currently offered for batched contexts only; a single-problem context returns
+ * ESS_ERR_UNSUPPORTED. */
+ess_status ess_autotune(ess_ctx* ctx, int32_t steps_per_trial, char* report, int32_t report_len);
 
 /* Kernel timing for measurement.  While enabled, every launch made by ess_run
  * is bracketed by a pair of HIP events on the context's stream; ess_profile_read

@@ -25,6 +25,7 @@ ESS_ERR_UNSUPPORTED = 5
 ESS_X0_BROADCAST = 1
 ESS_SORT_FULL = 2
 ESS_PER_CHAIN_B = 4
+ESS_EAGER = 8
 
 STATUS_NAMES = {0: "ESS_OK", 1: "ESS_ERR_INVALID_ARG", 2: "ESS_ERR_INFEASIBLE_START",
                 3: "ESS_ERR_HIP", 4: "ESS_ERR_OOM", 5: "ESS_ERR_UNSUPPORTED"}
@@ -71,6 +72,7 @@ _SIGS = {
     "ess_mlp_adam": ([_P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double],
                      ctypes.c_int),
     "ess_mlp_destroy": ([_P], None),
+    "ess_autotune": ([_P, ctypes.c_int32, ctypes.c_char_p, ctypes.c_int32], ctypes.c_int),
     "ess_destroy": ([_P], None),
     "ess_last_error": ([], ctypes.c_char_p),
 }
@@ -224,6 +226,13 @@ def ess_profile_read(ctx, kind):
     return ms.value, n.value
 
 
+def ess_autotune(ctx, steps_per_trial=8):
+    """Tunes the context in place; returns the per-trial report."""
+    buf = ctypes.create_string_buffer(8192)
+    _check(lib().ess_autotune(ctx, int(steps_per_trial), buf, len(buf)))
+    return buf.value.decode()
+
+
 def ess_destroy(ctx):
     if ctx:
         lib().ess_destroy(ctx)
@@ -239,7 +248,7 @@ class Sampler:
     are copied to the device in the working precision before ess_init."""
 
     def __init__(self, A, b, x0, n_chains, seed=0, precision=32, trim_eps=None,
-                 device="cuda", stream=None, full_sort=False):
+                 device="cuda", stream=None, full_sort=False, eager=False):
         import torch
         self.torch = torch
         self.dtype = torch.float32 if precision == 32 else torch.float64
@@ -257,6 +266,8 @@ class Sampler:
         flags = (ESS_X0_BROADCAST if x0.dim() == 1 else 0) | (ESS_SORT_FULL if full_sort else 0)
         if self.b.dim() == 2:       # one right-hand side per chain
             flags |= ESS_PER_CHAIN_B
+        if eager:
+            flags |= ESS_EAGER
         if trim_eps is None:
             trim_eps = 1e-6 if precision == 32 else 0.0
         self.trim_eps = float(trim_eps)

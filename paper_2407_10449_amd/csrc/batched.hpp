@@ -55,7 +55,8 @@ struct BatchArgs {
     int* fb_list;          // [total chains]: global chain-table indices
     int* fb_count;         // [2]
     int* error;            // [1]: set when a wait exceeds its spin limit
-    uint32_t step;
+    uint32_t step;         // relative to *step_base
+    const uint32_t* step_base;   // nullable device counter
     int has_pending;       // commit the previous proposals
     int do_sample;         // chain items also sample (0: commit only)
     int gen_next;
@@ -63,6 +64,10 @@ struct BatchArgs {
     int p_direct, strict;  // projection epilogue mode
     float* trace;          // nullable: committed states of the previous step
 };
+
+__device__ __forceinline__ uint32_t abs_step(const BatchArgs& a) {
+    return a.step + (a.step_base ? *a.step_base : 0u);
+}
 
 __device__ __forceinline__ ProjOut batch_proj_out(const BatchArgs& a, const ProbDesc& pd) {
     ProjOut o;
@@ -90,7 +95,7 @@ __device__ __forceinline__ ChainRef<float> batch_ref(const BatchArgs& a, const P
     r.m = pd.m;
     r.chain = static_cast<uint32_t>(c);
     r.problem = static_cast<uint32_t>(p);
-    r.step = a.step;
+    r.step = abs_step(a);
     r.gen_next = a.gen_next;
     r.eps = pd.eps;
     r.seed = pd.seed;
@@ -138,7 +143,7 @@ __global__ __launch_bounds__(256) void batched_step_kernel(BatchArgs a) {
     __shared__ __attribute__((aligned(16))) BatchLds<NB> lds;
     __shared__ int s_item;
     const int tid = threadIdx.x;
-    const int par = static_cast<int>(a.step & 1u);
+    const int par = static_cast<int>(abs_step(a) & 1u);
     const int total = a.NT + a.NC;
     for (;;) {
         if (tid == 0) s_item = atomicAdd(a.queue + par, 1);
@@ -189,7 +194,7 @@ __global__ __launch_bounds__(256) void batched_step_kernel(BatchArgs a) {
 template <int NMAX>
 __global__ __launch_bounds__(256) void batched_fallback_kernel(BatchArgs a) {
     ESS_FULL_LDS(NMAX)
-    const int par = static_cast<int>(a.step & 1u);
+    const int par = static_cast<int>(abs_step(a) & 1u);
     const int count = a.fb_count[par];
     for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
         const int2 ch = a.chains[a.fb_list[idx]];
@@ -213,7 +218,7 @@ __global__ __launch_bounds__(256) void batched_draw_kernel(BatchArgs a) {
     float* nu = a.N + pd.x_off + static_cast<size_t>(ch.y) * pd.dp;
     for (int j = threadIdx.x; 2 * j < pd.d; j += 256) {
         double z0, z1;
-        rng.normal_pair(j, ch.y, a.step, ch.x, z0, z1);
+        rng.normal_pair(j, ch.y, abs_step(a), ch.x, z0, z1);
         nu[2 * j] = static_cast<float>(z0);
         if (2 * j + 1 < pd.d) nu[2 * j + 1] = static_cast<float>(z1);
     }

@@ -8,6 +8,7 @@
 //                  A nu for the next step, in one launch over 2 Cp columns
 // so a run of T steps is 2 T + 3 launches.
 #include <hip/hip_runtime.h>
+#include <sys/stat.h>
 
 #include <algorithm>
 #include <memory>
@@ -15,6 +16,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <fstream>
+#include <sstream>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -97,7 +100,18 @@ struct ess_ctx {
     int* fb_list = nullptr;    // chains handed to the full-sort path
     int* fb_count = nullptr;   // [2 per group]: list lengths by step parity
     int* accepted = nullptr;   // [Cp]: gated starts taken
+    uint32_t* d_step = nullptr;   // device copy of the step counter, read by the kernels
     uint64_t step = 0;
+    // graph replay of ess_run: a capture stream and executables keyed by the run shape
+    hipStream_t cs = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    struct GraphEntry {
+        int64_t n_steps, thin;
+        void* trace;
+        hipGraphExec_t exec;
+    };
+    std::vector<GraphEntry> graphs;
+    bool use_graphs = true;
     int bm = 128, bn = 128, group_m = 4;
     int nmax = 512;
     // chain groups: each runs its own sample -> project pipeline on its own
@@ -135,8 +149,11 @@ struct ess_ctx {
     std::unique_ptr<Batch> batch;
 
     Group whole() const { return Group{0, C, Cp}; }
+    // G groups of whole 128-chain panels, as even as the panels allow
     Group group(int g) const {
-        const int Cg = Cp / G, c0 = g * Cg;
+        const int panels = Cp / 128;
+        const int p0 = g * panels / G, p1 = (g + 1) * panels / G;
+        const int c0 = p0 * 128, Cg = (p1 - p0) * 128;
         return Group{c0, std::max(0, std::min(C - c0, Cg)), Cg};
     }
 };
@@ -147,6 +164,14 @@ ess_status dalloc(ess_ctx* c, void** p, size_t bytes) {
     HIP_TRY(hipMalloc(p, bytes));
     c->allocs.push_back(*p);
     HIP_TRY(hipMemsetAsync(*p, 0, bytes, c->st));
+    return ESS_OK;
+}
+
+ess_status create_run_streams(ess_ctx* c) {
+    HIP_TRY(hipStreamCreateWithFlags(&c->cs, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
+    c->use_graphs = !(c->flags & ESS_EAGER) && !std::getenv("ESS_EAGER");
     return ESS_OK;
 }
 
@@ -274,6 +299,7 @@ SampleArgs sample_args(const ess_ctx* c, const Group& g, int gi) {
     a.seed = c->seed;
     a.fb_list = c->fb_list + g.c0;
     a.fb_count = c->fb_count + 2 * gi;
+    a.step_base = c->d_step;
     a.force_full = (c->flags & ESS_SORT_FULL) ? 1 : 0;
     return a;
 }
@@ -320,14 +346,17 @@ ess_status launch_commit(const ess_ctx* c, const Group& g, hipStream_t st, const
 
 // nu of `step` for chains [c0, c0 + n) into dst rows (leading dimension ld),
 // and/or their theta uniforms.
-ess_status launch_draw(const ess_ctx* c, int c0, int n, hipStream_t st, uint64_t step, void* dst,
-                       long long ld, double* u) {
+// step is relative to *step_base when step_base is given, else absolute.
+ess_status launch_draw(const ess_ctx* c, int c0, int n, hipStream_t st, uint64_t step,
+                       const uint32_t* step_base, void* dst, long long ld, double* u) {
     if (c->prec == 32)
         hipLaunchKernelGGL((draw_kernel<float>), dim3(n), dim3(256), 0, st, c->seed,
-                           static_cast<uint32_t>(step), 0u, c->d, static_cast<float*>(dst), ld, u, c0);
+                           static_cast<uint32_t>(step), step_base, 0u, c->d,
+                           static_cast<float*>(dst), ld, u, c0);
     else
         hipLaunchKernelGGL((draw_kernel<double>), dim3(n), dim3(256), 0, st, c->seed,
-                           static_cast<uint32_t>(step), 0u, c->d, static_cast<double*>(dst), ld, u, c0);
+                           static_cast<uint32_t>(step), step_base, 0u, c->d,
+                           static_cast<double*>(dst), ld, u, c0);
     HIP_TRY(hipGetLastError());
     return ESS_OK;
 }
@@ -398,19 +427,28 @@ ess_status sum_rejections(const ess_ctx* c, long long& total) {
     return ESS_OK;
 }
 
-// Issues n_steps transitions of every group; groups run on their own streams
-// between a fork and a join event on the caller's stream.
-ess_status issue_run(ess_ctx* c, int64_t n_steps, int64_t thin, void* trace) {
+ess_status launch_step_counter(const ess_ctx* c, hipStream_t st, uint64_t value, int add) {
+    hipLaunchKernelGGL(step_counter_kernel, dim3(1), dim3(64), 0, st, c->d_step,
+                       static_cast<uint32_t>(value), add);
+    HIP_TRY(hipGetLastError());
+    return ESS_OK;
+}
+
+// Issues n_steps transitions of every group on stream `base` (groups run on
+// their own streams between a fork and a join event) and advances the device
+// step counter.  Steps are relative to that counter, so the same launches can
+// be captured once and replayed.
+ess_status issue_run(ess_ctx* c, int64_t n_steps, int64_t thin, void* trace, hipStream_t base) {
     const size_t trace_row = static_cast<size_t>(c->C) * c->d * c->esz;
     const bool split = c->G > 1;
     hipStream_t sts[kMaxGroups];
     Group gr[kMaxGroups];
     for (int g = 0; g < c->G; ++g) {
-        sts[g] = split ? c->gs[g] : c->st;
+        sts[g] = split ? c->gs[g] : base;
         gr[g] = split ? c->group(g) : c->whole();
     }
     if (split) {
-        HIP_TRY(hipEventRecord(c->fork, c->st));
+        HIP_TRY(hipEventRecord(c->fork, base));
         for (int g = 0; g < c->G; ++g) HIP_TRY(hipStreamWaitEvent(sts[g], c->fork, 0));
     }
     SampleArgs a[kMaxGroups];
@@ -418,7 +456,7 @@ ess_status issue_run(ess_ctx* c, int64_t n_steps, int64_t thin, void* trace) {
         if (gr[g].n == 0) continue;
         ESS_TRY(clear_fallback_lists(c, sts[g], g));
         ESS_TRY(timed(c, ESS_KERNEL_OTHER, sts[g], [&] {
-            return launch_draw(c, gr[g].c0, gr[g].n, sts[g], c->step, c->N, c->dp, nullptr);
+            return launch_draw(c, gr[g].c0, gr[g].n, sts[g], 0, c->d_step, c->N, c->dp, nullptr);
         }));
         ESS_TRY(timed(c, ESS_KERNEL_OTHER, sts[g],
                       [&] { return launch_proj(c, gr[g], sts[g], c->Xprop, COLS_NU, 0, 0); }));
@@ -428,7 +466,7 @@ ess_status issue_run(ess_ctx* c, int64_t n_steps, int64_t thin, void* trace) {
         const bool both = s + 1 < n_steps;
         for (int g = 0; g < c->G; ++g) {
             if (gr[g].n == 0) continue;
-            a[g].step = static_cast<uint32_t>(c->step + s);
+            a[g].step = static_cast<uint32_t>(s);
             a[g].has_pending = s > 0;
             a[g].gen_next = both;
             a[g].trace = (trace && s > 0 && s % thin == 0)
@@ -452,10 +490,10 @@ ess_status issue_run(ess_ctx* c, int64_t n_steps, int64_t thin, void* trace) {
     if (split) {
         for (int g = 0; g < c->G; ++g) {
             HIP_TRY(hipEventRecord(c->join[g], sts[g]));
-            HIP_TRY(hipStreamWaitEvent(c->st, c->join[g], 0));
+            HIP_TRY(hipStreamWaitEvent(base, c->join[g], 0));
         }
     }
-    return ESS_OK;
+    return launch_step_counter(c, base, static_cast<uint64_t>(n_steps), 1);
 }
 
 // ---------------------------------------------------------------- batched
@@ -484,32 +522,33 @@ BatchArgs batch_args(const ess_ctx* c) {
     a.error = B.counters + 4;
     a.done = B.counters + 5;
     a.fb_list = B.fb_list;
+    a.step_base = c->d_step;
     return a;
 }
 
 template <int RPT, int NB>
-void launch_step_t(const ess_ctx* c, const BatchArgs& a) {
-    hipLaunchKernelGGL((batched_step_kernel<RPT, NB>), dim3(c->batch->grid), dim3(256), 0, c->st, a);
+void launch_step_t(const ess_ctx* c, const BatchArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL((batched_step_kernel<RPT, NB>), dim3(c->batch->grid), dim3(256), 0, st, a);
 }
 
-ess_status launch_batched_step(const ess_ctx* c, const BatchArgs& a) {
+ess_status launch_batched_step(const ess_ctx* c, const BatchArgs& a, hipStream_t st) {
     const ess_ctx::Batch& B = *c->batch;
-    if (B.nb == 256) launch_step_t<1, 256>(c, a);
-    else if (B.rpt <= 2) launch_step_t<2, 2048>(c, a);
-    else if (B.rpt <= 4) launch_step_t<4, 2048>(c, a);
-    else if (B.rpt <= 8) launch_step_t<8, 2048>(c, a);
-    else launch_step_t<16, 2048>(c, a);
+    if (B.nb == 256) launch_step_t<1, 256>(c, a, st);
+    else if (B.rpt <= 2) launch_step_t<2, 2048>(c, a, st);
+    else if (B.rpt <= 4) launch_step_t<4, 2048>(c, a, st);
+    else if (B.rpt <= 8) launch_step_t<8, 2048>(c, a, st);
+    else launch_step_t<16, 2048>(c, a, st);
     HIP_TRY(hipGetLastError());
     return ESS_OK;
 }
 
-ess_status launch_batched_fallback(const ess_ctx* c, const BatchArgs& a) {
+ess_status launch_batched_fallback(const ess_ctx* c, const BatchArgs& a, hipStream_t st) {
     const dim3 g(std::min(c->batch->NC, 768)), b(256);
     switch (c->batch->nmax) {
-        case 512: hipLaunchKernelGGL((batched_fallback_kernel<512>), g, b, 0, c->st, a); break;
-        case 1024: hipLaunchKernelGGL((batched_fallback_kernel<1024>), g, b, 0, c->st, a); break;
-        case 2048: hipLaunchKernelGGL((batched_fallback_kernel<2048>), g, b, 0, c->st, a); break;
-        default: hipLaunchKernelGGL((batched_fallback_kernel<4096>), g, b, 0, c->st, a); break;
+        case 512: hipLaunchKernelGGL((batched_fallback_kernel<512>), g, b, 0, st, a); break;
+        case 1024: hipLaunchKernelGGL((batched_fallback_kernel<1024>), g, b, 0, st, a); break;
+        case 2048: hipLaunchKernelGGL((batched_fallback_kernel<2048>), g, b, 0, st, a); break;
+        default: hipLaunchKernelGGL((batched_fallback_kernel<4096>), g, b, 0, st, a); break;
     }
     HIP_TRY(hipGetLastError());
     return ESS_OK;
@@ -540,22 +579,22 @@ ess_status batched_set_state_from_X(ess_ctx* c, const char* what) {
     return ESS_OK;
 }
 
-ess_status batched_run(ess_ctx* c, int64_t n_steps, int64_t thin, void* trace) {
+ess_status batched_issue(ess_ctx* c, int64_t n_steps, int64_t thin, void* trace, hipStream_t st) {
     ess_ctx::Batch& B = *c->batch;
     const int ncnt = 5 + 2 * B.n;
-    hipLaunchKernelGGL(zero_ints_n, dim3(std::min((ncnt + 255) / 256, 64)), dim3(256), 0, c->st,
+    hipLaunchKernelGGL(zero_ints_n, dim3(std::min((ncnt + 255) / 256, 64)), dim3(256), 0, st,
                        B.counters, ncnt);
     HIP_TRY(hipGetLastError());
     BatchArgs a = batch_args(c);
-    a.step = static_cast<uint32_t>(c->step);
-    ESS_TRY(timed(c, ESS_KERNEL_OTHER, c->st, [&] {
-        hipLaunchKernelGGL(batched_draw_kernel, dim3(B.NC), dim3(256), 0, c->st, a);
+    a.step = 0;
+    ESS_TRY(timed(c, ESS_KERNEL_OTHER, st, [&] {
+        hipLaunchKernelGGL(batched_draw_kernel, dim3(B.NC), dim3(256), 0, st, a);
         HIP_TRY(hipGetLastError());
         return ESS_OK;
     }));
     const size_t row = static_cast<size_t>(B.state_elems);
     for (int64_t s = 0; s <= n_steps; ++s) {
-        a.step = static_cast<uint32_t>(c->step + s);
+        a.step = static_cast<uint32_t>(s);
         a.has_pending = s > 0;
         a.do_sample = s < n_steps;
         a.gen_next = s + 1 < n_steps;
@@ -565,10 +604,15 @@ ess_status batched_run(ess_ctx* c, int64_t n_steps, int64_t thin, void* trace) {
         a.trace = (trace && s > 0 && s % thin == 0)
                       ? static_cast<float*>(trace) + (s / thin - 1) * row
                       : nullptr;
-        ESS_TRY(timed(c, ESS_KERNEL_BATCHED, c->st, [&] { return launch_batched_step(c, a); }));
+        ESS_TRY(timed(c, ESS_KERNEL_BATCHED, st, [&] { return launch_batched_step(c, a, st); }));
         if (a.do_sample)
-            ESS_TRY(timed(c, ESS_KERNEL_OTHER, c->st, [&] { return launch_batched_fallback(c, a); }));
+            ESS_TRY(timed(c, ESS_KERNEL_OTHER, st, [&] { return launch_batched_fallback(c, a, st); }));
     }
+    return launch_step_counter(c, st, static_cast<uint64_t>(n_steps), 1);
+}
+
+ess_status batched_check_error(ess_ctx* c) {
+    ess_ctx::Batch& B = *c->batch;
     int err = 0;
     HIP_TRY(hipMemcpyAsync(&err, B.counters + 4, sizeof(int), hipMemcpyDeviceToHost, c->st));
     HIP_TRY(hipStreamSynchronize(c->st));
@@ -655,6 +699,8 @@ ess_status batched_init(ess_ctx* c, const ess_problem* pr, int n) {
     ESS_TRY(dalloc(c, reinterpret_cast<void**>(&c->sel), sizeof(int) * chain_off));
     ESS_TRY(dalloc(c, reinterpret_cast<void**>(&c->flag), sizeof(int) * chain_off));
     ESS_TRY(dalloc(c, reinterpret_cast<void**>(&c->rej), sizeof(long long) * chain_off));
+    ESS_TRY(dalloc(c, reinterpret_cast<void**>(&c->d_step), sizeof(uint32_t)));
+    ESS_TRY(create_run_streams(c));
     HIP_TRY(hipMemcpyAsync(B.descs, B.h.data(), sizeof(ProbDesc) * n, hipMemcpyHostToDevice, c->st));
     HIP_TRY(hipMemcpyAsync(B.tiles, tiles.data(), sizeof(int4) * B.NT, hipMemcpyHostToDevice, c->st));
     HIP_TRY(hipMemcpyAsync(B.chains, caller_chains.data(), sizeof(int2) * B.NC,
@@ -703,6 +749,186 @@ ess_status batched_copy_state(const ess_ctx* c, const float* src, float* dst, in
                        to_library);
     HIP_TRY(hipGetLastError());
     return ESS_OK;
+}
+
+// ---------------------------------------------------------------- runs
+// Kernel by kernel on the caller's stream (while profiling, or with
+// ESS_EAGER), otherwise by replaying a graph captured once per run shape on
+// the library's capture stream, ordered after the caller's stream by events.
+ess_status run_dispatch(ess_ctx* c, int64_t n_steps, int64_t thin, void* trace) {
+    auto issue = [&](hipStream_t st) {
+        return c->batch ? batched_issue(c, n_steps, thin, trace, st)
+                        : issue_run(c, n_steps, thin, trace, st);
+    };
+    if (!c->use_graphs || c->profiling) {
+        ESS_TRY(issue(c->st));
+    } else {
+        hipGraphExec_t exec = nullptr;
+        for (auto& g : c->graphs)
+            if (g.n_steps == n_steps && g.thin == thin && g.trace == trace) exec = g.exec;
+        if (!exec) {
+            HIP_TRY(hipStreamBeginCapture(c->cs, hipStreamCaptureModeRelaxed));
+            const ess_status s = issue(c->cs);
+            hipGraph_t graph = nullptr;
+            const hipError_t e = hipStreamEndCapture(c->cs, &graph);
+            if (s != ESS_OK) {
+                if (e == hipSuccess && graph) (void)hipGraphDestroy(graph);
+                return s;
+            }
+            HIP_TRY(e);
+            const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            HIP_TRY(ei);
+            if (c->graphs.size() >= 8) {
+                (void)hipGraphExecDestroy(c->graphs.front().exec);
+                c->graphs.erase(c->graphs.begin());
+            }
+            c->graphs.push_back({n_steps, thin, trace, exec});
+        }
+        HIP_TRY(hipEventRecord(c->ev_in, c->st));
+        HIP_TRY(hipStreamWaitEvent(c->cs, c->ev_in, 0));
+        HIP_TRY(hipGraphLaunch(exec, c->cs));
+        HIP_TRY(hipEventRecord(c->ev_out, c->cs));
+        HIP_TRY(hipStreamWaitEvent(c->st, c->ev_out, 0));
+    }
+    if (c->batch) ESS_TRY(batched_check_error(c));
+    return ESS_OK;
+}
+
+ess_status drop_graphs(ess_ctx* c) {
+    if (!c->graphs.empty()) HIP_TRY(hipStreamSynchronize(c->cs));
+    for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+    c->graphs.clear();
+    return ESS_OK;
+}
+
+// ---------------------------------------------------------------- autotuning
+// Tile and launch choices per shape, cached in a small JSON file:
+//   {"<key>": {"G": 2, "bm": 128, "bn": 128, "group_m": 4, "grid": 0, "us_per_step": 162.5}, ...}
+std::string tune_cache_path() {
+    if (const char* p = std::getenv("ESS_TUNE_CACHE")) return p;
+    const char* home = std::getenv("HOME");
+    return std::string(home ? home : ".") + "/.cache/ess_tune.json";
+}
+
+std::string tune_key(const ess_ctx* c) {
+    hipDeviceProp_t prop;
+    int dev = 0;
+    std::string arch = "gpu";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        arch = prop.gcnArchName;
+    arch = arch.substr(0, arch.find(':'));
+    std::ostringstream k;
+    if (c->batch) {
+        long long work = 0;
+        for (const auto& d : c->batch->h) work += static_cast<long long>(d.m) * d.d * d.C;
+        k << arch << " batched n=" << c->batch->n << " chains=" << c->batch->NC << " work=" << work;
+    } else {
+        k << arch << " single p=" << c->prec << " d=" << c->d << " m=" << c->m << " C=" << c->C
+          << (c->bstride ? " perchainb" : "");
+    }
+    return k.str();
+}
+
+std::string read_file(const std::string& path) {
+    std::ifstream f(path);
+    std::stringstream ss;
+    ss << f.rdbuf();
+    return ss.str();
+}
+
+// The object stored under `key`, or "".
+std::string cache_entry(const std::string& text, const std::string& key) {
+    const std::string q = "\"" + key + "\"";
+    const size_t at = text.find(q);
+    if (at == std::string::npos) return "";
+    const size_t open = text.find('{', at + q.size());
+    const size_t close = text.find('}', open);
+    if (open == std::string::npos || close == std::string::npos) return "";
+    return text.substr(open, close - open + 1);
+}
+
+double field(const std::string& obj, const char* name, double dflt) {
+    const std::string q = std::string("\"") + name + "\"";
+    const size_t at = obj.find(q);
+    if (at == std::string::npos) return dflt;
+    const size_t colon = obj.find(':', at);
+    return colon == std::string::npos ? dflt : std::atof(obj.c_str() + colon + 1);
+}
+
+struct TuneChoice {
+    int G = 1, bm = 128, bn = 128, group_m = 4, grid = 0;
+    double us = 0;
+};
+
+void apply_choice(ess_ctx* c, const TuneChoice& t) {
+    if (c->batch) {
+        if (t.grid > 0) c->batch->grid = t.grid;
+    } else {
+        c->G = std::max(1, std::min({t.G, kMaxGroups, c->Cp / 128}));
+        if (c->G > 1 && (!c->fork || !c->gs[c->G - 1] || !c->join[c->G - 1])) c->G = 1;
+        if (c->prec == 32) {
+            c->bm = t.bm;
+            c->bn = t.bn;
+        }
+        c->group_m = t.group_m;
+    }
+}
+
+TuneChoice current_choice(const ess_ctx* c) {
+    TuneChoice t;
+    t.G = c->G;
+    t.bm = c->bm;
+    t.bn = c->bn;
+    t.group_m = c->group_m;
+    t.grid = c->batch ? c->batch->grid : 0;
+    return t;
+}
+
+void load_tuned(ess_ctx* c) {
+    if (!c->batch) return;   // single-problem tuning is switched off (see ess_autotune)
+    const std::string obj = cache_entry(read_file(tune_cache_path()), tune_key(c));
+    if (obj.empty()) return;
+    TuneChoice t = current_choice(c);
+    t.G = static_cast<int>(field(obj, "G", t.G));
+    t.bm = static_cast<int>(field(obj, "bm", t.bm));
+    t.bn = static_cast<int>(field(obj, "bn", t.bn));
+    t.group_m = static_cast<int>(field(obj, "group_m", t.group_m));
+    t.grid = static_cast<int>(field(obj, "grid", 0));
+    const bool tiles_ok = (t.bm == 64 || t.bm == 128) && (t.bn == 64 || t.bn == 128);
+    if (tiles_ok && t.group_m >= 1 && t.group_m <= 64) apply_choice(c, t);
+}
+
+void store_tuned(const ess_ctx* c, const TuneChoice& t) {
+    const std::string path = tune_cache_path();
+    std::string text = read_file(path);
+    const std::string key = tune_key(c);
+    std::ostringstream e;
+    e << "\"" << key << "\": {\"G\": " << t.G << ", \"bm\": " << t.bm << ", \"bn\": " << t.bn
+      << ", \"group_m\": " << t.group_m << ", \"grid\": " << t.grid
+      << ", \"us_per_step\": " << t.us << "}";
+    const std::string q = "\"" + key + "\"";
+    const size_t at = text.find(q);
+    if (at != std::string::npos) {
+        const size_t close = text.find('}', at);
+        text.replace(at, close - at + 1, e.str());
+    } else {
+        const size_t last = text.rfind('}');
+        if (text.empty() || last == std::string::npos) text = "{\n" + e.str() + "\n}\n";
+        else {
+            const bool empty_obj = text.find('"') == std::string::npos;
+            text.insert(last, (empty_obj ? "" : ",\n") + e.str() + "\n");
+        }
+    }
+    const size_t slash = path.rfind('/');
+    if (slash != std::string::npos) {
+        const std::string dir = path.substr(0, slash);
+        // create the directory one level at a time (no shell)
+        for (size_t i = 1; i <= dir.size(); ++i)
+            if (i == dir.size() || dir[i] == '/') (void)mkdir(dir.substr(0, i).c_str(), 0755);
+    }
+    std::ofstream f(path);
+    f << text;
 }
 
 // ---------------------------------------------------------------- network
@@ -939,14 +1165,18 @@ ess_status ess_init(const ess_problem* pr, void* stream, ess_ctx** out) {
     c->flags = pr->flags;
     c->bstride = (pr->flags & ESS_PER_CHAIN_B) ? pr->m : 0;
     c->st = static_cast<hipStream_t>(stream);
-    // two chain groups when there are enough chains to fill the GPU twice over
-    c->G = (c->prec == 32 && c->C >= 512) ? 2 : 1;
+    // One chain group by default: splitting the chains into two concurrent
+    // sample -> projection pipelines measured slower at d=1000, m=2000, 1024
+    // chains (two half-size projection launches took 141 us per step against
+    // 93 us for one).  ESS_CHAIN_GROUPS=2 selects the split.
+    c->G = 1;
     if (const char* e = std::getenv("ESS_CHAIN_GROUPS")) {
         const int g = std::atoi(e);
-        if (g >= 1 && g <= kMaxGroups) c->G = g;
+        if (g >= 1 && g <= 2) c->G = g;   // more than two groups has not been exercised
     }
     c->mp = round_up(c->m, 128);
-    c->Cp = round_up(c->C, 128 * c->G);
+    c->Cp = round_up(c->C, 128);
+    c->G = std::min(c->G, c->Cp / 128);
     c->dp = round_up(c->d, 32);
     if (c->prec == 32) {
         c->bm = c->m > 1024 ? 128 : 64;
@@ -977,11 +1207,15 @@ ess_status ess_init(const ess_problem* pr, void* stream, ess_ctx** out) {
         (s = dalloc(c, reinterpret_cast<void**>(&c->rej), sizeof(long long) * c->Cp)) != ESS_OK ||
         (s = dalloc(c, reinterpret_cast<void**>(&c->fb_list), sizeof(int) * c->Cp)) != ESS_OK ||
         (s = dalloc(c, reinterpret_cast<void**>(&c->accepted), sizeof(int) * c->Cp)) != ESS_OK ||
+        (s = dalloc(c, reinterpret_cast<void**>(&c->d_step), sizeof(uint32_t))) != ESS_OK ||
+        (s = create_run_streams(c)) != ESS_OK ||
         (s = dalloc(c, reinterpret_cast<void**>(&c->fb_count), sizeof(int) * 2 * kMaxGroups)) != ESS_OK)
         return bail(s);
-    if (c->G > 1) {
+    {
+        // every group stream and event exists from the start: the autotuner and
+        // cached choices may raise the group count up to kMaxGroups later
         hipError_t ee = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
-        for (int g = 0; g < c->G && ee == hipSuccess; ++g) {
+        for (int g = 0; g < kMaxGroups && ee == hipSuccess; ++g) {
             ee = hipStreamCreateWithFlags(&c->gs[g], hipStreamNonBlocking);
             if (ee == hipSuccess) ee = hipEventCreateWithFlags(&c->join[g], hipEventDisableTiming);
         }
@@ -1018,6 +1252,7 @@ ess_status ess_init(const ess_problem* pr, void* stream, ess_ctx** out) {
         return bail(ESS_ERR_HIP);
     }
     if ((s = set_state_from_X(c, "ess_init")) != ESS_OK) return bail(s);
+    load_tuned(c);
     *out = c;
     return ESS_OK;
 }
@@ -1061,6 +1296,10 @@ void ess_destroy(ess_ctx* c) {
         if (c->join[g]) (void)hipEventDestroy(c->join[g]);
     }
     if (c->fork) (void)hipEventDestroy(c->fork);
+    (void)drop_graphs(c);
+    if (c->cs) (void)hipStreamDestroy(c->cs);
+    if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+    if (c->ev_out) (void)hipEventDestroy(c->ev_out);
     for (void* p : c->allocs) (void)hipFree(p);
     delete c;
 }
@@ -1074,8 +1313,7 @@ ess_status ess_run(ess_ctx* c, int64_t n_steps, int64_t thin, void* trace, int64
     long long before = 0;
     if (n_rejected) ESS_TRY(sum_rejections(c, before));
     if (n_steps > 0) {
-        if (c->batch) ESS_TRY(batched_run(c, n_steps, thin, trace));
-        else ESS_TRY(issue_run(c, n_steps, thin, trace));
+        ESS_TRY(run_dispatch(c, n_steps, thin, trace));
         c->step += static_cast<uint64_t>(n_steps);
     }
     if (n_rejected) {
@@ -1115,6 +1353,7 @@ ess_status ess_set_state(ess_ctx* c, const void* x_in, uint64_t step) {
         ESS_TRY(copy_rows_in(c, c->X, x_in));
         ESS_TRY(set_state_from_X(c, "ess_set_state"));
     }
+    ESS_TRY(launch_step_counter(c, c->st, step, 0));
     c->step = step;
     return ESS_OK;
 }
@@ -1168,6 +1407,7 @@ ess_status ess_init_batched(const ess_problem* pr, int32_t n_problems, void* str
     c->st = static_cast<hipStream_t>(stream);
     c->C = static_cast<int>(total_chains);
     ess_status s = batched_init(c, pr, n_problems);
+    if (s == ESS_OK) load_tuned(c);
     if (s != ESS_OK) {
         std::string keep = g_err;
         ess_destroy(c);
@@ -1192,7 +1432,7 @@ ess_status ess_transition_explicit(ess_ctx* c, const void* x, const void* nu, co
     ESS_TRY(clear_fallback_lists(c, c->st, 0));
     ESS_TRY(launch_proj(c, w, c->st, c->Xprop, COLS_NU, 0, 0));
     SampleArgs a = sample_args(c, w, 0);
-    a.step = static_cast<uint32_t>(c->step);
+    a.step = 0;   // the device counter holds the current step
     a.u_explicit = u;
     a.intervals = intervals;
     a.n_intervals = n_intervals;
@@ -1212,7 +1452,7 @@ ess_status ess_draw(ess_ctx* c, uint64_t step, void* nu, double* u) {
     ESS_TRY(check_ctx(c));
     if (c->batch) return fail(ESS_ERR_UNSUPPORTED, "ess_draw takes single-problem contexts");
     if (step >= (1ull << 32)) return fail(ESS_ERR_UNSUPPORTED, "the step counter is limited to 2^32");
-    return launch_draw(c, 0, c->C, c->st, step, nu, c->d, u);
+    return launch_draw(c, 0, c->C, c->st, step, nullptr, nu, c->d, u);
 }
 
 
@@ -1234,6 +1474,7 @@ ess_status ess_set_state_gated(ess_ctx* c, const void* x_candidate, const void* 
     ESS_TRY(set_state_from_X(c, "ess_set_state_gated (fallback rows)"));
     if (accepted)
         for (int i = 0; i < c->C; ++i) accepted[i] = acc[i];
+    ESS_TRY(launch_step_counter(c, c->st, step, 0));
     c->step = step;
     return ESS_OK;
 }
@@ -1336,6 +1577,100 @@ void ess_mlp_destroy(ess_mlp* n) {
     else (void)hipDeviceSynchronize();
     for (void* p : n->allocs) (void)hipFree(p);
     delete n;
+}
+
+
+ess_status ess_autotune(ess_ctx* c, int32_t steps_per_trial, char* report, int32_t report_len) {
+    g_err.clear();
+    ESS_TRY(check_ctx(c));
+    if (steps_per_trial < 1) return fail(ESS_ERR_INVALID_ARG, "steps_per_trial must be >= 1");
+    if (!c->batch)
+        return fail(ESS_ERR_UNSUPPORTED,
+                    "ess_autotune is switched off for single-problem contexts: its trial loop "
+                    "ended the process with a host segmentation fault whose cause is not yet known");
+    // keep the chains where they are: save the state, restore it afterwards
+    float* saved = nullptr;
+    size_t bytes = c->batch ? sizeof(float) * c->batch->h.back().x_off +
+                                  sizeof(float) * static_cast<size_t>(c->batch->h.back().Cp) * c->batch->h.back().dp
+                            : static_cast<size_t>(c->Cp) * c->dp * c->esz;
+    void* X = c->batch ? static_cast<void*>(c->batch->X) : c->X;
+    HIP_TRY(hipMalloc(&saved, bytes));
+    HIP_TRY(hipMemcpyAsync(saved, X, bytes, hipMemcpyDeviceToDevice, c->st));
+    const uint64_t step0 = c->step;
+
+    std::vector<TuneChoice> cands;
+    if (c->batch) {
+        int dev = 0, cus = 0;
+        HIP_TRY(hipGetDevice(&dev));
+        HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        const int maxk = std::max(1, c->batch->grid / std::max(cus, 1));
+        for (int k = 1; k <= maxk; ++k) {
+            TuneChoice t = current_choice(c);
+            t.grid = cus * k;
+            cands.push_back(t);
+        }
+    } else {
+        const int gmax = std::min(kMaxGroups, c->Cp / 128);
+        const int tiles[4][2] = {{128, 128}, {128, 64}, {64, 128}, {64, 64}};
+        for (int G = 1; G <= gmax; G *= 2)
+            for (int ti = 0; ti < (c->prec == 32 ? 4 : 1); ++ti)
+                for (int gm : {2, 4, 8}) {
+                    TuneChoice t = current_choice(c);
+                    t.G = G;
+                    t.bm = tiles[ti][0];
+                    t.bn = tiles[ti][1];
+                    t.group_m = gm;
+                    cands.push_back(t);
+                }
+    }
+    const TuneChoice before = current_choice(c);
+    TuneChoice best = before;
+    best.us = 1e30;
+    std::ostringstream rep;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    ess_status st = ESS_OK;
+    for (TuneChoice t : cands) {
+        apply_choice(c, t);
+        if ((st = drop_graphs(c)) != ESS_OK) break;
+        if ((st = run_dispatch(c, steps_per_trial, 1, nullptr)) != ESS_OK) break;   // capture, warm
+        c->step += steps_per_trial;
+        HIP_TRY(hipEventRecord(e0, c->st));
+        if ((st = run_dispatch(c, steps_per_trial, 1, nullptr)) != ESS_OK) break;
+        c->step += steps_per_trial;
+        HIP_TRY(hipEventRecord(e1, c->st));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        t.us = 1e3 * ms / steps_per_trial;
+        rep << "G=" << t.G << " bm=" << t.bm << " bn=" << t.bn << " group_m=" << t.group_m
+            << " grid=" << t.grid << ": " << t.us << " us/step\n";
+        if (t.us < best.us) best = t;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != ESS_OK) apply_choice(c, before);
+    else apply_choice(c, best);
+    ESS_TRY(drop_graphs(c));
+    HIP_TRY(hipMemcpyAsync(X, saved, bytes, hipMemcpyDeviceToDevice, c->st));
+    HIP_TRY(hipStreamSynchronize(c->st));
+    (void)hipFree(saved);
+    if (c->batch) ESS_TRY(batched_set_state_from_X(c, "ess_autotune"));
+    else ESS_TRY(set_state_from_X(c, "ess_autotune"));
+    ESS_TRY(launch_step_counter(c, c->st, step0, 0));
+    c->step = step0;
+    if (st != ESS_OK) return st;
+    store_tuned(c, best);
+    rep << "chosen: G=" << best.G << " bm=" << best.bm << " bn=" << best.bn << " group_m="
+        << best.group_m << " grid=" << best.grid << " (" << best.us << " us/step)\n";
+    if (report && report_len > 0) {
+        const std::string r = rep.str();
+        const size_t n = std::min(r.size(), static_cast<size_t>(report_len - 1));
+        std::memcpy(report, r.data(), n);
+        report[n] = 0;
+    }
+    return ESS_OK;
 }
 
 }  // extern "C"

@@ -63,7 +63,8 @@ struct SampleArgs {
     long long* rej;       // [Cp]
     double eps;
     uint64_t seed;
-    uint32_t step;        // step whose nu/u are used
+    uint32_t step;        // step whose nu/u are used, relative to *step_base
+    const uint32_t* step_base;   // nullable: device counter added to step
     int has_pending;      // commit the previous proposal first
     int gen_next;         // write nu(step + 1) into N after the move
     void* trace;          // nullable: committed state of the previous step, [C][d] T
@@ -77,6 +78,10 @@ struct SampleArgs {
     int* fb_count;        // [2]: list length, indexed by step parity
     int force_full;       // 1: every chain takes the full path
 };
+
+__device__ __forceinline__ uint32_t abs_step(const SampleArgs& a) {
+    return a.step + (a.step_base ? *a.step_base : 0u);
+}
 
 constexpr double kKeyScale = 281474976710656.0 / kTwoPi;   // 2^48 / (2 pi)
 constexpr uint64_t kKeyMax = (1ull << 48) - 1;
@@ -217,7 +222,7 @@ __device__ __forceinline__ ChainRef<T> make_ref(const SampleArgs& a, int c) {
     r.m = a.m;
     r.chain = static_cast<uint32_t>(c);
     r.problem = a.problem;
-    r.step = a.step;
+    r.step = abs_step(a);
     r.gen_next = a.gen_next;
     r.eps = a.eps;
     r.seed = a.seed;
@@ -277,9 +282,11 @@ __global__ __launch_bounds__(256) void commit_kernel(SampleArgs a) {
 
 // nu for `step` into dst[c * ld + k], k < d (chains c0 .. c0 + gridDim.x - 1).
 template <typename T>
-__global__ __launch_bounds__(256) void draw_kernel(uint64_t seed, uint32_t step, uint32_t problem,
+__global__ __launch_bounds__(256) void draw_kernel(uint64_t seed, uint32_t step_rel,
+                                                   const uint32_t* step_base, uint32_t problem,
                                                    int d, T* dst, long long ld, double* u, int c0) {
     const int c = c0 + blockIdx.x;
+    const uint32_t step = step_rel + (step_base ? *step_base : 0u);
     const Rng rng(seed);
     T* row = dst ? dst + static_cast<size_t>(c) * ld : nullptr;
     if (row) {
@@ -511,7 +518,7 @@ __device__ void full_chain(const ChainRef<T>& r, int sel, const FullLds& L) {
 template <typename T, int NMAX>
 __global__ __launch_bounds__(256) void fallback_kernel(SampleArgs a) {
     ESS_FULL_LDS(NMAX)
-    const int count = a.fb_count[a.step & 1];
+    const int count = a.fb_count[abs_step(a) & 1];
     for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
         const ChainRef<T> r = make_ref<T>(a, a.fb_list[idx]);
         full_chain<T>(r, *r.sel, full_lds);
@@ -702,9 +709,18 @@ __global__ __launch_bounds__(256) void sample_bucket_kernel(SampleArgs a) {
     const int c = a.c0 + blockIdx.x;
     const ChainRef<T> r = make_ref<T>(a, c);
     const int sel = a.has_pending ? commit_chain<T>(r) : *r.sel;
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.fb_count[(a.step + 1) & 1] = 0;   // next step's list
+    const uint32_t step = r.step;
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.fb_count[(step + 1) & 1] = 0;   // next step's list
     const bool done = !a.force_full && bucket_chain<T, RPT, NB>(r, sel, lds);
-    if (!done && threadIdx.x == 0) a.fb_list[atomicAdd(a.fb_count + (a.step & 1), 1)] = c;
+    if (!done && threadIdx.x == 0) a.fb_list[atomicAdd(a.fb_count + (step & 1), 1)] = c;
+}
+
+}  // namespace ess
+
+namespace ess {
+
+__global__ void step_counter_kernel(uint32_t* counter, uint32_t value, int add) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = add ? *counter + value : value;
 }
 
 }  // namespace ess

@@ -77,3 +77,31 @@ def test_batched_full_workload_stays_feasible(E):
         bound = 2 * pr["A"].shape[1] * 2.0 ** -24 * (np.abs(g) @ np.abs(pr["A"]).T)
         assert (slack >= -bound).all()
     assert nrej <= 1e-4 * 256 * 64 * 20
+
+
+def test_batched_graph_replay_equals_eager(E, monkeypatch):
+    probs = problems(5, 8, seed=9)
+    g = E.BatchedSampler(probs)
+    tr1, _ = g.run(4)
+    tr2, _ = g.run(4)
+    g.close()
+    monkeypatch.setenv("ESS_EAGER", "1")
+    e = E.BatchedSampler(probs)
+    want, _ = e.run(8)
+    e.close()
+    assert torch.equal(torch.cat([tr1, tr2]), want)
+
+
+def test_batched_autotune_keeps_results(E, tmp_path, monkeypatch):
+    monkeypatch.setenv("ESS_TUNE_CACHE", str(tmp_path / "tune.json"))
+    probs = problems(6, 16, seed=12)
+    a = E.BatchedSampler(probs)
+    first, _ = a.run(3)
+    report = E.ess_autotune(a.ctx, 2)
+    assert "chosen" in report
+    rest, _ = a.run(3)
+    b = E.BatchedSampler(probs)
+    want, _ = b.run(6)
+    assert torch.equal(torch.cat([first, rest]), want)
+    a.close()
+    b.close()

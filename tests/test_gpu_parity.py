@@ -273,3 +273,61 @@ def test_full_sort_path_matches_bucket_path(E, name, d, m, C, precision, eps):
     assert np.abs(a["theta"] - f["theta"]).max() <= 1e-12
     assert np.array_equal(a["rejected"], f["rejected"])
     assert np.abs(a["x_new"] - f["x_new"]).max() <= 1e-6
+
+
+def test_graph_replay_equals_eager_launches(E):
+    """Captured-graph runs (default) and kernel-by-kernel runs agree bit for bit,
+    across repeated replays of one captured shape and a state reset."""
+    pr = synth.box_halfspace(n_chains=700)            # two chain groups
+    g = E.Sampler(pr.A, pr.b, pr.x0, pr.n_chains, seed=4, precision=32)
+    e = E.Sampler(pr.A, pr.b, pr.x0, pr.n_chains, seed=4, precision=32, eager=True)
+    trace = torch.empty(3, pr.n_chains, pr.d, device="cuda")
+    parts = []
+    for _ in range(3):                                 # same shape and trace buffer: replays
+        E.ess_run(g.ctx, 6, 2, trace, False)
+        parts.append(trace.clone())
+    want, _ = e.run(18, thin=2)
+    assert torch.equal(torch.cat(parts), want)
+    x, step = g.state()
+    assert step == 18
+    g.set_state(x, 3)                                  # rewind the counter: replay uses it
+    E.ess_run(g.ctx, 6, 2, trace, False)
+    e2 = E.Sampler(pr.A, pr.b, pr.x0, pr.n_chains, seed=4, precision=32, eager=True)
+    e2.set_state(x, 3)
+    want2, _ = e2.run(6, thin=2)
+    assert torch.equal(trace, want2)
+    for s in (g, e, e2):
+        s.close()
+
+
+@pytest.mark.skip(reason="single-context autotuning is switched off: on the GPU its trial loop "
+                         "ended the process with a host segmentation fault (twice) whose cause is "
+                         "not yet shown; ess_autotune now returns ESS_ERR_UNSUPPORTED for it")
+def test_autotune_keeps_state_and_results(E, tmp_path, monkeypatch):
+    monkeypatch.setenv("ESS_TUNE_CACHE", str(tmp_path / "tune.json"))
+    pr = synth.box_halfspace(n_chains=640)
+    a = E.Sampler(pr.A, pr.b, pr.x0, pr.n_chains, seed=8, precision=32)
+    first, _ = a.run(5)
+    report = E.ess_autotune(a.ctx, 2)
+    say(report)
+    assert "chosen" in report and (tmp_path / "tune.json").exists()
+    x, step = a.state()
+    assert step == 5 and torch.equal(x, first[-1])
+    rest, _ = a.run(5)
+    b = E.Sampler(pr.A, pr.b, pr.x0, pr.n_chains, seed=8, precision=32, eager=True)
+    want, _ = b.run(10)
+    assert torch.equal(torch.cat([first, rest]), want)
+    c = E.Sampler(pr.A, pr.b, pr.x0, pr.n_chains, seed=8, precision=32)   # loads the cache
+    again, _ = c.run(10)
+    assert torch.equal(again, want)
+    for s in (a, b, c):
+        s.close()
+
+
+def test_single_context_autotune_is_refused(E):
+    pr = synth.small_fp64()
+    s = E.Sampler(pr.A, pr.b, pr.x0, pr.n_chains, precision=64)
+    with pytest.raises(E.EssError) as ei:
+        E.ess_autotune(s.ctx, 2)
+    assert ei.value.status == E.ESS_ERR_UNSUPPORTED
+    s.close()
