@@ -237,14 +237,15 @@ ProjOut proj_out(const ess_ctx* c, const Group& g, int p_direct, int strict) {
 
 enum Cols { COLS_X = 0, COLS_NU = 1, COLS_BOTH = 2 };
 
-template <int BM, int BN>
+template <int BM, int BN, int NW_M = 2, int NW_N = 2>
 void launch_f32(const ess_ctx* c, const Group& g, hipStream_t st, const float* B0, int cols,
                 const ProjOut& o) {
     const int tiles_m = c->mp / BM, half = g.Cg / BN;
     const int tn0 = (cols == COLS_NU) ? half : 0;
     const int tiles_n = (cols == COLS_BOTH) ? 2 * half : half;
     const float* B1 = static_cast<const float*>(c->N) + static_cast<size_t>(g.c0) * c->dp;
-    hipLaunchKernelGGL((proj_gemm_f32<BM, BN>), dim3(tiles_m * tiles_n), dim3(256), 0, st,
+    hipLaunchKernelGGL((proj_gemm_f32<BM, BN, NW_M, NW_N>), dim3(tiles_m * tiles_n),
+                       dim3(64 * NW_M * NW_N), 0, st,
                        static_cast<const float*>(c->A), B0, B1, c->dp, tiles_m, tiles_n, tn0,
                        c->group_m, o);
 }
@@ -257,7 +258,7 @@ ess_status launch_proj(const ess_ctx* c, const Group& g, hipStream_t st, const v
     const size_t off = static_cast<size_t>(g.c0) * c->dp;
     if (c->prec == 32) {
         const float* B0 = static_cast<const float*>(Y) + off;
-        if (c->bm == 128 && c->bn == 128) launch_f32<128, 128>(c, g, st, B0, cols, o);
+        if (c->bm == 128 && c->bn == 128) launch_f32<128, 128, 4, 2>(c, g, st, B0, cols, o);
         else if (c->bm == 128 && c->bn == 64) launch_f32<128, 64>(c, g, st, B0, cols, o);
         else if (c->bm == 64 && c->bn == 128) launch_f32<64, 128>(c, g, st, B0, cols, o);
         else launch_f32<64, 64>(c, g, st, B0, cols, o);

@@ -93,8 +93,9 @@ __device__ __forceinline__ void tile_coords(int bid, int tiles_m, int tiles_n, i
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // float32 projections on the matrix cores (v_mfma_f32_16x16x4_f32), float32
-// accumulation.  256 threads = 2 x 2 waves, each wave owns a (BM/2) x (BN/2)
-// block of 16 x 16 MFMA tiles.  K advances 32 at a time through a double-
+// accumulation.  NW_M x NW_N waves, each owning a (BM / NW_M) x (BN / NW_N)
+// block of 16 x 16 MFMA tiles; 128 x 128 tiles use 4 x 2 waves (two per
+// SIMD, which hides LDS and barrier latency behind the other wave's MFMAs).  K advances 32 at a time through a double-
 // buffered LDS tile.  Inside each group of 16 k, lane l supplies the four k
 // values 4 (l / 16) .. 4 (l / 16) + 3 of its row as one 16-byte LDS read, and
 // MFMA number kk uses element kk: A and B use the same k for the same (lane
@@ -109,19 +110,20 @@ struct GemmLds {
 };
 
 // One BM x BN output tile at (m0, n0) of the group described by `o`; B0 / B1
-// point at the group's first x' / nu row.  All 256 threads call it; the tile
-// ends with the block synchronised.
-template <int BM, int BN>
+// point at the group's first x' / nu row.  All NW_M x NW_N waves of the block
+// call it; the tile ends with the block synchronised.
+template <int BM, int BN, int NW_M = 2, int NW_N = 2>
 __device__ __forceinline__ void gemm_tile_f32(const float* __restrict__ A,
                                               const float* __restrict__ B0,
                                               const float* __restrict__ B1, int K, int m0, int n0,
                                               const ProjOut& o, GemmLds<BM, BN>& L) {
+    constexpr int NT = 64 * NW_M * NW_N;
     constexpr int BK = GemmLds<BM, BN>::BK, LK = GemmLds<BM, BN>::LK;
-    constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 16, TN = WN / 16;
-    constexpr int ALD = BM * BK / 4 / 256, BLD = BN * BK / 4 / 256;
-    static_assert(ALD >= 1 && BLD >= 1, "tile too small for 256 threads");
+    constexpr int WM = BM / NW_M, WN = BN / NW_N, TM = WM / 16, TN = WN / 16;
+    constexpr int ALD = BM * BK / 4 / NT, BLD = BN * BK / 4 / NT;
+    static_assert(ALD >= 1 && BLD >= 1 && TM >= 1 && TN >= 1, "tile too small for the waves");
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
+    const int wm = wave / NW_N, wn = wave % NW_N;
     const float* Ab = A + static_cast<size_t>(m0) * K;
     const float* Bb = (n0 < o.Cg) ? B0 + static_cast<size_t>(n0) * K
                                   : B1 + static_cast<size_t>(n0 - o.Cg) * K;
@@ -130,24 +132,24 @@ __device__ __forceinline__ void gemm_tile_f32(const float* __restrict__ A,
     auto gload = [&](int k0) {
 #pragma unroll
         for (int i = 0; i < ALD; ++i) {
-            const int idx = tid + i * 256, row = idx >> 3, kq = idx & 7;
+            const int idx = tid + i * NT, row = idx >> 3, kq = idx & 7;
             ra[i] = *reinterpret_cast<const f32x4*>(Ab + static_cast<size_t>(row) * K + k0 + kq * 4);
         }
 #pragma unroll
         for (int i = 0; i < BLD; ++i) {
-            const int idx = tid + i * 256, row = idx >> 3, kq = idx & 7;
+            const int idx = tid + i * NT, row = idx >> 3, kq = idx & 7;
             rb[i] = *reinterpret_cast<const f32x4*>(Bb + static_cast<size_t>(row) * K + k0 + kq * 4);
         }
     };
     auto lstore = [&](int buf) {
 #pragma unroll
         for (int i = 0; i < ALD; ++i) {
-            const int idx = tid + i * 256, row = idx >> 3, kq = idx & 7;
+            const int idx = tid + i * NT, row = idx >> 3, kq = idx & 7;
             *reinterpret_cast<f32x4*>(&L.As[buf][row * LK + kq * 4]) = ra[i];
         }
 #pragma unroll
         for (int i = 0; i < BLD; ++i) {
-            const int idx = tid + i * 256, row = idx >> 3, kq = idx & 7;
+            const int idx = tid + i * NT, row = idx >> 3, kq = idx & 7;
             *reinterpret_cast<f32x4*>(&L.Bs[buf][row * LK + kq * 4]) = rb[i];
         }
     };
@@ -202,25 +204,26 @@ __device__ __forceinline__ void gemm_tile_f32(const float* __restrict__ A,
 }
 
 // float32 projections on the matrix cores (v_mfma_f32_16x16x4_f32), float32
-// accumulation.  256 threads = 2 x 2 waves, each wave owns a (BM/2) x (BN/2)
-// block of 16 x 16 MFMA tiles.  K advances 32 at a time through a double-
+// accumulation.  NW_M x NW_N waves, each owning a (BM / NW_M) x (BN / NW_N)
+// block of 16 x 16 MFMA tiles; 128 x 128 tiles use 4 x 2 waves (two per
+// SIMD, which hides LDS and barrier latency behind the other wave's MFMAs).  K advances 32 at a time through a double-
 // buffered LDS tile.  Inside each group of 16 k, lane l supplies the four k
 // values 4 (l / 16) .. 4 (l / 16) + 3 of its row as one 16-byte LDS read, and
 // MFMA number kk uses element kk: A and B use the same k for the same (lane
 // group, kk), so the contraction covers all 16 k exactly once.  Rows in LDS
 // are padded to 36 floats, which spreads the 16 rows of one read over
 // distinct banks.
-template <int BM, int BN>
-__global__ __launch_bounds__(256) void proj_gemm_f32(const float* __restrict__ A,
-                                                     const float* __restrict__ B0,
-                                                     const float* __restrict__ B1, int K,
-                                                     int tiles_m, int tiles_n, int tn0,
-                                                     int group_m, ProjOut o) {
+template <int BM, int BN, int NW_M, int NW_N>
+__global__ __launch_bounds__(64 * NW_M * NW_N) void proj_gemm_f32(const float* __restrict__ A,
+                                                                  const float* __restrict__ B0,
+                                                                  const float* __restrict__ B1,
+                                                                  int K, int tiles_m, int tiles_n,
+                                                                  int tn0, int group_m, ProjOut o) {
     __shared__ __attribute__((aligned(16))) GemmLds<BM, BN> lds;
     int tm, tn;
     tile_coords(blockIdx.x, tiles_m, tiles_n, group_m, tm, tn);
     tn += tn0;
-    gemm_tile_f32<BM, BN>(A, B0, B1, K, tm * BM, tn * BN, o, lds);
+    gemm_tile_f32<BM, BN, NW_M, NW_N>(A, B0, B1, K, tm * BM, tn * BN, o, lds);
 }
 
 // float64 projections on the vector ALUs (MI355X runs float64 FMA on the
