@@ -208,6 +208,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched and warm-start measurements")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain elementwise copy of 256 MiB (reference for "
+                         "hardware byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -224,6 +227,13 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     E.lib()
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.add(src, 0.0, out=dst)     # reads 256 MiB, writes 256 MiB
+        torch.cuda.synchronize()
+        del src, dst
     pr = synth.gp_rbf()
     C, d, m = pr.n_chains, pr.d, pr.m
     s = E.Sampler(pr.A, pr.b, pr.x0, C, seed=0, precision=32, trim_eps=1e-6)
@@ -267,7 +277,9 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "gp_rbf", "d": d, "m": m, "chains": C,
-                   "storage": "f32", "roots": "f64", "trim_eps": 1e-6, "seed": 0},
+                   "storage": "f32", "projections": "f32 MFMA, f32 accumulate",
+                   "roots": "f32 atan2/acos for |b/r| <= 0.99, f64 near tangency",
+                   "interval_ends_and_sampling": "f64", "trim_eps": 1e-6, "seed": 0},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS,
                      "unit": "TFLOP/s",
                      "frac": (achieved / PEAK_FP32_MFMA_TFLOPS) if achieved else None,

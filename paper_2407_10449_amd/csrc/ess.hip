@@ -119,6 +119,7 @@ struct ess_ctx {
     int G = 1;
     hipStream_t gs[kMaxGroups] = {};
     hipEvent_t fork = nullptr, join[kMaxGroups] = {};
+    hipEvent_t stagger[kMaxGroups] = {};   // group g's per-chain kernel of a step is done
     std::vector<void*> allocs;
     // kernel timing (ess_profile)
     bool profiling = false;
@@ -316,7 +317,9 @@ void launch_sample_t(const ess_ctx* c, const Group& g, hipStream_t st, const Sam
     else if (rpt <= 4) hipLaunchKernelGGL((sample_bucket_kernel<T, 4, 2048>), grid, b, 0, st, a);
     else if (rpt <= 8) hipLaunchKernelGGL((sample_bucket_kernel<T, 8, 2048>), grid, b, 0, st, a);
     else hipLaunchKernelGGL((sample_bucket_kernel<T, 16, 2048>), grid, b, 0, st, a);
-    const dim3 fg(std::min(g.n, 768));
+    // the full-sort pass is usually empty: a small grid keeps its launch cheap,
+    // unless every chain takes it (ESS_SORT_FULL)
+    const dim3 fg(a.force_full ? std::min(g.n, 768) : std::min(g.n, 32));
     switch (c->nmax) {
         case 512: hipLaunchKernelGGL((fallback_kernel<T, 512>), fg, b, 0, st, a); break;
         case 1024: hipLaunchKernelGGL((fallback_kernel<T, 1024>), fg, b, 0, st, a); break;
@@ -473,8 +476,13 @@ ess_status issue_run(ess_ctx* c, int64_t n_steps, int64_t thin, void* trace, hip
             a[g].trace = (trace && s > 0 && s % thin == 0)
                              ? static_cast<char*>(trace) + (s / thin - 1) * trace_row
                              : nullptr;
+            // staggered groups: group g's per-chain kernel of step s starts after
+            // group g-1's, so it runs beside group g-1's projections (vector work
+            // beside matrix-core work) instead of beside its per-chain kernel
+            if (split && g > 0) HIP_TRY(hipStreamWaitEvent(sts[g], c->stagger[g - 1], 0));
             ESS_TRY(timed(c, ESS_KERNEL_SAMPLE, sts[g],
                           [&] { return launch_sample(c, gr[g], sts[g], a[g]); }));
+            if (split && g + 1 < c->G) HIP_TRY(hipEventRecord(c->stagger[g], sts[g]));
             ESS_TRY(timed(c, both ? ESS_KERNEL_PROJECT : ESS_KERNEL_OTHER, sts[g], [&] {
                 return launch_proj(c, gr[g], sts[g], c->Xprop, both ? COLS_BOTH : COLS_X, 0, 0);
             }));
@@ -544,7 +552,7 @@ ess_status launch_batched_step(const ess_ctx* c, const BatchArgs& a, hipStream_t
 }
 
 ess_status launch_batched_fallback(const ess_ctx* c, const BatchArgs& a, hipStream_t st) {
-    const dim3 g(std::min(c->batch->NC, 768)), b(256);
+    const dim3 g(std::min(c->batch->NC, 64)), b(256);
     switch (c->batch->nmax) {
         case 512: hipLaunchKernelGGL((batched_fallback_kernel<512>), g, b, 0, st, a); break;
         case 1024: hipLaunchKernelGGL((batched_fallback_kernel<1024>), g, b, 0, st, a); break;
@@ -1185,6 +1193,14 @@ ess_status ess_init(const ess_problem* pr, void* stream, ess_ctx** out) {
     } else {
         c->bm = c->bn = 64;
     }
+    if (const char* e = std::getenv("ESS_PROJ_TILE")) {   // "BMxBN", e.g. 64x128
+        int bm = 0, bn = 0;
+        if (std::sscanf(e, "%dx%d", &bm, &bn) == 2 && (bm == 64 || bm == 128) &&
+            (bn == 64 || bn == 128) && c->prec == 32) {
+            c->bm = bm;
+            c->bn = bn;
+        }
+    }
     c->nmax = 512;
     while (c->nmax < c->m) c->nmax <<= 1;
 
@@ -1219,6 +1235,7 @@ ess_status ess_init(const ess_problem* pr, void* stream, ess_ctx** out) {
         for (int g = 0; g < kMaxGroups && ee == hipSuccess; ++g) {
             ee = hipStreamCreateWithFlags(&c->gs[g], hipStreamNonBlocking);
             if (ee == hipSuccess) ee = hipEventCreateWithFlags(&c->join[g], hipEventDisableTiming);
+            if (ee == hipSuccess) ee = hipEventCreateWithFlags(&c->stagger[g], hipEventDisableTiming);
         }
         if (ee != hipSuccess) {
             fail(ESS_ERR_HIP, "creating group streams: %s", hipGetErrorString(ee));
@@ -1295,6 +1312,7 @@ void ess_destroy(ess_ctx* c) {
         if (c->gs[g]) (void)hipStreamSynchronize(c->gs[g]);
         if (c->gs[g]) (void)hipStreamDestroy(c->gs[g]);
         if (c->join[g]) (void)hipEventDestroy(c->join[g]);
+        if (c->stagger[g]) (void)hipEventDestroy(c->stagger[g]);
     }
     if (c->fork) (void)hipEventDestroy(c->fork);
     (void)drop_graphs(c);

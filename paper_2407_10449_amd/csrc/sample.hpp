@@ -87,6 +87,14 @@ constexpr double kKeyScale = 281474976710656.0 / kTwoPi;   // 2^48 / (2 pi)
 constexpr uint64_t kKeyMax = (1ull << 48) - 1;
 constexpr int SMAX = 128;   // survivors the bucket path resolves in place
 
+// T is the storage type of p and q.  With float storage the two angles tau
+// and phi come from float32 atan2 / acos while |b / r| <= 0.99: p and q are
+// exact floats, so atan2 is off by a few float ulps (< 1e-6 rad), and the
+// rounding of z to float moves acos by at most 6e-8 / sqrt(1 - 0.99^2)
+// (< 5e-7 rad).  Near tangency (|b / r| > 0.99, where acos amplifies
+// rounding without bound) both angles are taken in float64.  r, z, the wrap,
+// alpha, beta and every later comparison stay in float64.
+template <typename T>
 __device__ __forceinline__ bool solve_roots(double p, double q, double bi, double& al,
                                             double& be) {
     const double r = hypot(p, q);
@@ -94,8 +102,14 @@ __device__ __forceinline__ bool solve_roots(double p, double q, double bi, doubl
     double z = bi / r;
     if (!(z < 1.0)) return false;
     z = fmax(z, -1.0);
-    const double tau = atan2(q, p);
-    const double phi = acos(z);
+    double tau, phi;
+    if (sizeof(T) == 4 && fabs(z) <= 0.99) {
+        tau = static_cast<double>(atan2f(static_cast<float>(q), static_cast<float>(p)));
+        phi = static_cast<double>(acosf(static_cast<float>(z)));
+    } else {
+        tau = atan2(q, p);
+        phi = acos(z);
+    }
     double a = tau - phi;
     if (a < 0.0) a += kTwoPi;
     if (a >= kTwoPi) a = 0.0;
@@ -351,7 +365,7 @@ __device__ void full_chain(const ChainRef<T>& r, int sel, const FullLds& L) {
         bool hit = false;
         if (i < r.m) {
             const T p = Pc[i], q = r.q[i];
-            hit = solve_roots(static_cast<double>(p), static_cast<double>(q), r.b[i], al, be);
+            hit = solve_roots<T>(static_cast<double>(p), static_cast<double>(q), r.b[i], al, be);
             if (r.p_out) {
                 r.p_out[i] = p;
                 r.q_out[i] = q;
@@ -568,7 +582,7 @@ __device__ bool bucket_chain(const ChainRef<T>& r, int sel, BucketLds<NB>& L) {
         if (i < r.m) {
             const T p = Pc[i], q = r.q[i];
             double x0, x1;
-            if (solve_roots(static_cast<double>(p), static_cast<double>(q), r.b[i], x0, x1)) {
+            if (solve_roots<T>(static_cast<double>(p), static_cast<double>(q), r.b[i], x0, x1)) {
                 al[j] = x0;
                 be[j] = x1;
                 bk[j] = min(static_cast<int>(x0 * kBucket), NB - 1);

@@ -77,11 +77,14 @@ def test_explicit_transition_matches_oracle(E, name, d, m, C, precision, eps):
     fails, excused = compare_transition(Ab, b, x, nu, u, g, ref)
     assert not fails, "\n".join(fails[:10])
     assert excused <= max(1, len(u) // 20)
-    # tier 2: same projections -> intervals and theta agree to float64 rounding
+    # tier 2: same projections -> intervals and theta agree to the root solve's
+    # rounding: float64 trig in float64 mode; float32 trig away from tangency in
+    # float32 mode (a few 1e-7 rad, bounded here by 1e-5)
+    tol2 = 1e-9 if precision == 64 else 1e-5
     for c in range(len(u)):
         gi = pieces(g["intervals"][c], g["n_intervals"][c], 0.0)
-        assert intervals_match(gi, ref2["intervals"][c], 1e-9), (c, gi, ref2["intervals"][c])
-        assert abs(g["theta"][c] - ref2["theta"][c]) <= 1e-9 * max(1.0, len(gi)), c
+        assert intervals_match(gi, ref2["intervals"][c], tol2), (c, gi, ref2["intervals"][c])
+        assert abs(g["theta"][c] - ref2["theta"][c]) <= tol2 * max(1.0, len(gi)), c
 
 
 def test_explicit_full_size_gp_rbf(E):
@@ -94,7 +97,7 @@ def test_explicit_full_size_gp_rbf(E):
     assert not fails, "\n".join(fails[:10])
     for c in range(len(u)):
         gi = pieces(g["intervals"][c], g["n_intervals"][c], 0.0)
-        assert intervals_match(gi, ref2["intervals"][c], 1e-9)
+        assert intervals_match(gi, ref2["intervals"][c], 1e-5)
 
 
 def test_no_constraint_crosses_the_ellipse(E):
