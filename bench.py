@@ -122,81 +122,24 @@ def bench_batched(E, torch, steps=50, plain_steps=10):
 
 
 def bench_warm_start(E, torch, log):
-    """ESS/s: batched (one context over all problems of the family) with the
-    learned warm start, against plain per-problem contexts started at 0."""
+    """ESS/s at equal accuracy: batched + learned warm start against plain
+    per-problem contexts (and against the batched context started plain)."""
     import numpy as np
     import synth
-    from paper_2407_10449_amd import diagnostics as D
     from paper_2407_10449_amd import warmstart as W
     A, b0, draw = synth.warm_family()
     m, d = A.shape
     rng = np.random.default_rng(21)
     train_b, eval_b = draw(rng, 10000), draw(rng, 32)
-    X, Y, t_gen = W.generate_pairs(E, A, train_b, chains_per_b=1, burn=200, n_keep=10, thin=10)
+    X, Y, t_gen = W.generate_pairs(E, A, train_b, chains_per_b=1, burn=500, n_keep=10, thin=10)
     net = E.Mlp((m, 512, 512, d), seed=0)
     hist, t_train = W.train(net, X, Y, epochs=10, batch=1024, lr=1e-3)
-    ref_mean, ref_sd = W.reference_moments(E, A, eval_b, chains=64, burn=300, steps=1200, thin=4)
-    chains, T = 64, 120
-    mon = np.random.default_rng(0).choice(d, 64, replace=False)
-
-    def ess_total(tr, burn):
-        x = tr[burn:]
-        tot, worst = 0.0, 1e30
-        for j in range(len(eval_b)):
-            xj = x[:, j * chains:(j + 1) * chains, :]
-            e = D.min_ess(xj, mon)
-            tot += e
-            worst = min(worst, e)
-        return tot, worst
-
-    # plain per-problem: one context per b, x0 = 0
-    ctxs = [E.Sampler(A, b, np.zeros(d), chains, seed=100 + j, precision=32)
-            for j, b in enumerate(eval_b)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    trs = [q.run(T, count_rejections=False)[0] for q in ctxs]
-    torch.cuda.synchronize()
-    t_plain = time.perf_counter() - t0
-    plain_tr = torch.cat(trs, dim=1).double().cpu().numpy()
-    for q in ctxs:
-        q.close()
-    # batched + warm start: one context with a b per chain, gated network start
-    B = np.repeat(eval_b, chains, axis=0)
-    s = E.Sampler(A, B, np.zeros(d), B.shape[0], seed=7, precision=32)
-    bdev = torch.tensor(eval_b, dtype=torch.float32, device="cuda")
-    zeros = torch.zeros(B.shape[0], d, device="cuda")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    xhat = net.forward(bdev).repeat_interleave(chains, dim=0)
-    acc = s.set_state_gated(xhat, zeros)
-    warm_tr_t, _ = s.run(T, count_rejections=False)
-    torch.cuda.synchronize()
-    t_warm = time.perf_counter() - t0
-    warm_tr = warm_tr_t.double().cpu().numpy()
-    s.close()
+    cmp = W.compare(E, A, eval_b, net, log=log)
     net.close()
-    x0w = (xhat.cpu().numpy() * acc[:, None])[None]
-    cp = W.burn_in_curve(np.concatenate([np.zeros((1, B.shape[0], d)), plain_tr]), 32, chains,
-                         ref_mean, ref_sd)
-    cw = W.burn_in_curve(np.concatenate([x0w, warm_tr]), 32, chains, ref_mean, ref_sd)
-    bp, bw = max(W.burn_in_steps(cp), 1), max(W.burn_in_steps(cw), 1)
-    ess_p, worst_p = ess_total(plain_tr, bp)
-    ess_w, worst_w = ess_total(warm_tr, bw)
-    # accuracy: posterior means after burn-in against the long reference
-    def max_z(tr, burn):
-        x = tr[burn:].reshape(tr.shape[0] - burn, 32, chains, d).mean(axis=(0, 2))
-        return float(np.abs(x - ref_mean).max() / (ref_sd.mean() / np.sqrt(chains * (tr.shape[0] - burn))) )
-    out = {"workload": "warm_family d=256 m=768, 32 held-out b x 64 chains, 120 steps",
-           "train_pairs": int(X.shape[0]), "train_gen_s": t_gen, "train_s": t_train,
-           "train_mse_first_last": [hist[0], hist[-1]],
-           "gate_accepted": float(acc.mean()),
-           "burn_in_steps": {"plain": bp, "warm": bw},
-           "plain_per_problem": {"ess": ess_p, "min_ess": worst_p, "wall_s": t_plain, "ess_per_s": ess_p / t_plain},
-           "batched_warm": {"ess": ess_w, "min_ess": worst_w, "wall_s": t_warm, "ess_per_s": ess_w / t_warm},
-           "ess_per_s_ratio": (ess_w / t_warm) / (ess_p / t_plain),
-           "accuracy_max_z_vs_reference": {"plain": max_z(plain_tr, bp), "warm": max_z(warm_tr, bw)}}
-    log(f"warm start: {out}")
-    return out
+    cmp.update({"workload": "warm_family d=256 m=768: 32 held-out b x 64 chains, 4000 steps each",
+                "train_samples": int(X.shape[0]), "train_gen_s": t_gen, "train_s": t_train,
+                "train_mse_before_after": [hist[0], hist[-1]]})
+    return cmp
 
 
 def main():

@@ -71,17 +71,35 @@ def train(net, inputs, targets, epochs=20, batch=1024, lr=1e-3, seed=0, log=None
     return history, time.perf_counter() - t0
 
 
-def reference_moments(E, A, bs, chains=64, burn=500, steps=2000, thin=4, seed=1):
-    """Long plain runs: per b, the mean and sd of every coordinate."""
+def reference_moments(E, A, bs, chains=64, burn=500, steps=2000, thin=4, seed=1, segment=2000):
+    """Long plain runs: per b, the mean and sd of every coordinate over all
+    chains and recorded steps (float64 sums on the device, `segment` steps at
+    a time, so the trace never has to be held whole)."""
+    import torch
     m, d = A.shape
+    nb = len(bs)
     B = _per_chain_b(bs, chains)
     s = E.Sampler(A, B, np.zeros(d), B.shape[0], seed=seed, precision=32)
     s.run(burn, keep_trace=False, count_rejections=False)
-    tr, _ = s.run(steps, thin=thin, count_rejections=False)
+    s1 = torch.zeros(nb, d, dtype=torch.float64, device="cuda")
+    s2 = torch.zeros_like(s1)
+    n = 0
+    left = steps
+    while left > 0:
+        k = min(segment, left)
+        k -= k % thin
+        if k == 0:
+            break
+        tr, _ = s.run(k, thin=thin, count_rejections=False)
+        x = tr.double().reshape(tr.shape[0], nb, chains, d)
+        s1 += x.sum(dim=(0, 2))
+        s2 += (x * x).sum(dim=(0, 2))
+        n += tr.shape[0] * chains
+        left -= k
     s.close()
-    x = tr.double().cpu().numpy().reshape(tr.shape[0], len(bs), chains, d)
-    flat = x.transpose(1, 0, 2, 3).reshape(len(bs), -1, d)
-    return flat.mean(axis=1), flat.std(axis=1)
+    mean = s1 / n
+    var = (s2 / n - mean * mean).clamp_min(0.0)
+    return mean.cpu().numpy(), var.sqrt().cpu().numpy()
 
 
 def burn_in_curve(trace, bs_count, chains, ref_mean, ref_sd):
@@ -98,3 +116,106 @@ def burn_in_steps(curve, level=2.0):
     """First step from which the curve stays at or below `level`."""
     above = np.nonzero(curve > level)[0]
     return 0 if above.size == 0 else int(above[-1] + 1)
+
+
+def burn_in_excess(curve):
+    """Threshold-free initialisation bias: sum over steps of max(D_t - 1, 0)."""
+    return float(np.maximum(np.asarray(curve) - 1.0, 0.0).sum())
+
+
+def compare(E, A, eval_b, net, chains=64, burn_window=1000, steps=4000, thin=4, ref=None,
+            seed=0, log=None):
+    """ESS/s at equal accuracy for three ways to sample the posteriors of `eval_b`:
+      plain_per_problem  one context per b (`chains` chains each), started at 0
+      batched_plain      one context over all b's (a b per chain), started at 0
+      batched_warm       the same context started at the gated network prediction
+    Every arm runs `steps` steps, recorded every `thin` steps, in the same wall
+    time budget.  The burn-in curve D_t (`burn_in_curve`) over the first
+    `burn_window` steps fixes each arm's burn-in: the first recorded step with
+    D_t <= 1.25 x the median of D over the window's last quarter (the arm's
+    stationary level).  Each arm discards its own burn-in; ESS counts the rest
+    (bulk ESS, minimum over 64 monitored coordinates and |x|^2, summed over
+    problems).  Wall time covers inference, gating and every step.  Accuracy:
+    the largest |posterior mean - reference| / MCSE over problems and the first
+    16 monitored coordinates."""
+    import torch
+    from . import diagnostics as D
+    m, d = A.shape
+    nb = len(eval_b)
+    if ref is None:
+        ref = reference_moments(E, A, eval_b, chains=chains, burn=4000, steps=40000, thin=10,
+                                seed=seed + 1)
+    ref_mean, ref_sd = ref
+    mon = np.sort(np.random.default_rng(seed).choice(d, min(d, 64), replace=False))
+    mon_t = torch.as_tensor(mon, device="cuda")
+    B = np.repeat(eval_b, chains, axis=0)
+    nwin = burn_window // thin
+    out = {}
+
+    def reduce(tr):
+        """Burn-in window (full states) and the monitored coordinates plus |x|^2
+        of the whole trace, float64 on the host."""
+        win = tr[:nwin].double().cpu().numpy()
+        sub = tr.index_select(2, mon_t).double()
+        sq = (tr.double() ** 2).sum(dim=2, keepdim=True)
+        return win, torch.cat([sub, sq], dim=2).cpu().numpy()
+
+    def finish(name, win, mon_x, wall, x0):
+        curve = burn_in_curve(np.concatenate([x0[None], win]), nb, chains, ref_mean, ref_sd)
+        level = float(np.median(curve[-max(1, len(curve) // 4):]))
+        first = int(np.nonzero(curve <= 1.25 * level)[0][0])   # the last quarter qualifies
+        x = mon_x[max(first - 1, 0):]                          # curve[k] is after k * thin steps
+        ess, worst, zmax = 0.0, 1e30, 0.0
+        for j in range(nb):
+            xj = x[:, j * chains:(j + 1) * chains, :]
+            e = min(D.ess(xj[:, :, k]) for k in range(xj.shape[2]))
+            ess += e
+            worst = min(worst, e)
+            for k in range(16):
+                se = D.mcse_mean(xj[:, :, k])
+                zmax = max(zmax, abs(xj[:, :, k].mean() - ref_mean[j, mon[k]]) / max(se, 1e-12))
+        out[name] = {"burn_in_steps": first * thin, "stationary_D": level,
+                     "burn_in_excess": burn_in_excess(curve) * thin, "D_0": float(curve[0]),
+                     "ess": ess, "min_ess_per_problem": worst, "wall_s": wall,
+                     "ess_per_s": ess / wall, "max_z_mean_vs_reference": float(zmax)}
+        if log:
+            log(f"{name}: {out[name]}")
+
+    ctxs = [E.Sampler(A, b, np.zeros(d), chains, seed=seed + 100 + j, precision=32)
+            for j, b in enumerate(eval_b)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    trs = [q.run(steps, thin=thin, count_rejections=False)[0] for q in ctxs]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for q in ctxs:
+        q.close()
+    win, mon_x = reduce(torch.cat(trs, 1))
+    del trs
+    finish("plain_per_problem", win, mon_x, wall, np.zeros((B.shape[0], d)))
+
+    for name in ("batched_plain", "batched_warm"):
+        s = E.Sampler(A, B, np.zeros(d), B.shape[0], seed=seed + 7, precision=32)
+        bdev = torch.tensor(eval_b, dtype=torch.float32, device="cuda")
+        zeros = torch.zeros(B.shape[0], d, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x0 = np.zeros((B.shape[0], d))
+        if name == "batched_warm":
+            xhat = net.forward(bdev).repeat_interleave(chains, dim=0)
+            acc = s.set_state_gated(xhat, zeros)
+        tr, _ = s.run(steps, thin=thin, count_rejections=False)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        if name == "batched_warm":
+            x0 = xhat.double().cpu().numpy() * acc[:, None]
+            out["gate_accepted"] = float(acc.mean())
+        s.close()
+        win, mon_x = reduce(tr)
+        del tr
+        finish(name, win, mon_x, wall, x0)
+    out["ess_per_s_batched_warm_over_plain_per_problem"] = (
+        out["batched_warm"]["ess_per_s"] / out["plain_per_problem"]["ess_per_s"])
+    out["ess_per_s_batched_warm_over_batched_plain"] = (
+        out["batched_warm"]["ess_per_s"] / out["batched_plain"]["ess_per_s"])
+    return out
