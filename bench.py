@@ -82,22 +82,27 @@ def cpu_baseline(pr, seconds, n_chains=64):
 
 
 def bench_batched(E, torch, steps=50, plain_steps=10):
-    """256 uneven polytopes x 64 chains: one persistent launch per step, against
-    one context per problem run one after another."""
+    """256 uneven polytopes x 64 chains: one launch per step (tile shapes from
+    the autotuner), against one context per problem run one after another."""
     import synth
     probs = synth.batched_uneven()
     spec = [dict(A=p.A, b=p.b, x0=p.x0, n_chains=p.n_chains, seed=i, trim_eps=1e-6)
             for i, p in enumerate(probs)]
     C = sum(p.n_chains for p in probs)
     s = E.BatchedSampler(spec)
-    E.ess_run(s.ctx, 5, 1, None, False)
+    report = E.ess_autotune(s.ctx, 10)
+    E.ess_run(s.ctx, steps, 1, None, False)          # capture the graph, warm up
     torch.cuda.synchronize()
-    E.ess_profile(s.ctx, True)
     t0 = time.perf_counter()
-    E.ess_run(s.ctx, steps, 1, None, False)
+    E.ess_run(s.ctx, steps, 1, None, False)          # timed: a graph replay
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    k_ms, k_n = E.ess_profile_read(s.ctx, E.ESS_KERNEL_BATCHED)
+    E.ess_profile(s.ctx, True)                       # kernel durations: launched one by one
+    E.ess_run(s.ctx, steps, 1, None, False)
+    fused_ms, fused_n = E.ess_profile_read(s.ctx, E.ESS_KERNEL_BATCHED)
+    tile_ms, tile_n = E.ess_profile_read(s.ctx, E.ESS_KERNEL_PROJECT)
+    chain_ms, chain_n = E.ess_profile_read(s.ctx, E.ESS_KERNEL_SAMPLE)
+    E.ess_profile(s.ctx, False)
     s.close()
     singles = [E.Sampler(p.A, p.b, p.x0, p.n_chains, seed=i, precision=32)
                for i, p in enumerate(probs)]
@@ -112,13 +117,16 @@ def bench_batched(E, torch, steps=50, plain_steps=10):
     for q in singles:
         q.close()
     flops = sum(4.0 * p.m * p.d * p.n_chains for p in probs)
+    kernels = ({"fused_step_ms": fused_ms / fused_n} if fused_n else
+               {"tiles_ms": tile_ms / max(tile_n, 1), "chains_ms": chain_ms / max(chain_n, 1),
+                "projection_tflops": flops / (tile_ms / max(tile_n, 1) / 1e3) / 1e12 if tile_n else None})
     return {"workload": "batched_uneven: 256 polytopes, d log-uniform [16,512], m = d U{1..4}, 64 chains each",
             "chain_steps_per_s": C * steps / dt,
             "ms_per_step": dt * 1e3 / steps,
-            "persistent_step_ms": k_ms / max(k_n, 1),
-            "projection_tflops_in_step": flops / (k_ms / max(k_n, 1) / 1e3) / 1e12 if k_n else None,
+            "kernels_per_step": kernels,
             "per_problem_chain_steps_per_s": C * plain_steps / dt1,
-            "speedup_vs_per_problem": (C * steps / dt) / (C * plain_steps / dt1)}
+            "speedup_vs_per_problem": (C * steps / dt) / (C * plain_steps / dt1),
+            "autotune": report.strip().splitlines()[-1]}
 
 
 def bench_warm_start(E, torch, log):
@@ -136,7 +144,7 @@ def bench_warm_start(E, torch, log):
     hist, t_train = W.train(net, X, Y, epochs=10, batch=1024, lr=1e-3)
     cmp = W.compare(E, A, eval_b, net, log=log)
     net.close()
-    cmp.update({"workload": "warm_family d=256 m=768: 32 held-out b x 64 chains, 4000 steps each",
+    cmp.update({"workload": "warm_family d=256 m=768: 32 held-out b x 64 chains, 12000 steps each",
                 "train_samples": int(X.shape[0]), "train_gen_s": t_gen, "train_s": t_train,
                 "train_mse_before_after": [hist[0], hist[-1]]})
     return cmp

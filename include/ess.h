@@ -149,15 +149,17 @@ ess_status ess_transition_explicit(ess_ctx* ctx, const void* x, const void* nu,
  * theta uniforms u (n_chains double, nullable).  Does not change the context. */
 ess_status ess_draw(ess_ctx* ctx, uint64_t step, void* nu, double* u);
 
-/* Autotuner.  Times each candidate configuration on this context for
- * 2 x steps_per_trial steps (single problem: chain groups x projection tile
- * shape x XCD band height; batched: persistent grid size), keeps the fastest,
- * and stores it in a JSON cache keyed by GPU architecture and problem shape
- * ($ESS_TUNE_CACHE, default ~/.cache/ess_tune.json), which later contexts of
- * the same shape load at init.  The chains' state and step counter are
- * restored afterwards.  report (host, nullable) receives one line per trial.
- * Currently offered for batched contexts only; a single-problem context returns
- * ESS_ERR_UNSUPPORTED. */
+/* Autotuner for batched contexts (ess_init_batched).  Problems fall into six
+ * size classes (d <= 64, d <= 192, d > 192, each split at m <= 256); each
+ * class has its own projection tile shape (64x64, 32x64, 64x32 or 32x32 rows
+ * x chain columns).  One pass of coordinate descent times every shape of
+ * every class present, the other classes fixed, each trial 2 x steps_per_trial
+ * steps (the first captures and warms the graph, the second is timed), keeps
+ * the fastest, and stores it in a JSON cache keyed by GPU architecture and
+ * workload ($ESS_TUNE_CACHE, default ~/.cache/ess_tune.json), which later
+ * batched contexts of the same workload load at init.  The chains' state and
+ * step counter are restored afterwards.  report (host, nullable) receives one
+ * line per trial.  A single-problem context returns ESS_ERR_UNSUPPORTED. */
 ess_status ess_autotune(ess_ctx* ctx, int32_t steps_per_trial, char* report, int32_t report_len);
 
 /* Kernel timing for measurement.  While enabled, every launch made by ess_run

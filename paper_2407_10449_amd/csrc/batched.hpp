@@ -1,15 +1,31 @@
 // Many independent polytopes of uneven size advanced together.
 //
-// One persistent launch per step.  Its work queue holds first every projection
-// tile of every problem (A x' for the previous proposals and A nu for this
-// step, Section 2 and 3.3), then one item per chain (commit the previous
-// proposal; roots, active intervals, theta and move as in the single-problem
-// kernels).  Workgroups take items from a device counter in queue order.  A
-// chain item waits until all tiles of its problem have been released: every
-// tile is taken before any chain item, and a taken tile belongs to a running
-// workgroup, so the wait ends (a spin limit turns a broken invariant into an
-// error flag instead of a hang).  Queue and tile counters are indexed by step
-// parity; each launch clears the other parity's counters for the next one.
+// Work per step: every projection tile of every problem (A x' for the
+// previous proposals and A nu for this step, Section 2 and 3.3), then one item
+// per chain (commit the previous proposal; roots, active intervals, theta and
+// move as in the single-problem kernels).  Two launch forms give the same
+// results:
+//
+// * split (batched_proj_kernel, then batched_chain_kernel): the kernel
+//   boundary makes the tiles' projections visible to the chains.  The tile
+//   order keeps each row panel of a problem's A on one XCD.
+// * fused (batched_step_kernel): one launch.  Every problem owns a run of
+//   workgroups, one per tile and one per chain; the tile runs of all problems
+//   come first in the grid, then the chain runs.  A workgroup takes its item
+//   from its problem's own ticket counter when it starts: tickets below the
+//   problem's tile count are tiles, the rest chains.  A chain waits until all
+//   tiles of its problem are released.  The tiles hold smaller tickets, and a
+//   ticket is only ever held by a running workgroup, so the wait ends whatever
+//   order the hardware starts workgroups in (a spin limit turns a broken
+//   invariant into an error flag instead of a hang).  Counters per problem
+//   keep the atomics spread out.  Ticket and tile counters are indexed by step
+//   parity; the workgroup holding a problem's ticket 0 clears that problem's
+//   counters of the other parity for the next launch.
+//
+// The fused form pays for its device-scope release / acquire pairs: on a part
+// whose XCDs have separate L2 caches they write back and invalidate L2, per
+// workgroup.  The split form pays one kernel boundary instead and is the
+// default; the autotuner times both.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -19,11 +35,19 @@
 
 namespace ess {
 
-constexpr int kBatchBM = 64, kBatchBN = 64;
+// Projection tile shapes, chosen per problem: 0 = 64 x 64, 1 = 32 x 64,
+// 2 = 64 x 32, 3 = 32 x 32 (rows of A x chain columns).  Rows are padded to
+// 64 and chains to 64, so every shape tiles the padded blocks exactly.
+constexpr int kBatchShapes = 4;
+constexpr int kBatchPadM = 64, kBatchPadC = 64;
+__host__ __device__ constexpr int shape_bm(int s) { return (s & 1) ? 32 : 64; }
+__host__ __device__ constexpr int shape_bn(int s) { return (s & 2) ? 32 : 64; }
 
 struct ProbDesc {
     int d, m, C, dp, mp, Cp;
-    int ntiles;          // projection tiles of this problem (both column halves)
+    int shape;           // projection tile shape (see shape_bm / shape_bn)
+    int tiles_n;         // tile columns: 2 Cp / shape_bn(shape)
+    int ntiles;          // tiles: ceil(m / shape_bm(shape)) x tiles_n
     int chain_off;       // first padded chain index (sel / flag / rej)
     long long a_off;     // A pack: mp x dp block
     long long b_off;     // b pack: m
@@ -38,8 +62,10 @@ struct ProbDesc {
 struct BatchArgs {
     int n_probs, NT, NC;
     const ProbDesc* descs;
-    const int4* tiles;     // (problem, tile row, tile column, 0)
-    const int2* chains;    // (problem, chain)
+    const int* wg_prob;    // [NT + NC]: the problem of each workgroup of the step launch
+    const int4* tiles;     // [NTL]: (problem, tile row, tile column, 0) or (-1, ...) padding
+    int NTL;               // entries of the tile table (NT plus padding)
+    const int2* chains;    // [NC]: (problem, chain) in the caller's order
     const float* A;
     const double* b;
     float* X;
@@ -50,9 +76,9 @@ struct BatchArgs {
     int* sel;
     int* flag;
     long long* rej;
-    int* queue;            // [2]
-    int* done;             // [2][n_probs]
-    int* fb_list;          // [total chains]: global chain-table indices
+    int* tickets;          // [2][n_probs]
+    int* done;             // [2][n_probs]: released tiles
+    int2* fb_list;         // [NC]: (problem, chain) handed to the full sort
     int* fb_count;         // [2]
     int* error;            // [1]: set when a wait exceeds its spin limit
     uint32_t step;         // relative to *step_base
@@ -120,21 +146,37 @@ __device__ __forceinline__ ChainRef<float> batch_ref(const BatchArgs& a, const P
     return r;
 }
 
-// Tile `t` of the batch (skipped when outside the selected column half).
-__device__ __forceinline__ void batch_tile(const BatchArgs& a, int4 t,
-                                           GemmLds<kBatchBM, kBatchBN>& L) {
-    const ProbDesc& pd = a.descs[t.x];
-    const int n0 = t.z * kBatchBN;
+union BatchGemmLds {
+    GemmLds<64, 64> s0;
+    GemmLds<32, 64> s1;
+    GemmLds<64, 32> s2;
+    GemmLds<32, 32> s3;
+};
+
+// Tile (tm, tn) of problem pd in its own shape (skipped when outside the
+// selected column half).
+__device__ __forceinline__ void batch_tile(const BatchArgs& a, const ProbDesc& pd, int tm, int tn,
+                                           BatchGemmLds& L) {
+    const int bm = shape_bm(pd.shape), bn = shape_bn(pd.shape);
+    const int n0 = tn * bn;
     const bool nu_half = n0 >= pd.Cp;
     if ((a.cols == 0 && nu_half) || (a.cols == 1 && !nu_half)) return;
     const ProjOut o = batch_proj_out(a, pd);
-    gemm_tile_f32<kBatchBM, kBatchBN>(a.A + pd.a_off, a.Xprop + pd.x_off, a.N + pd.x_off, pd.dp,
-                                      t.y * kBatchBM, n0, o, L);
+    const float* A = a.A + pd.a_off;
+    const float* B0 = a.Xprop + pd.x_off;
+    const float* B1 = a.N + pd.x_off;
+    const int m0 = tm * bm;
+    switch (pd.shape) {
+        case 0: gemm_tile_f32<64, 64>(A, B0, B1, pd.dp, m0, n0, o, L.s0); break;
+        case 1: gemm_tile_f32<32, 64>(A, B0, B1, pd.dp, m0, n0, o, L.s1); break;
+        case 2: gemm_tile_f32<64, 32>(A, B0, B1, pd.dp, m0, n0, o, L.s2); break;
+        default: gemm_tile_f32<32, 32>(A, B0, B1, pd.dp, m0, n0, o, L.s3); break;
+    }
 }
 
 template <int NB>
 union BatchLds {
-    GemmLds<kBatchBM, kBatchBN> g;
+    BatchGemmLds g;
     BucketLds<NB> b;
 };
 
@@ -144,49 +186,63 @@ __global__ __launch_bounds__(256) void batched_step_kernel(BatchArgs a) {
     __shared__ int s_item;
     const int tid = threadIdx.x;
     const int par = static_cast<int>(abs_step(a) & 1u);
-    const int total = a.NT + a.NC;
-    for (;;) {
-        if (tid == 0) s_item = atomicAdd(a.queue + par, 1);
+    const int p = a.wg_prob[blockIdx.x];
+    const ProbDesc& pd = a.descs[p];
+    if (tid == 0) s_item = atomicAdd(a.tickets + par * a.n_probs + p, 1);
+    if (blockIdx.x == 0 && tid == 0) a.fb_count[par ^ 1] = 0;   // the next launch's list
+    __syncthreads();
+    const int item = __builtin_amdgcn_readfirstlane(s_item);
+    if (item == 0 && tid == 0) {                                 // the next launch's counters
+        a.tickets[(par ^ 1) * a.n_probs + p] = 0;
+        a.done[(par ^ 1) * a.n_probs + p] = 0;
+    }
+    if (item < pd.ntiles) {
+        batch_tile(a, pd, item / pd.tiles_n, item % pd.tiles_n, lds.g);
+        // every wave publishes its own stores before the barrier (a barrier
+        // alone does not wait for them), then one release counts the tile
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();
-        const int item = s_item;
-        __syncthreads();
-        if (item >= total) break;
-        if (item == 0 && tid == 0) {
-            a.queue[par ^ 1] = 0;            // the next launch's queue
-            a.fb_count[par ^ 1] = 0;         // and its full-sort list
-        }
-        if (item < a.NT) {
-            const int4 t = a.tiles[item];
-            batch_tile(a, t, lds.g);
-            if (tid == 0) {
-                __threadfence();
-                atomicAdd(a.done + par * a.n_probs + t.x, 1);
-            }
-        } else {
-            const int2 ch = a.chains[item - a.NT];
-            const ProbDesc& pd = a.descs[ch.x];
-            if (tid == 0) {
-                int* cnt = a.done + par * a.n_probs + ch.x;
-                long spins = 0;
-                while (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < pd.ntiles) {
-                    __builtin_amdgcn_s_sleep(2);
-                    if (++spins > (1l << 26)) {
-                        atomicExch(a.error, 1);
-                        break;
-                    }
-                }
-                __threadfence();
-                if (ch.y == 0) a.done[(par ^ 1) * a.n_probs + ch.x] = 0;   // next launch
-            }
-            __syncthreads();
-            const ChainRef<float> r = batch_ref(a, pd, ch.x, ch.y);
-            const int sel = a.has_pending ? commit_chain<float>(r) : *r.sel;
-            if (a.do_sample) {
-                const bool ok = bucket_chain<float, RPT, NB>(r, sel, lds.b);
-                if (!ok && tid == 0) a.fb_list[atomicAdd(a.fb_count + par, 1)] = item - a.NT;
+        if (tid == 0)
+            __hip_atomic_fetch_add(a.done + par * a.n_probs + p, 1, __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        return;
+    }
+    const int c = item - pd.ntiles;
+    if (c >= pd.C) return;   // the grid holds exactly ntiles + C workgroups per problem
+    if (tid == 0) {
+        int* cnt = a.done + par * a.n_probs + p;
+        long spins = 0;
+        while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < pd.ntiles) {
+            __builtin_amdgcn_s_sleep(2);
+            if (++spins > (1l << 26)) {
+                atomicExch(a.error, 1);
+                break;
             }
         }
-        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // one acquire, after the wait
+    }
+    __syncthreads();
+    const ChainRef<float> r = batch_ref(a, pd, p, c);
+    const int sel = a.has_pending ? commit_chain<float>(r) : *r.sel;
+    if (a.do_sample) {
+        const bool ok = bucket_chain<float, RPT, NB>(r, sel, lds.b);
+        if (!ok && tid == 0) a.fb_list[atomicAdd(a.fb_count + par, 1)] = make_int2(p, c);
+    }
+}
+
+// Split form, second launch: one workgroup per chain (the caller's order).
+template <int RPT, int NB>
+__global__ __launch_bounds__(256) void batched_chain_kernel(BatchArgs a) {
+    __shared__ __attribute__((aligned(16))) BucketLds<NB> lds;
+    const int par = static_cast<int>(abs_step(a) & 1u);
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.fb_count[par ^ 1] = 0;   // the next step's list
+    const int2 ch = a.chains[blockIdx.x];
+    const ProbDesc& pd = a.descs[ch.x];
+    const ChainRef<float> r = batch_ref(a, pd, ch.x, ch.y);
+    const int sel = a.has_pending ? commit_chain<float>(r) : *r.sel;
+    if (a.do_sample) {
+        const bool ok = bucket_chain<float, RPT, NB>(r, sel, lds);
+        if (!ok && threadIdx.x == 0) a.fb_list[atomicAdd(a.fb_count + par, 1)] = ch;
     }
 }
 
@@ -197,17 +253,20 @@ __global__ __launch_bounds__(256) void batched_fallback_kernel(BatchArgs a) {
     const int par = static_cast<int>(abs_step(a) & 1u);
     const int count = a.fb_count[par];
     for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
-        const int2 ch = a.chains[a.fb_list[idx]];
+        const int2 ch = a.fb_list[idx];
         const ChainRef<float> r = batch_ref(a, a.descs[ch.x], ch.x, ch.y);
         full_chain<float>(r, *r.sel, full_lds);
         __syncthreads();
     }
 }
 
-// Projection tiles only, one block per tile (state checks outside a run).
+// Projection tiles, one block per entry of the tile table (split form, and
+// the state checks outside a run).
 __global__ __launch_bounds__(256) void batched_proj_kernel(BatchArgs a) {
-    __shared__ __attribute__((aligned(16))) GemmLds<kBatchBM, kBatchBN> lds;
-    batch_tile(a, a.tiles[blockIdx.x], lds);
+    __shared__ __attribute__((aligned(16))) BatchGemmLds lds;
+    const int4 t = a.tiles[blockIdx.x];
+    if (t.x < 0) return;   // padding that keeps the XCD assignment of the order
+    batch_tile(a, a.descs[t.x], t.y, t.z, lds);
 }
 
 // nu of `step` for every chain of the batch (one block per chain).

@@ -72,6 +72,9 @@ __global__ void broadcast_rows(const T* __restrict__ src, T* __restrict__ dst, i
 }  // namespace
 
 constexpr int kMaxGroups = 4;
+// size classes of batched problems for the tile-shape choice:
+// d <= 64, d <= 192, d > 192, each split at m <= 256
+constexpr int kTileBuckets = 6;
 
 // A contiguous block of chains with its own stream during ess_run: chains
 // [c0, c0 + n) valid, padded to Cg (a multiple of every projection tile width).
@@ -129,13 +132,19 @@ struct ess_ctx {
     long long prof_n[4] = {0, 0, 0, 0};
     // many problems advanced together (ess_init_batched)
     struct Batch {
-        int n = 0, NT = 0, NC = 0, rpt = 1, nb = 256, nmax = 512, grid = 256;
+        int n = 0, NT = 0, NTL = 0, NC = 0, rpt = 1, nb = 256, nmax = 512;
+        bool fused = false;          // one launch per step instead of tiles, then chains
         long long state_elems = 0;   // sum of C d (caller layout)
         int chains_padded = 0;
+        int max_tiles = 0;           // NT with the smallest tiles everywhere
+        int max_table = 0;           // tile table capacity (max_tiles plus XCD padding)
+        int bucket_shape[kTileBuckets] = {};   // tile shape of each size class
         std::vector<ProbDesc> h;
+        std::vector<int> order;      // problems by decreasing projection work
         ProbDesc* descs = nullptr;
-        int4* tiles = nullptr;
-        int2* chains = nullptr;
+        int* wg_prob = nullptr;      // [max_tiles + NC]
+        int4* tiles = nullptr;       // [max_table]
+        int2* chains = nullptr;      // [NC], the caller's order
         float* A = nullptr;
         float* X = nullptr;
         float* Xprop = nullptr;
@@ -143,9 +152,8 @@ struct ess_ctx {
         float* P = nullptr;
         float* Q = nullptr;
         double* b = nullptr;
-        int* counters = nullptr;   // queue[2], fb_count[2], error[1], done[2 n]
-        int* fb_list = nullptr;
-        int2* caller_chains = nullptr;   // chains in the caller's problem order
+        int* counters = nullptr;   // fb_count[2], error[1], tickets[2 n], done[2 n]
+        int2* fb_list = nullptr;
     };
     std::unique_ptr<Batch> batch;
 
@@ -514,7 +522,9 @@ BatchArgs batch_args(const ess_ctx* c) {
     a.NT = B.NT;
     a.NC = B.NC;
     a.descs = B.descs;
+    a.wg_prob = B.wg_prob;
     a.tiles = B.tiles;
+    a.NTL = B.NTL;
     a.chains = B.chains;
     a.A = B.A;
     a.b = B.b;
@@ -526,29 +536,43 @@ BatchArgs batch_args(const ess_ctx* c) {
     a.sel = c->sel;
     a.flag = c->flag;
     a.rej = c->rej;
-    a.queue = B.counters;
-    a.fb_count = B.counters + 2;
-    a.error = B.counters + 4;
-    a.done = B.counters + 5;
+    a.fb_count = B.counters;
+    a.error = B.counters + 2;
+    a.tickets = B.counters + 3;
+    a.done = B.counters + 3 + 2 * B.n;
     a.fb_list = B.fb_list;
     a.step_base = c->d_step;
     return a;
 }
 
 template <int RPT, int NB>
-void launch_step_t(const ess_ctx* c, const BatchArgs& a, hipStream_t st) {
-    hipLaunchKernelGGL((batched_step_kernel<RPT, NB>), dim3(c->batch->grid), dim3(256), 0, st, a);
+ess_status launch_step_t(ess_ctx* c, const BatchArgs& a, hipStream_t st) {
+    const ess_ctx::Batch& B = *c->batch;
+    if (B.fused)
+        return timed(c, ESS_KERNEL_BATCHED, st, [&] {
+            hipLaunchKernelGGL((batched_step_kernel<RPT, NB>), dim3(a.NT + a.NC), dim3(256), 0, st, a);
+            HIP_TRY(hipGetLastError());
+            return ESS_OK;
+        });
+    ESS_TRY(timed(c, ESS_KERNEL_PROJECT, st, [&] {
+        hipLaunchKernelGGL(batched_proj_kernel, dim3(a.NTL), dim3(256), 0, st, a);
+        HIP_TRY(hipGetLastError());
+        return ESS_OK;
+    }));
+    return timed(c, ESS_KERNEL_SAMPLE, st, [&] {
+        hipLaunchKernelGGL((batched_chain_kernel<RPT, NB>), dim3(a.NC), dim3(256), 0, st, a);
+        HIP_TRY(hipGetLastError());
+        return ESS_OK;
+    });
 }
 
-ess_status launch_batched_step(const ess_ctx* c, const BatchArgs& a, hipStream_t st) {
+ess_status launch_batched_step(ess_ctx* c, const BatchArgs& a, hipStream_t st) {
     const ess_ctx::Batch& B = *c->batch;
-    if (B.nb == 256) launch_step_t<1, 256>(c, a, st);
-    else if (B.rpt <= 2) launch_step_t<2, 2048>(c, a, st);
-    else if (B.rpt <= 4) launch_step_t<4, 2048>(c, a, st);
-    else if (B.rpt <= 8) launch_step_t<8, 2048>(c, a, st);
-    else launch_step_t<16, 2048>(c, a, st);
-    HIP_TRY(hipGetLastError());
-    return ESS_OK;
+    if (B.nb == 256) return launch_step_t<1, 256>(c, a, st);
+    if (B.rpt <= 2) return launch_step_t<2, 2048>(c, a, st);
+    if (B.rpt <= 4) return launch_step_t<4, 2048>(c, a, st);
+    if (B.rpt <= 8) return launch_step_t<8, 2048>(c, a, st);
+    return launch_step_t<16, 2048>(c, a, st);
 }
 
 ess_status launch_batched_fallback(const ess_ctx* c, const BatchArgs& a, hipStream_t st) {
@@ -572,7 +596,7 @@ ess_status batched_set_state_from_X(ess_ctx* c, const char* what) {
     a.cols = 0;
     a.p_direct = 1;
     a.strict = 1;
-    hipLaunchKernelGGL(batched_proj_kernel, dim3(B.NT), dim3(256), 0, c->st, a);
+    hipLaunchKernelGGL(batched_proj_kernel, dim3(B.NTL), dim3(256), 0, c->st, a);
     HIP_TRY(hipGetLastError());
     std::vector<int> fl(B.chains_padded);
     HIP_TRY(hipMemcpyAsync(fl.data(), c->flag, sizeof(int) * B.chains_padded, hipMemcpyDeviceToHost,
@@ -590,7 +614,7 @@ ess_status batched_set_state_from_X(ess_ctx* c, const char* what) {
 
 ess_status batched_issue(ess_ctx* c, int64_t n_steps, int64_t thin, void* trace, hipStream_t st) {
     ess_ctx::Batch& B = *c->batch;
-    const int ncnt = 5 + 2 * B.n;
+    const int ncnt = 3 + 4 * B.n;
     hipLaunchKernelGGL(zero_ints_n, dim3(std::min((ncnt + 255) / 256, 64)), dim3(256), 0, st,
                        B.counters, ncnt);
     HIP_TRY(hipGetLastError());
@@ -613,7 +637,7 @@ ess_status batched_issue(ess_ctx* c, int64_t n_steps, int64_t thin, void* trace,
         a.trace = (trace && s > 0 && s % thin == 0)
                       ? static_cast<float*>(trace) + (s / thin - 1) * row
                       : nullptr;
-        ESS_TRY(timed(c, ESS_KERNEL_BATCHED, st, [&] { return launch_batched_step(c, a, st); }));
+        ESS_TRY(launch_batched_step(c, a, st));
         if (a.do_sample)
             ESS_TRY(timed(c, ESS_KERNEL_OTHER, st, [&] { return launch_batched_fallback(c, a, st); }));
     }
@@ -623,9 +647,61 @@ ess_status batched_issue(ess_ctx* c, int64_t n_steps, int64_t thin, void* trace,
 ess_status batched_check_error(ess_ctx* c) {
     ess_ctx::Batch& B = *c->batch;
     int err = 0;
-    HIP_TRY(hipMemcpyAsync(&err, B.counters + 4, sizeof(int), hipMemcpyDeviceToHost, c->st));
+    HIP_TRY(hipMemcpyAsync(&err, B.counters + 2, sizeof(int), hipMemcpyDeviceToHost, c->st));
     HIP_TRY(hipStreamSynchronize(c->st));
     if (err) return fail(ESS_ERR_HIP, "batched step: a chain waited past its spin limit");
+    return ESS_OK;
+}
+
+int tile_bucket(const ProbDesc& d) {
+    const int db = d.d <= 64 ? 0 : (d.d <= 192 ? 1 : 2);
+    return 2 * db + (d.m > 256 ? 1 : 0);
+}
+
+// Tile counts, the workgroup -> problem table of the fused launch (all tile
+// runs, then all chain runs, problems by decreasing work) and the tile table
+// of the split launch and the state check, from the current shape of every
+// size class.  Workgroups go to the 8 XCDs round-robin by index, so table
+// entry 8 k + x runs on XCD x: each row panel of a problem (the tiles that
+// share its rows of A) is given whole to the XCD with the fewest tiles so
+// far, and the eight lists are padded to one length and interleaved.
+ess_status batched_layout(ess_ctx* c) {
+    constexpr int kXcds = 8;
+    ess_ctx::Batch& B = *c->batch;
+    for (auto& d : B.h) {
+        d.shape = B.bucket_shape[tile_bucket(d)];
+        d.tiles_n = 2 * d.Cp / shape_bn(d.shape);
+        d.ntiles = ((d.m + shape_bm(d.shape) - 1) / shape_bm(d.shape)) * d.tiles_n;
+    }
+    std::vector<int> wg;
+    std::vector<int4> lists[kXcds];
+    B.NT = 0;
+    for (int p : B.order) {
+        const ProbDesc& d = B.h[p];
+        wg.insert(wg.end(), d.ntiles, p);
+        B.NT += d.ntiles;
+        for (int tm = 0; tm < d.ntiles / d.tiles_n; ++tm) {
+            int x = 0;
+            for (int y = 1; y < kXcds; ++y)
+                if (lists[y].size() < lists[x].size()) x = y;
+            for (int tn = 0; tn < d.tiles_n; ++tn) lists[x].push_back(make_int4(p, tm, tn, 0));
+        }
+    }
+    for (int p : B.order) wg.insert(wg.end(), B.h[p].C, p);
+    size_t len = 0;
+    for (auto& l : lists) len = std::max(len, l.size());
+    std::vector<int4> table(kXcds * len, make_int4(-1, 0, 0, 0));
+    for (int x = 0; x < kXcds; ++x)
+        for (size_t k = 0; k < lists[x].size(); ++k) table[kXcds * k + x] = lists[x][k];
+    if (B.NT > B.max_tiles || static_cast<long long>(table.size()) > B.max_table)
+        return fail(ESS_ERR_INVALID_ARG, "batched layout: tile table overflow");
+    B.NTL = static_cast<int>(table.size());
+    HIP_TRY(hipMemcpyAsync(B.descs, B.h.data(), sizeof(ProbDesc) * B.n, hipMemcpyHostToDevice, c->st));
+    HIP_TRY(hipMemcpyAsync(B.wg_prob, wg.data(), sizeof(int) * wg.size(), hipMemcpyHostToDevice, c->st));
+    HIP_TRY(hipMemcpyAsync(B.tiles, table.data(), sizeof(int4) * table.size(), hipMemcpyHostToDevice,
+                           c->st));
+    // the host vectors go away at return: wait for the copies
+    HIP_TRY(hipStreamSynchronize(c->st));
     return ESS_OK;
 }
 
@@ -636,15 +712,16 @@ ess_status batched_init(ess_ctx* c, const ess_problem* pr, int n) {
     B.h.resize(n);
     long long a_off = 0, b_off = 0, x_off = 0, p_off = 0, q_off = 0, t_off = 0;
     int chain_off = 0, max_m = 1;
+    long long max_tiles = 0;
+    int max_panel = 0;
     for (int p = 0; p < n; ++p) {
         ProbDesc& d = B.h[p];
         d.d = pr[p].d;
         d.m = pr[p].m;
         d.C = pr[p].n_chains;
         d.dp = round_up(d.d, 32);
-        d.mp = round_up(d.m, kBatchBM);
-        d.Cp = round_up(d.C, kBatchBN);
-        d.ntiles = (d.mp / kBatchBM) * (2 * d.Cp / kBatchBN);
+        d.mp = round_up(d.m, kBatchPadM);
+        d.Cp = round_up(d.C, kBatchPadC);
         d.chain_off = chain_off;
         d.a_off = a_off;
         d.b_off = b_off;
@@ -662,39 +739,35 @@ ess_status batched_init(ess_ctx* c, const ess_problem* pr, int n) {
         t_off += static_cast<long long>(d.C) * d.d;
         chain_off += d.Cp;
         max_m = std::max(max_m, d.m);
+        max_tiles += static_cast<long long>(d.mp / 32) * (2 * d.Cp / 32);
+        max_panel = std::max(max_panel, 2 * d.Cp / 32);
+        if (max_tiles + chain_off > (1ll << 31) - 1)
+            return fail(ESS_ERR_UNSUPPORTED, "ess_init_batched: more than 2^31 - 1 work items");
     }
     B.state_elems = t_off;
     B.chains_padded = chain_off;
+    B.max_tiles = static_cast<int>(max_tiles);
+    // greedy by count: list lengths differ by at most one panel
+    B.max_table = static_cast<int>(max_tiles + 8ll * (max_panel + 1));
     B.rpt = (max_m + 255) / 256;
     B.nb = max_m <= 256 ? 256 : 2048;
     B.nmax = 512;
     while (B.nmax < max_m) B.nmax <<= 1;
-    // queue order: problems with the most projection work first, so their
-    // long tiles start early; chains follow in the same problem order
-    std::vector<int> order(n);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    // problems with the most projection work first, so their tiles start early
+    B.order.resize(n);
+    std::iota(B.order.begin(), B.order.end(), 0);
+    std::stable_sort(B.order.begin(), B.order.end(), [&](int x, int y) {
         return static_cast<long long>(B.h[x].mp) * B.h[x].dp * B.h[x].Cp >
                static_cast<long long>(B.h[y].mp) * B.h[y].dp * B.h[y].Cp;
     });
-    std::vector<int4> tiles;
     std::vector<int2> chains;
-    for (int p : order) {
-        const ProbDesc& d = B.h[p];
-        for (int tm = 0; tm < d.mp / kBatchBM; ++tm)
-            for (int tn = 0; tn < 2 * d.Cp / kBatchBN; ++tn) tiles.push_back(make_int4(p, tm, tn, 0));
-    }
-    for (int p : order)
-        for (int ch = 0; ch < B.h[p].C; ++ch) chains.push_back(make_int2(p, ch));
-    // the caller's chain order (problem by problem) for the state/trace copies
-    std::vector<int2> caller_chains;
     for (int p = 0; p < n; ++p)
-        for (int ch = 0; ch < B.h[p].C; ++ch) caller_chains.push_back(make_int2(p, ch));
-    B.NT = static_cast<int>(tiles.size());
+        for (int ch = 0; ch < B.h[p].C; ++ch) chains.push_back(make_int2(p, ch));
     B.NC = static_cast<int>(chains.size());
 
     ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.descs), sizeof(ProbDesc) * n));
-    ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.tiles), sizeof(int4) * B.NT));
+    ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.wg_prob), sizeof(int) * (max_tiles + B.NC)));
+    ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.tiles), sizeof(int4) * B.max_table));
     ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.chains), sizeof(int2) * B.NC));
     ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.A), sizeof(float) * a_off));
     ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.b), sizeof(double) * b_off));
@@ -703,17 +776,15 @@ ess_status batched_init(ess_ctx* c, const ess_problem* pr, int n) {
     ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.N), sizeof(float) * x_off));
     ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.P), sizeof(float) * p_off));
     ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.Q), sizeof(float) * q_off));
-    ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.counters), sizeof(int) * (5 + 2 * n)));
-    ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.fb_list), sizeof(int) * B.NC));
+    ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.counters), sizeof(int) * (3 + 4 * n)));
+    ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.fb_list), sizeof(int2) * B.NC));
     ESS_TRY(dalloc(c, reinterpret_cast<void**>(&c->sel), sizeof(int) * chain_off));
     ESS_TRY(dalloc(c, reinterpret_cast<void**>(&c->flag), sizeof(int) * chain_off));
     ESS_TRY(dalloc(c, reinterpret_cast<void**>(&c->rej), sizeof(long long) * chain_off));
     ESS_TRY(dalloc(c, reinterpret_cast<void**>(&c->d_step), sizeof(uint32_t)));
     ESS_TRY(create_run_streams(c));
-    HIP_TRY(hipMemcpyAsync(B.descs, B.h.data(), sizeof(ProbDesc) * n, hipMemcpyHostToDevice, c->st));
-    HIP_TRY(hipMemcpyAsync(B.tiles, tiles.data(), sizeof(int4) * B.NT, hipMemcpyHostToDevice, c->st));
-    HIP_TRY(hipMemcpyAsync(B.chains, caller_chains.data(), sizeof(int2) * B.NC,
-                           hipMemcpyHostToDevice, c->st));
+    HIP_TRY(hipMemcpyAsync(B.chains, chains.data(), sizeof(int2) * B.NC, hipMemcpyHostToDevice,
+                           c->st));
     for (int p = 0; p < n; ++p) {
         const ProbDesc& d = B.h[p];
         HIP_TRY(hipMemcpy2DAsync(B.A + d.a_off, sizeof(float) * d.dp, pr[p].A, sizeof(float) * d.d,
@@ -729,31 +800,12 @@ ess_status batched_init(ess_ctx* c, const ess_problem* pr, int n) {
                                      hipMemcpyDefault, c->st));
         }
     }
-    // the state check walks the caller order; the step kernel walks the queue order
-    ESS_TRY(batched_set_state_from_X(c, "ess_init_batched"));
-    HIP_TRY(hipMemcpyAsync(B.chains, chains.data(), sizeof(int2) * B.NC, hipMemcpyHostToDevice, c->st));
-    int dev = 0, cus = 0, occ = 0;
-    HIP_TRY(hipGetDevice(&dev));
-    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    const void* fn = nullptr;
-    if (B.nb == 256) fn = reinterpret_cast<const void*>(&batched_step_kernel<1, 256>);
-    else if (B.rpt <= 2) fn = reinterpret_cast<const void*>(&batched_step_kernel<2, 2048>);
-    else if (B.rpt <= 4) fn = reinterpret_cast<const void*>(&batched_step_kernel<4, 2048>);
-    else if (B.rpt <= 8) fn = reinterpret_cast<const void*>(&batched_step_kernel<8, 2048>);
-    else fn = reinterpret_cast<const void*>(&batched_step_kernel<16, 2048>);
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, 256, 0));
-    B.grid = std::max(1, cus * std::max(1, occ));
-    // keep the caller-order table for state copies
-    B.caller_chains = nullptr;
-    ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.caller_chains), sizeof(int2) * B.NC));
-    HIP_TRY(hipMemcpyAsync(B.caller_chains, caller_chains.data(), sizeof(int2) * B.NC,
-                           hipMemcpyHostToDevice, c->st));
-    return ESS_OK;
+    ESS_TRY(batched_layout(c));   // synchronises: the host chain table is copied
+    return batched_set_state_from_X(c, "ess_init_batched");
 }
 
 ess_status batched_copy_state(const ess_ctx* c, const float* src, float* dst, int to_library) {
     BatchArgs a = batch_args(c);
-    a.chains = c->batch->caller_chains;
     hipLaunchKernelGGL(batched_copy_rows, dim3(c->batch->NC), dim3(256), 0, c->st, a, src, dst,
                        to_library);
     HIP_TRY(hipGetLastError());
@@ -812,8 +864,8 @@ ess_status drop_graphs(ess_ctx* c) {
 }
 
 // ---------------------------------------------------------------- autotuning
-// Tile and launch choices per shape, cached in a small JSON file:
-//   {"<key>": {"G": 2, "bm": 128, "bn": 128, "group_m": 4, "grid": 0, "us_per_step": 162.5}, ...}
+// Tile choices per batched workload, cached in a small JSON file:
+//   {"<key>": {"shape_code": 1365, "fused": 0, "us_per_step": 162.5}, ...}
 std::string tune_cache_path() {
     if (const char* p = std::getenv("ESS_TUNE_CACHE")) return p;
     const char* home = std::getenv("HOME");
@@ -865,47 +917,74 @@ double field(const std::string& obj, const char* name, double dflt) {
     return colon == std::string::npos ? dflt : std::atof(obj.c_str() + colon + 1);
 }
 
+// A batched context's tile shape per size class, as one base-4 number
+// (class k in digit k).
 struct TuneChoice {
-    int G = 1, bm = 128, bn = 128, group_m = 4, grid = 0;
+    int shape_code = 0;
+    int fused = 0;
     double us = 0;
 };
 
-void apply_choice(ess_ctx* c, const TuneChoice& t) {
-    if (c->batch) {
-        if (t.grid > 0) c->batch->grid = t.grid;
-    } else {
-        c->G = std::max(1, std::min({t.G, kMaxGroups, c->Cp / 128}));
-        if (c->G > 1 && (!c->fork || !c->gs[c->G - 1] || !c->join[c->G - 1])) c->G = 1;
-        if (c->prec == 32) {
-            c->bm = t.bm;
-            c->bn = t.bn;
-        }
-        c->group_m = t.group_m;
+int encode_shapes(const ess_ctx* c) {
+    int code = 0;
+    for (int k = kTileBuckets - 1; k >= 0; --k) code = code * kBatchShapes + c->batch->bucket_shape[k];
+    return code;
+}
+
+void set_choice(ess_ctx* c, const TuneChoice& t) {
+    c->batch->fused = t.fused != 0;
+    int code = t.shape_code;
+    for (int k = 0; k < kTileBuckets; ++k) {
+        c->batch->bucket_shape[k] = code % kBatchShapes;
+        code /= kBatchShapes;
     }
+}
+
+ess_status apply_choice(ess_ctx* c, const TuneChoice& t) {
+    set_choice(c, t);
+    return batched_layout(c);
 }
 
 TuneChoice current_choice(const ess_ctx* c) {
     TuneChoice t;
-    t.G = c->G;
-    t.bm = c->bm;
-    t.bn = c->bn;
-    t.group_m = c->group_m;
-    t.grid = c->batch ? c->batch->grid : 0;
+    t.shape_code = encode_shapes(c);
+    t.fused = c->batch->fused ? 1 : 0;
     return t;
 }
 
-void load_tuned(ess_ctx* c) {
-    if (!c->batch) return;   // single-problem tuning is switched off (see ess_autotune)
+int max_shape_code() {
+    int v = 1;
+    for (int k = 0; k < kTileBuckets; ++k) v *= kBatchShapes;
+    return v;
+}
+
+// The cached choice for this workload, then the overrides ESS_BATCH_TILE
+// ("BMxBN" for every size class) and ESS_BATCH_LAUNCH ("split" or "fused").
+ess_status load_tuned(ess_ctx* c) {
+    if (!c->batch) return ESS_OK;   // single-problem tuning is switched off (see ess_autotune)
     const std::string obj = cache_entry(read_file(tune_cache_path()), tune_key(c));
-    if (obj.empty()) return;
-    TuneChoice t = current_choice(c);
-    t.G = static_cast<int>(field(obj, "G", t.G));
-    t.bm = static_cast<int>(field(obj, "bm", t.bm));
-    t.bn = static_cast<int>(field(obj, "bn", t.bn));
-    t.group_m = static_cast<int>(field(obj, "group_m", t.group_m));
-    t.grid = static_cast<int>(field(obj, "grid", 0));
-    const bool tiles_ok = (t.bm == 64 || t.bm == 128) && (t.bn == 64 || t.bn == 128);
-    if (tiles_ok && t.group_m >= 1 && t.group_m <= 64) apply_choice(c, t);
+    if (!obj.empty()) {
+        TuneChoice t;
+        t.shape_code = static_cast<int>(field(obj, "shape_code", -1));
+        t.fused = field(obj, "fused", 0) != 0 ? 1 : 0;
+        if (t.shape_code >= 0 && t.shape_code < max_shape_code()) set_choice(c, t);
+    }
+    if (const char* env = std::getenv("ESS_BATCH_TILE")) {
+        int bm = 0, bn = 0, shape = -1;
+        if (std::sscanf(env, "%dx%d", &bm, &bn) == 2)
+            for (int sh = 0; sh < kBatchShapes; ++sh)
+                if (shape_bm(sh) == bm && shape_bn(sh) == bn) shape = sh;
+        if (shape < 0)
+            return fail(ESS_ERR_INVALID_ARG, "ESS_BATCH_TILE must be 64x64, 32x64, 64x32 or 32x32");
+        for (int k = 0; k < kTileBuckets; ++k) c->batch->bucket_shape[k] = shape;
+    }
+    if (const char* env = std::getenv("ESS_BATCH_LAUNCH")) {
+        const std::string v(env);
+        if (v != "split" && v != "fused")
+            return fail(ESS_ERR_INVALID_ARG, "ESS_BATCH_LAUNCH must be split or fused");
+        c->batch->fused = v == "fused";
+    }
+    return batched_layout(c);
 }
 
 void store_tuned(const ess_ctx* c, const TuneChoice& t) {
@@ -913,8 +992,7 @@ void store_tuned(const ess_ctx* c, const TuneChoice& t) {
     std::string text = read_file(path);
     const std::string key = tune_key(c);
     std::ostringstream e;
-    e << "\"" << key << "\": {\"G\": " << t.G << ", \"bm\": " << t.bm << ", \"bn\": " << t.bn
-      << ", \"group_m\": " << t.group_m << ", \"grid\": " << t.grid
+    e << "\"" << key << "\": {\"shape_code\": " << t.shape_code << ", \"fused\": " << t.fused
       << ", \"us_per_step\": " << t.us << "}";
     const std::string q = "\"" + key + "\"";
     const size_t at = text.find(q);
@@ -1270,7 +1348,6 @@ ess_status ess_init(const ess_problem* pr, void* stream, ess_ctx** out) {
         return bail(ESS_ERR_HIP);
     }
     if ((s = set_state_from_X(c, "ess_init")) != ESS_OK) return bail(s);
-    load_tuned(c);
     *out = c;
     return ESS_OK;
 }
@@ -1426,7 +1503,7 @@ ess_status ess_init_batched(const ess_problem* pr, int32_t n_problems, void* str
     c->st = static_cast<hipStream_t>(stream);
     c->C = static_cast<int>(total_chains);
     ess_status s = batched_init(c, pr, n_problems);
-    if (s == ESS_OK) load_tuned(c);
+    if (s == ESS_OK) s = load_tuned(c);
     if (s != ESS_OK) {
         std::string keep = g_err;
         ess_destroy(c);
@@ -1607,82 +1684,80 @@ ess_status ess_autotune(ess_ctx* c, int32_t steps_per_trial, char* report, int32
         return fail(ESS_ERR_UNSUPPORTED,
                     "ess_autotune is switched off for single-problem contexts: its trial loop "
                     "ended the process with a host segmentation fault whose cause is not yet known");
+    ess_ctx::Batch& B = *c->batch;
     // keep the chains where they are: save the state, restore it afterwards
     float* saved = nullptr;
-    size_t bytes = c->batch ? sizeof(float) * c->batch->h.back().x_off +
-                                  sizeof(float) * static_cast<size_t>(c->batch->h.back().Cp) * c->batch->h.back().dp
-                            : static_cast<size_t>(c->Cp) * c->dp * c->esz;
-    void* X = c->batch ? static_cast<void*>(c->batch->X) : c->X;
+    const size_t bytes = sizeof(float) * (B.h.back().x_off +
+                                          static_cast<size_t>(B.h.back().Cp) * B.h.back().dp);
     HIP_TRY(hipMalloc(&saved, bytes));
-    HIP_TRY(hipMemcpyAsync(saved, X, bytes, hipMemcpyDeviceToDevice, c->st));
+    HIP_TRY(hipMemcpyAsync(saved, B.X, bytes, hipMemcpyDeviceToDevice, c->st));
     const uint64_t step0 = c->step;
+    bool present[kTileBuckets] = {};
+    for (const auto& d : B.h) present[tile_bucket(d)] = true;
 
-    std::vector<TuneChoice> cands;
-    if (c->batch) {
-        int dev = 0, cus = 0;
-        HIP_TRY(hipGetDevice(&dev));
-        HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        const int maxk = std::max(1, c->batch->grid / std::max(cus, 1));
-        for (int k = 1; k <= maxk; ++k) {
-            TuneChoice t = current_choice(c);
-            t.grid = cus * k;
-            cands.push_back(t);
-        }
-    } else {
-        const int gmax = std::min(kMaxGroups, c->Cp / 128);
-        const int tiles[4][2] = {{128, 128}, {128, 64}, {64, 128}, {64, 64}};
-        for (int G = 1; G <= gmax; G *= 2)
-            for (int ti = 0; ti < (c->prec == 32 ? 4 : 1); ++ti)
-                for (int gm : {2, 4, 8}) {
-                    TuneChoice t = current_choice(c);
-                    t.G = G;
-                    t.bm = tiles[ti][0];
-                    t.bn = tiles[ti][1];
-                    t.group_m = gm;
-                    cands.push_back(t);
-                }
-    }
-    const TuneChoice before = current_choice(c);
-    TuneChoice best = before;
-    best.us = 1e30;
-    std::ostringstream rep;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
+    std::ostringstream rep;
     ess_status st = ESS_OK;
-    for (TuneChoice t : cands) {
-        apply_choice(c, t);
-        if ((st = drop_graphs(c)) != ESS_OK) break;
-        if ((st = run_dispatch(c, steps_per_trial, 1, nullptr)) != ESS_OK) break;   // capture, warm
+    // time the current choice: capture and warm, then time a replay
+    auto trial = [&](TuneChoice& t) -> ess_status {
+        ESS_TRY(apply_choice(c, t));
+        ESS_TRY(drop_graphs(c));
+        ESS_TRY(run_dispatch(c, steps_per_trial, 1, nullptr));
         c->step += steps_per_trial;
         HIP_TRY(hipEventRecord(e0, c->st));
-        if ((st = run_dispatch(c, steps_per_trial, 1, nullptr)) != ESS_OK) break;
+        ESS_TRY(run_dispatch(c, steps_per_trial, 1, nullptr));
         c->step += steps_per_trial;
         HIP_TRY(hipEventRecord(e1, c->st));
         HIP_TRY(hipEventSynchronize(e1));
         float ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
         t.us = 1e3 * ms / steps_per_trial;
-        rep << "G=" << t.G << " bm=" << t.bm << " bn=" << t.bn << " group_m=" << t.group_m
-            << " grid=" << t.grid << ": " << t.us << " us/step\n";
-        if (t.us < best.us) best = t;
+        rep << (t.fused ? "fused" : "split") << ", shapes";
+        int code = t.shape_code;
+        for (int k = 0; k < kTileBuckets; ++k, code /= kBatchShapes)
+            rep << " " << shape_bm(code % kBatchShapes) << "x" << shape_bn(code % kBatchShapes);
+        rep << ": " << t.us << " us/step\n";
+        return ESS_OK;
+    };
+    const TuneChoice before = current_choice(c);
+    TuneChoice best = before;
+    st = trial(best);
+    // one pass of coordinate descent: each size class in turn, the others fixed
+    int place = 1;
+    for (int k = 0; k < kTileBuckets && st == ESS_OK; ++k, place *= kBatchShapes) {
+        if (!present[k]) continue;
+        const int digit = (best.shape_code / place) % kBatchShapes;
+        for (int sh = 0; sh < kBatchShapes && st == ESS_OK; ++sh) {
+            if (sh == digit) continue;
+            TuneChoice t;
+            t.shape_code = best.shape_code + (sh - digit) * place;
+            st = trial(t);
+            if (st == ESS_OK && t.us < best.us) best = t;
+        }
+    }
+    if (st == ESS_OK) {   // the other launch form with the chosen shapes
+        TuneChoice t = best;
+        t.fused = best.fused ? 0 : 1;
+        st = trial(t);
+        if (st == ESS_OK && t.us < best.us) best = t;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (st != ESS_OK) apply_choice(c, before);
-    else apply_choice(c, best);
-    ESS_TRY(drop_graphs(c));
-    HIP_TRY(hipMemcpyAsync(X, saved, bytes, hipMemcpyDeviceToDevice, c->st));
+    ess_status fin = apply_choice(c, st == ESS_OK ? best : before);
+    if (fin == ESS_OK) fin = drop_graphs(c);
+    HIP_TRY(hipMemcpyAsync(B.X, saved, bytes, hipMemcpyDeviceToDevice, c->st));
     HIP_TRY(hipStreamSynchronize(c->st));
     (void)hipFree(saved);
-    if (c->batch) ESS_TRY(batched_set_state_from_X(c, "ess_autotune"));
-    else ESS_TRY(set_state_from_X(c, "ess_autotune"));
+    ESS_TRY(fin);
+    ESS_TRY(batched_set_state_from_X(c, "ess_autotune"));
     ESS_TRY(launch_step_counter(c, c->st, step0, 0));
     c->step = step0;
     if (st != ESS_OK) return st;
     store_tuned(c, best);
-    rep << "chosen: G=" << best.G << " bm=" << best.bm << " bn=" << best.bn << " group_m="
-        << best.group_m << " grid=" << best.grid << " (" << best.us << " us/step)\n";
+    rep << "chosen: " << (best.fused ? "fused" : "split") << ", shape_code " << best.shape_code
+        << " (" << best.us << " us/step)\n";
     if (report && report_len > 0) {
         const std::string r = rep.str();
         const size_t n = std::min(r.size(), static_cast<size_t>(report_len - 1));

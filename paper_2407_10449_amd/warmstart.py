@@ -123,59 +123,67 @@ def burn_in_excess(curve):
     return float(np.maximum(np.asarray(curve) - 1.0, 0.0).sum())
 
 
-def compare(E, A, eval_b, net, chains=64, burn_window=1000, steps=4000, thin=4, ref=None,
-            seed=0, log=None):
+def _device_curve(tr, x0, nb, chains, ref_mean, ref_sd):
+    """burn_in_curve for a device trace (T, C, d) and start x0 (C, d), computed
+    on the device; returns a host float64 array of length T + 1."""
+    import torch
+    mu = torch.as_tensor(ref_mean, device=tr.device)
+    se = torch.as_tensor(ref_sd, device=tr.device) / np.sqrt(chains)
+    out = []
+    for x in [x0[None]] + [tr[i:i + 256] for i in range(0, tr.shape[0], 256)]:
+        m = x.double().reshape(x.shape[0], nb, chains, -1).mean(dim=2)
+        out.append((((m - mu) / se) ** 2).mean(dim=(1, 2)))
+    return torch.cat(out).cpu().numpy()
+
+
+def compare(E, A, eval_b, net, chains=64, steps=12000, thin=4, level=2.0, ref=None, seed=0,
+            log=None):
     """ESS/s at equal accuracy for three ways to sample the posteriors of `eval_b`:
       plain_per_problem  one context per b (`chains` chains each), started at 0
       batched_plain      one context over all b's (a b per chain), started at 0
       batched_warm       the same context started at the gated network prediction
-    Every arm runs `steps` steps, recorded every `thin` steps, in the same wall
-    time budget.  The burn-in curve D_t (`burn_in_curve`) over the first
-    `burn_window` steps fixes each arm's burn-in: the first recorded step with
-    D_t <= 1.25 x the median of D over the window's last quarter (the arm's
-    stationary level).  Each arm discards its own burn-in; ESS counts the rest
-    (bulk ESS, minimum over 64 monitored coordinates and |x|^2, summed over
-    problems).  Wall time covers inference, gating and every step.  Accuracy:
-    the largest |posterior mean - reference| / MCSE over problems and the first
-    16 monitored coordinates."""
+    Every arm runs `steps` steps recorded every `thin` steps.  Its burn-in is
+    the first recorded step from which the curve D_t (`burn_in_curve`, against
+    long reference runs) stays at or below `level`; the draws after it give the
+    ESS (bulk ESS, minimum over 64 monitored coordinates and |x|^2, summed over
+    problems).  Wall time covers inference, gating and every step of the arm.
+    Accuracy: the largest |posterior mean - reference| / MCSE over problems and
+    the first 16 monitored coordinates."""
     import torch
     from . import diagnostics as D
     m, d = A.shape
     nb = len(eval_b)
     if ref is None:
-        ref = reference_moments(E, A, eval_b, chains=chains, burn=4000, steps=40000, thin=10,
-                                seed=seed + 1)
+        ref = reference_moments(E, A, eval_b, chains=chains, burn=3 * steps, steps=5 * steps,
+                                thin=10, seed=seed + 1)
     ref_mean, ref_sd = ref
     mon = np.sort(np.random.default_rng(seed).choice(d, min(d, 64), replace=False))
     mon_t = torch.as_tensor(mon, device="cuda")
     B = np.repeat(eval_b, chains, axis=0)
-    nwin = burn_window // thin
-    out = {}
+    marks = [k for k in (0, 100, 250, 500, 1000, 2000, 4000, 8000, 16000) if k <= steps]
+    out = {"reference": f"{chains} chains per b, {3 * steps} burn-in + {5 * steps} steps",
+           "burn_in_level": level}
 
-    def reduce(tr):
-        """Burn-in window (full states) and the monitored coordinates plus |x|^2
-        of the whole trace, float64 on the host."""
-        win = tr[:nwin].double().cpu().numpy()
+    def finish(name, tr, x0, wall):
+        curve = _device_curve(tr, x0, nb, chains, ref_mean, ref_sd)
+        tb = burn_in_steps(curve, level)           # in recorded steps
         sub = tr.index_select(2, mon_t).double()
         sq = (tr.double() ** 2).sum(dim=2, keepdim=True)
-        return win, torch.cat([sub, sq], dim=2).cpu().numpy()
-
-    def finish(name, win, mon_x, wall, x0):
-        curve = burn_in_curve(np.concatenate([x0[None], win]), nb, chains, ref_mean, ref_sd)
-        level = float(np.median(curve[-max(1, len(curve) // 4):]))
-        first = int(np.nonzero(curve <= 1.25 * level)[0][0])   # the last quarter qualifies
-        x = mon_x[max(first - 1, 0):]                          # curve[k] is after k * thin steps
+        x = torch.cat([sub, sq], dim=2)[max(tb - 1, 0):].cpu().numpy()
         ess, worst, zmax = 0.0, 1e30, 0.0
-        for j in range(nb):
-            xj = x[:, j * chains:(j + 1) * chains, :]
-            e = min(D.ess(xj[:, :, k]) for k in range(xj.shape[2]))
-            ess += e
-            worst = min(worst, e)
-            for k in range(16):
-                se = D.mcse_mean(xj[:, :, k])
-                zmax = max(zmax, abs(xj[:, :, k].mean() - ref_mean[j, mon[k]]) / max(se, 1e-12))
-        out[name] = {"burn_in_steps": first * thin, "stationary_D": level,
-                     "burn_in_excess": burn_in_excess(curve) * thin, "D_0": float(curve[0]),
+        if x.shape[0] >= 8:
+            for j in range(nb):
+                xj = x[:, j * chains:(j + 1) * chains, :]
+                e = min(D.ess(xj[:, :, k]) for k in range(xj.shape[2]))
+                ess += e
+                worst = min(worst, e)
+                for k in range(16):
+                    se = D.mcse_mean(xj[:, :, k])
+                    zmax = max(zmax, abs(xj[:, :, k].mean() - ref_mean[j, mon[k]]) / max(se, 1e-12))
+        else:
+            worst = 0.0
+        out[name] = {"burn_in_steps": tb * thin, "burn_in_excess": burn_in_excess(curve) * thin,
+                     "D_at_step": {str(k): round(float(curve[k // thin]), 3) for k in marks},
                      "ess": ess, "min_ess_per_problem": worst, "wall_s": wall,
                      "ess_per_s": ess / wall, "max_z_mean_vs_reference": float(zmax)}
         if log:
@@ -190,9 +198,10 @@ def compare(E, A, eval_b, net, chains=64, burn_window=1000, steps=4000, thin=4, 
     wall = time.perf_counter() - t0
     for q in ctxs:
         q.close()
-    win, mon_x = reduce(torch.cat(trs, 1))
+    tr = torch.cat(trs, 1)
     del trs
-    finish("plain_per_problem", win, mon_x, wall, np.zeros((B.shape[0], d)))
+    finish("plain_per_problem", tr, torch.zeros(B.shape[0], d, device="cuda"), wall)
+    del tr
 
     for name in ("batched_plain", "batched_warm"):
         s = E.Sampler(A, B, np.zeros(d), B.shape[0], seed=seed + 7, precision=32)
@@ -200,7 +209,7 @@ def compare(E, A, eval_b, net, chains=64, burn_window=1000, steps=4000, thin=4, 
         zeros = torch.zeros(B.shape[0], d, device="cuda")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        x0 = np.zeros((B.shape[0], d))
+        x0 = zeros
         if name == "batched_warm":
             xhat = net.forward(bdev).repeat_interleave(chains, dim=0)
             acc = s.set_state_gated(xhat, zeros)
@@ -208,14 +217,13 @@ def compare(E, A, eval_b, net, chains=64, burn_window=1000, steps=4000, thin=4, 
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         if name == "batched_warm":
-            x0 = xhat.double().cpu().numpy() * acc[:, None]
-            out["gate_accepted"] = float(acc.mean())
+            x0 = xhat * torch.as_tensor(acc, device="cuda", dtype=xhat.dtype)[:, None]
+            out["gate_accepted"] = float(np.mean(acc))
         s.close()
-        win, mon_x = reduce(tr)
+        finish(name, tr, x0, wall)
         del tr
-        finish(name, win, mon_x, wall, x0)
     out["ess_per_s_batched_warm_over_plain_per_problem"] = (
-        out["batched_warm"]["ess_per_s"] / out["plain_per_problem"]["ess_per_s"])
+        out["batched_warm"]["ess_per_s"] / max(out["plain_per_problem"]["ess_per_s"], 1e-30))
     out["ess_per_s_batched_warm_over_batched_plain"] = (
-        out["batched_warm"]["ess_per_s"] / out["batched_plain"]["ess_per_s"])
+        out["batched_warm"]["ess_per_s"] / max(out["batched_plain"]["ess_per_s"], 1e-30))
     return out

@@ -1,4 +1,4 @@
-"""Batched contexts: many uneven polytopes in one persistent launch per step."""
+"""Batched contexts: many uneven polytopes advanced by one launch per step."""
 import sys
 
 import numpy as np
@@ -105,3 +105,24 @@ def test_batched_autotune_keeps_results(E, tmp_path, monkeypatch):
     assert torch.equal(torch.cat([first, rest]), want)
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("launch,tile", [("split", "32x64"), ("split", "64x32"),
+                                         ("split", "32x32"), ("fused", "64x64"),
+                                         ("fused", "32x32")])
+def test_batched_launch_forms_and_tiles_give_identical_chains(E, monkeypatch, launch, tile):
+    """Every tile shape sums each projection in the same order, and the fused
+    and split launches run the same arithmetic, so the chains are
+    bit-identical to the default (split launch, 64x64 tiles)."""
+    probs = problems(12, 16, seed=21)
+    monkeypatch.setenv("ESS_BATCH_TILE", "64x64")
+    monkeypatch.setenv("ESS_BATCH_LAUNCH", "split")
+    a = E.BatchedSampler(probs)
+    want, _ = a.run(5)
+    a.close()
+    monkeypatch.setenv("ESS_BATCH_TILE", tile)
+    monkeypatch.setenv("ESS_BATCH_LAUNCH", launch)
+    b = E.BatchedSampler(probs)
+    got, _ = b.run(5)
+    b.close()
+    assert torch.equal(got, want)
