@@ -144,7 +144,7 @@ def bench_warm_start(E, torch, log):
     hist, t_train = W.train(net, X, Y, epochs=10, batch=1024, lr=1e-3)
     cmp = W.compare(E, A, eval_b, net, log=log)
     net.close()
-    cmp.update({"workload": "warm_family d=256 m=768: 32 held-out b x 64 chains, 12000 steps each",
+    cmp.update({"workload": "warm_family d=256 m=768: 32 held-out b x 64 chains, 48000 steps each",
                 "train_samples": int(X.shape[0]), "train_gen_s": t_gen, "train_s": t_train,
                 "train_mse_before_after": [hist[0], hist[-1]]})
     return cmp
@@ -159,6 +159,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched and warm-start measurements")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="run only the batched measurement and print its JSON (for profiling)")
+    ap.add_argument("--warm-only", action="store_true",
+                    help="run only the warm-start comparison and print its JSON")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain elementwise copy of 256 MiB (reference for "
                          "hardware byte counters)")
@@ -185,6 +189,13 @@ def main():
             torch.add(src, 0.0, out=dst)     # reads 256 MiB, writes 256 MiB
         torch.cuda.synchronize()
         del src, dst
+    if args.batched_only:
+        print(json.dumps({"batched": bench_batched(E, torch, steps=args.steps)}), flush=True)
+        return
+    if args.warm_only:
+        log = lambda msg: print(msg, file=sys.stderr, flush=True)
+        print(json.dumps({"warm_start": bench_warm_start(E, torch, log)}), flush=True)
+        return
     pr = synth.gp_rbf()
     C, d, m = pr.n_chains, pr.d, pr.m
     s = E.Sampler(pr.A, pr.b, pr.x0, C, seed=0, precision=32, trim_eps=1e-6)

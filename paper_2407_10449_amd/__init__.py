@@ -243,6 +243,13 @@ def ess_last_error():
 
 
 # ----------------------------------------------------------- convenience
+def _check_out(out, shape, dtype, device):
+    if (tuple(out.shape) != tuple(shape) or out.dtype != dtype or out.device != device
+            or not out.is_contiguous()):
+        raise ValueError(f"trace buffer must be a contiguous {dtype} tensor of shape {shape} "
+                         f"on {device}, got {tuple(out.shape)} {out.dtype} on {out.device}")
+
+
 class Sampler:
     """Owns one ess_ctx.  A, b, x0 may be numpy arrays or torch tensors; they
     are copied to the device in the working precision before ess_init."""
@@ -283,8 +290,16 @@ class Sampler:
         ess_step(self.ctx, x)
         return x
 
-    def run(self, n_steps, thin=1, keep_trace=True, count_rejections=True):
-        tr = self._empty(n_steps // thin, self.n_chains, self.d) if keep_trace and n_steps // thin else None
+    def run(self, n_steps, thin=1, keep_trace=True, count_rejections=True, out=None):
+        """n_steps transitions; the trace (every thin-th state) goes to `out`
+        when given (a reused buffer lets later runs replay the same captured
+        graph), else to a new tensor."""
+        shape = (n_steps // thin, self.n_chains, self.d)
+        if out is not None:
+            _check_out(out, shape, self.dtype, self.device)
+            tr = out
+        else:
+            tr = self._empty(*shape) if keep_trace and n_steps // thin else None
         nrej = ess_run(self.ctx, n_steps, thin, tr, count_rejections)
         return tr, nrej
 
@@ -377,10 +392,15 @@ class BatchedSampler:
             off += C * d
         return out
 
-    def run(self, n_steps, thin=1, keep_trace=True, count_rejections=True):
+    def run(self, n_steps, thin=1, keep_trace=True, count_rejections=True, out=None):
         t = self.torch
-        tr = (t.empty(n_steps // thin, self.n_state, device=self.device, dtype=t.float32)
-              if keep_trace and n_steps // thin else None)
+        shape = (n_steps // thin, self.n_state)
+        if out is not None:
+            _check_out(out, shape, t.float32, self.device)
+            tr = out
+        else:
+            tr = (t.empty(*shape, device=self.device, dtype=t.float32)
+                  if keep_trace and n_steps // thin else None)
         nrej = ess_run(self.ctx, n_steps, thin, tr, count_rejections)
         return tr, nrej
 

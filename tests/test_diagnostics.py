@@ -41,3 +41,26 @@ def test_mcse_of_iid_mean():
     rng = np.random.default_rng(3)
     x = rng.standard_normal((4000, 4))
     assert abs(D.mcse_mean(x) - 1 / np.sqrt(x.size)) < 0.15 / np.sqrt(x.size)
+
+
+def test_batched_estimators_equal_the_reference_ones():
+    """The torch versions reproduce ess / mcse_mean, including ties, constant
+    draws and random walks."""
+    torch = __import__("pytest").importorskip("torch")
+    rng = np.random.default_rng(5)
+    T, M, Q = 401, 12, 6
+    x = rng.standard_normal((T, M, Q)).cumsum(0) * 0.05 + rng.standard_normal((T, M, Q))
+    x[:, :, 2] = np.round(x[:, :, 2], 1)
+    x[:, :, 3] = 2.5
+    x[:, :, 4] = rng.standard_normal((T, M)).cumsum(0)
+    x[:, :, 5] = ar1(rng, 0.9, T, M)
+    got = D.ess_batch(torch.as_tensor(x)).numpy()
+    want = np.array([D.ess(x[:, :, q]) for q in range(Q)])
+    np.testing.assert_allclose(got, want, rtol=1e-9)
+    got = D.ess_batch(torch.as_tensor(x), rank=False).numpy()
+    want = np.array([D.ess(x[:, :, q], rank=False) for q in range(Q)])
+    np.testing.assert_allclose(got, want, rtol=1e-9)
+    keep = [0, 1, 2, 4, 5]
+    got = D.mcse_mean_batch(torch.as_tensor(x[:, :, keep])).numpy()
+    want = np.array([D.mcse_mean(x[:, :, q]) for q in keep])
+    np.testing.assert_allclose(got, want, rtol=1e-9)
