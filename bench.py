@@ -129,7 +129,7 @@ def bench_batched(E, torch, steps=50, plain_steps=10):
             "autotune": report.strip().splitlines()[-1]}
 
 
-def bench_warm_start(E, torch, log):
+def bench_warm_start(E, torch, log, steps=48000):
     """ESS/s at equal accuracy: batched + learned warm start against plain
     per-problem contexts (and against the batched context started plain)."""
     import numpy as np
@@ -142,9 +142,9 @@ def bench_warm_start(E, torch, log):
     X, Y, t_gen = W.generate_pairs(E, A, train_b, chains_per_b=1, burn=500, n_keep=10, thin=10)
     net = E.Mlp((m, 512, 512, d), seed=0)
     hist, t_train = W.train(net, X, Y, epochs=10, batch=1024, lr=1e-3)
-    cmp = W.compare(E, A, eval_b, net, log=log)
+    cmp = W.compare(E, A, eval_b, net, steps=steps, log=log)
     net.close()
-    cmp.update({"workload": "warm_family d=256 m=768: 32 held-out b x 64 chains, 48000 steps each",
+    cmp.update({"workload": f"warm_family d=256 m=768: 32 held-out b x 64 chains, {steps} steps each",
                 "train_samples": int(X.shape[0]), "train_gen_s": t_gen, "train_s": t_train,
                 "train_mse_before_after": [hist[0], hist[-1]]})
     return cmp
@@ -163,6 +163,8 @@ def main():
                     help="run only the batched measurement and print its JSON (for profiling)")
     ap.add_argument("--warm-only", action="store_true",
                     help="run only the warm-start comparison and print its JSON")
+    ap.add_argument("--warm-steps", type=int, default=48000,
+                    help="steps per arm of the warm-start comparison")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain elementwise copy of 256 MiB (reference for "
                          "hardware byte counters)")
@@ -194,7 +196,8 @@ def main():
         return
     if args.warm_only:
         log = lambda msg: print(msg, file=sys.stderr, flush=True)
-        print(json.dumps({"warm_start": bench_warm_start(E, torch, log)}), flush=True)
+        print(json.dumps({"warm_start": bench_warm_start(E, torch, log, args.warm_steps)}),
+              flush=True)
         return
     pr = synth.gp_rbf()
     C, d, m = pr.n_chains, pr.d, pr.m
@@ -257,7 +260,7 @@ def main():
     if not args.no_extras:
         log = lambda msg: print(msg, file=sys.stderr, flush=True)
         out["batched"] = bench_batched(E, torch)
-        out["warm_start"] = bench_warm_start(E, torch, log)
+        out["warm_start"] = bench_warm_start(E, torch, log, args.warm_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pr, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -243,9 +243,20 @@ def ess_last_error():
 
 
 # ----------------------------------------------------------- convenience
+def _same_device(a, b):
+    import torch
+    a, b = torch.device(a), torch.device(b)
+    if a.type != b.type:
+        return False
+    if a.type != "cuda":
+        return True
+    cur = torch.cuda.current_device()
+    return (cur if a.index is None else a.index) == (cur if b.index is None else b.index)
+
+
 def _check_out(out, shape, dtype, device):
-    if (tuple(out.shape) != tuple(shape) or out.dtype != dtype or out.device != device
-            or not out.is_contiguous()):
+    if (tuple(out.shape) != tuple(shape) or out.dtype != dtype
+            or not _same_device(out.device, device) or not out.is_contiguous()):
         raise ValueError(f"trace buffer must be a contiguous {dtype} tensor of shape {shape} "
                          f"on {device}, got {tuple(out.shape)} {out.dtype} on {out.device}")
 

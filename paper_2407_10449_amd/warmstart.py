@@ -169,11 +169,15 @@ def compare(E, A, eval_b, net, chains=64, steps=48000, thin=20, level=2.0, ref=N
         x = tr[max(tb - 1, 0):]
         T = x.shape[0]
         if T >= 8:
-            q = torch.cat([x.index_select(2, mon_t), (x.double() ** 2).sum(dim=2, keepdim=True)
-                           .to(x.dtype)], dim=2)                      # (T, C, 65)
+            sq = torch.cat([(x[i:i + 512].double() ** 2).sum(dim=2, keepdim=True)
+                            for i in range(0, T, 512)]).to(x.dtype)
+            q = torch.cat([x.index_select(2, mon_t), sq], dim=2)      # (T, C, 65)
             Qn = q.shape[2]
             qb = q.reshape(T, nb, chains, Qn).permute(0, 2, 1, 3).reshape(T, chains, nb * Qn)
-            e = D.ess_batch(qb).reshape(nb, Qn).min(dim=1).values     # per problem
+            step = max(Qn, (1 << 27) // max(1, T * chains) // Qn * Qn)   # bounded memory
+            e = torch.cat([D.ess_batch(qb[:, :, i:i + step]) for i in range(0, nb * Qn, step)])
+            e_all = e.reshape(nb, Qn)
+            e = e_all.min(dim=1).values                                 # per problem
             ess, worst = float(e.sum()), float(e.min())
             c16 = qb.reshape(T, chains, nb, Qn)[:, :, :, :16].reshape(T, chains, nb * 16)
             se = D.mcse_mean_batch(c16)
@@ -183,6 +187,8 @@ def compare(E, A, eval_b, net, chains=64, steps=48000, thin=20, level=2.0, ref=N
         else:
             ess, worst, zs = 0.0, 0.0, np.zeros(1)
         out[name] = {"burn_in_steps": tb * thin, "burn_in_excess": burn_in_excess(curve) * thin,
+                     "median_ess_coordinates": float(e_all[:, :-1].median()) if T >= 8 else 0.0,
+                     "median_ess_sq_norm": float(e_all[:, -1].median()) if T >= 8 else 0.0,
                      "D_at_step": {str(k): round(float(curve[k // thin]), 3) for k in marks},
                      "ess": ess, "min_ess_per_problem": worst, "wall_s": wall,
                      "ess_per_s": ess / wall, "max_z_mean_vs_reference": float(zs.max()),
