@@ -71,7 +71,8 @@ def train(net, inputs, targets, epochs=20, batch=1024, lr=1e-3, seed=0, log=None
     return history, time.perf_counter() - t0
 
 
-def reference_moments(E, A, bs, chains=64, burn=500, steps=2000, thin=4, seed=1, segment=2000):
+def reference_moments(E, A, bs, chains=64, burn=500, steps=2000, thin=4, seed=1, segment=2000,
+                      log=None):
     """Long plain runs: per b, the mean and sd of every coordinate over all
     chains and recorded steps.  Runs `segment` steps at a time into one reused
     buffer (one captured graph), with float64 sums kept on the device."""
@@ -88,8 +89,11 @@ def reference_moments(E, A, bs, chains=64, burn=500, steps=2000, thin=4, seed=1,
     s1 = torch.zeros(nb, d, dtype=torch.float64, device="cuda")
     s2 = torch.zeros_like(s1)
     n = 0
-    for _ in range(max(1, steps // segment)):
+    for k in range(max(1, steps // segment)):
         s.run(segment, thin=thin, count_rejections=False, out=buf)
+        if log and k % 50 == 49:
+            torch.cuda.synchronize()
+            log(f"reference: {(k + 1) * segment} of {steps} steps")
         x = buf.double().reshape(buf.shape[0], nb, chains, d)
         s1 += x.sum(dim=(0, 2))
         s2 += (x * x).sum(dim=(0, 2))
@@ -154,7 +158,7 @@ def compare(E, A, eval_b, net, chains=64, steps=48000, thin=20, level=2.0, ref=N
     nb = len(eval_b)
     if ref is None:
         ref = reference_moments(E, A, eval_b, chains=chains, burn=max(20000, steps // 2),
-                                steps=4 * steps, thin=20, seed=seed + 1)
+                                steps=4 * steps, thin=20, seed=seed + 1, log=log)
     ref_mean, ref_sd = ref
     mon = np.sort(np.random.default_rng(seed).choice(d, min(d, 64), replace=False))
     mon_t = torch.as_tensor(mon, device="cuda")
@@ -199,7 +203,7 @@ def compare(E, A, eval_b, net, chains=64, steps=48000, thin=20, level=2.0, ref=N
     seg = min(steps, 2000)
     steps -= steps % seg
 
-    def timed_run(samplers, start):
+    def timed_run(samplers, start, name):
         """Every sampler runs `steps` steps in segments of `seg` into a buffer
         of its own, so each captures its graph once, before the clock starts
         (a capture run, then the state is reset).  `start(i, s)` sets sampler
@@ -221,13 +225,16 @@ def compare(E, A, eval_b, net, chains=64, steps=48000, thin=20, level=2.0, ref=N
                 q.run(seg, thin=thin, count_rejections=False, out=buf)
                 full[rows, c0:c0 + q.n_chains].copy_(buf)
                 c0 += q.n_chains
+            if log and k % 10 == 9 and len(samplers) > 1:
+                torch.cuda.synchronize()   # progress of the slow arm (its wall time includes this)
+                log(f"{name}: {(k + 1) * seg} of {steps} steps")
         torch.cuda.synchronize()
         return full, time.perf_counter() - t0
 
     zeros = torch.zeros(B.shape[0], d, device="cuda")
     ctxs = [E.Sampler(A, b, np.zeros(d), chains, seed=seed + 100 + j, precision=32)
             for j, b in enumerate(eval_b)]
-    tr, wall = timed_run(ctxs, lambda i, q: None)
+    tr, wall = timed_run(ctxs, lambda i, q: None, "plain_per_problem")
     for q in ctxs:
         q.close()
     finish("plain_per_problem", tr, zeros, wall)
@@ -243,7 +250,7 @@ def compare(E, A, eval_b, net, chains=64, steps=48000, thin=20, level=2.0, ref=N
                 gate["xhat"] = net.forward(bdev).repeat_interleave(chains, dim=0)
                 gate["acc"] = q.set_state_gated(gate["xhat"], zeros)
 
-        tr, wall = timed_run([s], start)
+        tr, wall = timed_run([s], start, name)
         x0 = zeros
         if name == "batched_warm":
             acc = gate["acc"]

@@ -52,7 +52,7 @@ def compare_transition(A, b, x, nu, u, gpu, ref, tol_ang=TOL_ANG, tol_x=TOL_X):
         rg, rr = bool(gpu["rejected"][c]), bool(ref["rejected"][c])
         if rg != rr:
             xp = ref["x_prop"][c]
-            slack = b - A @ xp
+            slack = (b[c] if np.ndim(b) == 2 else b) - A @ xp
             # float32 dot-product rounding plus the state tolerance below
             bound = fp32_dot_bound(A, xp[None, :])[0] + tol_x * (np.abs(A) @ np.maximum(np.abs(xp), 1.0))
             if np.any(np.abs(slack) <= bound):
