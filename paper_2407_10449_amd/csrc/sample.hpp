@@ -87,26 +87,38 @@ constexpr double kKeyScale = 281474976710656.0 / kTwoPi;   // 2^48 / (2 pi)
 constexpr uint64_t kKeyMax = (1ull << 48) - 1;
 constexpr int SMAX = 128;   // survivors the bucket path resolves in place
 
-// T is the storage type of p and q.  With float storage the two angles tau
-// and phi come from float32 atan2 / acos while |b / r| <= 0.99: p and q are
-// exact floats, so atan2 is off by a few float ulps (< 1e-6 rad), and the
-// rounding of z to float moves acos by at most 6e-8 / sqrt(1 - 0.99^2)
-// (< 5e-7 rad).  Near tangency (|b / r| > 0.99, where acos amplifies
-// rounding without bound) both angles are taken in float64.  r, z, the wrap,
-// alpha, beta and every later comparison stay in float64.
+// T is the storage type of p and q.  With float storage, r = hypot(p, q) and
+// z = b / r are first formed in float32 (relative error a few 1e-7).  Where
+// that z lies clearly inside (-0.99, 0.99) the row certainly crosses the
+// ellipse and both angles come from float32 atan2 / acos: p and q are exact
+// floats, so atan2 is off by a few float ulps (< 1e-6 rad), and the rounding
+// of z moves acos by at most a few 1e-7 / sqrt(1 - 0.99^2) (< 3e-6 rad).
+// Where z >= 1.01 the row certainly misses it.  Only rows in between (near
+// tangency, where acos amplifies rounding without bound, and where the
+// decision itself is close) take r, z and both angles in float64, as all rows
+// do with double storage.  The wrap, alpha, beta and every later comparison
+// are float64.
 template <typename T>
 __device__ __forceinline__ bool solve_roots(double p, double q, double bi, double& al,
                                             double& be) {
-    const double r = hypot(p, q);
-    if (!(r > 0.0)) return false;
-    double z = bi / r;
-    if (!(z < 1.0)) return false;
-    z = fmax(z, -1.0);
     double tau, phi;
-    if (sizeof(T) == 4 && fabs(z) <= 0.99) {
-        tau = static_cast<double>(atan2f(static_cast<float>(q), static_cast<float>(p)));
-        phi = static_cast<double>(acosf(static_cast<float>(z)));
-    } else {
+    bool fast = false;
+    if (sizeof(T) == 4) {
+        const float pf = static_cast<float>(p), qf = static_cast<float>(q);
+        const float zf = static_cast<float>(bi) / sqrtf(pf * pf + qf * qf);
+        if (zf >= 1.01f) return false;   // also r = 0 (z = +inf) for b > 0
+        if (fabsf(zf) <= 0.99f) {
+            tau = static_cast<double>(atan2f(qf, pf));
+            phi = static_cast<double>(acosf(zf));
+            fast = true;
+        }
+    }
+    if (!fast) {
+        const double r = hypot(p, q);
+        if (!(r > 0.0)) return false;
+        double z = bi / r;
+        if (!(z < 1.0)) return false;
+        z = fmax(z, -1.0);
         tau = atan2(q, p);
         phi = acos(z);
     }

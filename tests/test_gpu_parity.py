@@ -87,6 +87,39 @@ def test_explicit_transition_matches_oracle(E, name, d, m, C, precision, eps):
         assert abs(g["theta"][c] - ref2["theta"][c]) <= tol2 * max(1.0, len(gi)), c
 
 
+def test_near_tangent_rows_cross_both_root_branches(E):
+    """With x = 0 and per-chain b, every row's b / r is set in [0.97, 1.03], so
+    the float32 root solve's two decision thresholds (|b / r| <= 0.99 takes
+    float32 angles, b / r >= 1.01 misses) and the exact float64 band between
+    them are all exercised.  Tier 1 against the oracle; tier 2 with the
+    oracle fed the kernel's own projections, to 1e-5 rad."""
+    say("[explicit] near-tangent rows")
+    rng = np.random.default_rng(17)
+    d, m, C = 32, 512, 64
+    A = rng.standard_normal((m, d)) / math.sqrt(d)
+    A32 = A.astype(np.float32).astype(np.float64)
+    x = np.zeros((C, d), np.float32)
+    nu = rng.standard_normal((C, d)).astype(np.float32)
+    q = nu.astype(np.float64) @ A32.T
+    z = rng.uniform(0.97, 1.03, (C, m))
+    b = np.maximum(z * np.abs(q), 1e-3)
+    u = rng.uniform(size=C)
+    s = E.Sampler(A, b, x, C, seed=1, precision=32, trim_eps=1e-6)
+    g = {k: v.cpu().numpy() for k, v in s.transition_explicit(x, nu, u).items()}
+    s.close()
+    x64, nu64 = x.astype(np.float64), nu.astype(np.float64)
+    ref = ref_ess.transition(A32, b, x64, nu64, u, eps=1e-6, store=np.float32)
+    fails, excused = compare_transition(A32, b, x64, nu64, u, g, ref)
+    assert not fails, "\n".join(fails[:10])
+    assert excused <= 2
+    ref2 = ref_ess.transition(A32, b, x64, nu64, u, eps=1e-6, store=np.float32,
+                              pq=(g["pq"][0], g["pq"][1]))
+    for c in range(C):
+        gi = pieces(g["intervals"][c], g["n_intervals"][c], 0.0)
+        assert intervals_match(gi, ref2["intervals"][c], 1e-5), (c, gi, ref2["intervals"][c])
+        assert abs(g["theta"][c] - ref2["theta"][c]) <= 1e-5 * max(1.0, len(gi)), c
+
+
 def test_explicit_full_size_gp_rbf(E):
     """d=1000, m=2000, 1024 chains (the benchmarked shape): sampled chains."""
     say("[explicit] gp_rbf full size")
