@@ -82,6 +82,10 @@ def lib():
     """The loaded libess.so (raises if it has not been built)."""
     global _LIB
     if _LIB is None:
+        # torch first: libess.so must bind to the HIP runtime torch has loaded
+        # (loading libess.so first brings in a second runtime, which then sees
+        # no device)
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"libess.so is not built at {LIB_PATH}; run "
                               "`python -m paper_2407_10449_amd.build` first")

@@ -126,3 +126,21 @@ def test_batched_launch_forms_and_tiles_give_identical_chains(E, monkeypatch, la
     got, _ = b.run(5)
     b.close()
     assert torch.equal(got, want)
+
+
+def test_batched_problem_zero_equals_its_own_context(E):
+    """The first problem of a batch draws with problem word 0, as a
+    single-problem context does, and every projection sums in the same order
+    whatever the tile: its chains are bit-identical to the same problem run
+    alone."""
+    probs = problems(7, 16, seed=31)
+    a = E.BatchedSampler(probs)
+    tr, _ = a.run(6)
+    first = a.split(tr)[0]
+    a.close()
+    p = probs[0]
+    s = E.Sampler(p["A"], p["b"], p["x0"], p["n_chains"], seed=p["seed"], precision=32,
+                  trim_eps=p["trim_eps"])
+    alone, _ = s.run(6)
+    s.close()
+    assert torch.equal(first, alone)

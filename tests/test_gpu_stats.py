@@ -105,3 +105,57 @@ def test_float64_never_rejects(E):
     s.close()
     assert nrej == 0
     assert (X @ pr.A.T <= pr.b).all()
+
+
+def test_matches_iid_rejection_sampling_reference(E):
+    """A small polytope (d=3, m=5, about 2 % of N(0, I) inside) where plain
+    rejection sampling is exact: GPU chain means and variances agree with the
+    i.i.d. reference within Monte Carlo error, in both precisions."""
+    rng = np.random.default_rng(23)
+    A = np.array([[1.0, 1.0, 0.0], [-1.0, 0.5, 0.3], [0.3, -1.0, 0.5], [0.0, 0.4, -1.0],
+                  [0.6, 0.2, 0.9]])
+    b = np.array([0.4, 0.3, 0.5, 0.2, 0.3])
+    z = rng.standard_normal((2_000_000, 3))
+    keep = z[(z @ A.T <= b).all(axis=1)]
+    say(f"[iid] acceptance {len(keep) / len(z):.3f}")
+    assert len(keep) / len(z) > 0.01
+    ref_m, ref_v = keep.mean(axis=0), keep.var(axis=0)
+    for precision in (32, 64):
+        s = E.Sampler(A, b, np.zeros(3), 4096, seed=5, precision=precision)
+        s.run(50, keep_trace=False)
+        tr, _ = s.run(400, thin=4)
+        g = tr.double().cpu().numpy()
+        s.close()
+        for j in range(3):
+            se = math.hypot(D.mcse_mean(g[:, :, j]), keep[:, j].std() / math.sqrt(len(keep)))
+            assert abs(g[:, :, j].mean() - ref_m[j]) <= 4 * se, (precision, j)
+            gv = g[:, :, j].var()
+            sev = math.hypot(D.mcse_mean((g[:, :, j] - g[:, :, j].mean()) ** 2),
+                             ((keep[:, j] - ref_m[j]) ** 2).std() / math.sqrt(len(keep)))
+            assert abs(gv - ref_v[j]) <= 4 * sev, (precision, j, gv, ref_v[j])
+
+
+@pytest.mark.parametrize("d,chains,steps,precision,max_rate",
+                         [(100, 10, 100, 32, 0.0), (1000, 10, 100, 32, 0.01),
+                          (1000, 1, 1000, 32, 0.01), (1000, 10, 100, 64, 0.0)])
+def test_section_4_2_instances(E, d, chains, steps, precision, max_rate):
+    """Section 4.2's timing instances (A d x d N(0, 1), x0 N(0, I),
+    b = A x0 + U[0, 1]^d, started at x0) over the paper's run lengths: every
+    recorded state is feasible (up to float32 rounding of the products), and
+    safeguard rejections stay practically absent.  In float64 there are none
+    (Section 3.3).  In float32 the rows' norms (about sqrt(d)) make the
+    float32-accumulated projections' rounding comparable to the slack that a
+    1e-6 rad trim leaves, so a rejection now and then is expected at d = 1000
+    (about 0.2 % of transitions measured); d = 100 has none."""
+    pr = synth.paper_highdim(d=d, n_chains=chains, n_steps=steps)
+    s = E.Sampler(pr.A, pr.b, pr.x0, chains, seed=2, precision=precision)
+    tr, nrej = s.run(steps, thin=max(1, steps // 50))
+    X = tr.double().cpu().numpy().reshape(-1, d)
+    s.close()
+    say(f"[4.2] d={d} chains={chains} steps={steps} f{precision} rejections={nrej}")
+    assert nrej <= max_rate * chains * steps
+    Ar = pr.A.astype(np.float32).astype(np.float64) if precision == 32 else pr.A
+    slack = pr.b - X @ Ar.T
+    unit = 2.0 ** -24 if precision == 32 else 2.0 ** -53
+    bound = 2 * d * unit * (np.abs(X) @ np.abs(Ar).T)
+    assert (slack >= -bound).all()
