@@ -100,11 +100,12 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // values 4 (l / 16) .. 4 (l / 16) + 3 of its row as one 16-byte LDS read, and
 // MFMA number kk uses element kk: A and B use the same k for the same (lane
 // group, kk), so the contraction covers all 16 k exactly once.  Rows in LDS
-// are padded to 36 floats, which spreads the 16 rows of one read over
-// distinct banks.
-template <int BM, int BN>
+// are padded by PADK floats so that the rows of one fragment read fall on
+// distinct banks; the padding never changes the order of the sums, so every
+// tile shape and padding gives bit-identical products.
+template <int BM, int BN, int PADK = 4>
 struct GemmLds {
-    static constexpr int BK = 32, LK = BK + 4;
+    static constexpr int BK = 32, LK = BK + PADK;
     float As[2][BM * LK];
     float Bs[2][BN * LK];
 };
@@ -112,13 +113,13 @@ struct GemmLds {
 // One BM x BN output tile at (m0, n0) of the group described by `o`; B0 / B1
 // point at the group's first x' / nu row.  All NW_M x NW_N waves of the block
 // call it; the tile ends with the block synchronised.
-template <int BM, int BN, int NW_M = 2, int NW_N = 2>
+template <int BM, int BN, int NW_M = 2, int NW_N = 2, int PADK = 4>
 __device__ __forceinline__ void gemm_tile_f32(const float* __restrict__ A,
                                               const float* __restrict__ B0,
                                               const float* __restrict__ B1, int K, int m0, int n0,
-                                              const ProjOut& o, GemmLds<BM, BN>& L) {
+                                              const ProjOut& o, GemmLds<BM, BN, PADK>& L) {
     constexpr int NT = 64 * NW_M * NW_N;
-    constexpr int BK = GemmLds<BM, BN>::BK, LK = GemmLds<BM, BN>::LK;
+    constexpr int BK = GemmLds<BM, BN, PADK>::BK, LK = GemmLds<BM, BN, PADK>::LK;
     constexpr int WM = BM / NW_M, WN = BN / NW_N, TM = WM / 16, TN = WN / 16;
     constexpr int ALD = BM * BK / 4 / NT, BLD = BN * BK / 4 / NT;
     static_assert(ALD >= 1 && BLD >= 1 && TM >= 1 && TN >= 1, "tile too small for the waves");
@@ -203,27 +204,22 @@ __device__ __forceinline__ void gemm_tile_f32(const float* __restrict__ A,
         }
 }
 
-// float32 projections on the matrix cores (v_mfma_f32_16x16x4_f32), float32
-// accumulation.  NW_M x NW_N waves, each owning a (BM / NW_M) x (BN / NW_N)
-// block of 16 x 16 MFMA tiles; 128 x 128 tiles use 4 x 2 waves (two per
-// SIMD, which hides LDS and barrier latency behind the other wave's MFMAs).  K advances 32 at a time through a double-
-// buffered LDS tile.  Inside each group of 16 k, lane l supplies the four k
-// values 4 (l / 16) .. 4 (l / 16) + 3 of its row as one 16-byte LDS read, and
-// MFMA number kk uses element kk: A and B use the same k for the same (lane
-// group, kk), so the contraction covers all 16 k exactly once.  Rows in LDS
-// are padded to 36 floats, which spreads the 16 rows of one read over
-// distinct banks.
+// One launch of gemm_tile_f32 tiles over a group of chains (see above), with
+// the XCD-aware tile order of tile_coords.
 template <int BM, int BN, int NW_M, int NW_N>
 __global__ __launch_bounds__(64 * NW_M * NW_N) void proj_gemm_f32(const float* __restrict__ A,
                                                                   const float* __restrict__ B0,
                                                                   const float* __restrict__ B1,
                                                                   int K, int tiles_m, int tiles_n,
                                                                   int tn0, int group_m, ProjOut o) {
-    __shared__ __attribute__((aligned(16))) GemmLds<BM, BN> lds;
+    // rows of 40 floats: measured free of LDS bank conflicts at the
+    // benchmarked shape, where rows of 36 conflicted (about 3.2M conflict
+    // cycles per launch) and cost 3 % of the kernel time
+    __shared__ __attribute__((aligned(16))) GemmLds<BM, BN, 8> lds;
     int tm, tn;
     tile_coords(blockIdx.x, tiles_m, tiles_n, group_m, tm, tn);
     tn += tn0;
-    gemm_tile_f32<BM, BN, NW_M, NW_N>(A, B0, B1, K, tm * BM, tn * BN, o, lds);
+    gemm_tile_f32<BM, BN, NW_M, NW_N, 8>(A, B0, B1, K, tm * BM, tn * BN, o, lds);
 }
 
 // float64 projections on the vector ALUs (MI355X runs float64 FMA on the
