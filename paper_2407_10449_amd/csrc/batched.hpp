@@ -232,7 +232,7 @@ __global__ __launch_bounds__(256) void batched_step_kernel(BatchArgs a) {
 
 // Split form, second launch: one workgroup per chain (the caller's order).
 template <int RPT, int NB>
-__global__ __launch_bounds__(256) void batched_chain_kernel(BatchArgs a) {
+__global__ __launch_bounds__(256, RPT <= 8 ? 6 : 1) void batched_chain_kernel(BatchArgs a) {
     __shared__ __attribute__((aligned(16))) BucketLds<NB> lds;
     const int par = static_cast<int>(abs_step(a) & 1u);
     if (blockIdx.x == 0 && threadIdx.x == 0) a.fb_count[par ^ 1] = 0;   // the next step's list

@@ -87,38 +87,37 @@ constexpr double kKeyScale = 281474976710656.0 / kTwoPi;   // 2^48 / (2 pi)
 constexpr uint64_t kKeyMax = (1ull << 48) - 1;
 constexpr int SMAX = 128;   // survivors the bucket path resolves in place
 
-// T is the storage type of p and q.  With float storage, r = hypot(p, q) and
-// z = b / r are first formed in float32 (relative error a few 1e-7).  Where
-// that z lies clearly inside (-0.99, 0.99) the row certainly crosses the
-// ellipse and both angles come from float32 atan2 / acos: p and q are exact
-// floats, so atan2 is off by a few float ulps (< 1e-6 rad), and the rounding
-// of z moves acos by at most a few 1e-7 / sqrt(1 - 0.99^2) (< 3e-6 rad).
-// Where z >= 1.01 the row certainly misses it.  Only rows in between (near
-// tangency, where acos amplifies rounding without bound, and where the
-// decision itself is close) take r, z and both angles in float64, as all rows
-// do with double storage.  The wrap, alpha, beta and every later comparison
-// are float64.
+// T is the storage type of p and q.  With float storage, a float32 estimate
+// of z = b / r (relative error a few 1e-7) first discards rows that certainly
+// miss the ellipse (z >= 1.01), which saves the float64 work for about a third
+// of the rows at the benchmarked shape.  For every other row r and z are
+// float64, and while |z| <= 0.99 the two angles come from float32 atan2 / acos
+// of the exact floats p, q and of z rounded once: atan2 is off by a few float
+// ulps (< 1e-6 rad) and that rounding moves acos by at most
+// 6e-8 / sqrt(1 - 0.99^2) (< 5e-7 rad), inside the 1e-6 rad trim of the
+// interval ends.  (A float32 z, rounded several times, moved acos by up to
+// 1.5e-6 rad there and let a few proposals cross a constraint.)  Near
+// tangency, where acos amplifies rounding without bound, both angles are
+// float64, as all of them are with double storage.  The wrap, alpha, beta and
+// every later comparison are float64.
 template <typename T>
 __device__ __forceinline__ bool solve_roots(double p, double q, double bi, double& al,
                                             double& be) {
-    double tau, phi;
-    bool fast = false;
     if (sizeof(T) == 4) {
         const float pf = static_cast<float>(p), qf = static_cast<float>(q);
-        const float zf = static_cast<float>(bi) / sqrtf(pf * pf + qf * qf);
-        if (zf >= 1.01f) return false;   // also r = 0 (z = +inf) for b > 0
-        if (fabsf(zf) <= 0.99f) {
-            tau = static_cast<double>(atan2f(qf, pf));
-            phi = static_cast<double>(acosf(zf));
-            fast = true;
-        }
+        if (static_cast<float>(bi) / sqrtf(pf * pf + qf * qf) >= 1.01f)
+            return false;   // also r = 0 (z = +inf) for b > 0
     }
-    if (!fast) {
-        const double r = hypot(p, q);
-        if (!(r > 0.0)) return false;
-        double z = bi / r;
-        if (!(z < 1.0)) return false;
-        z = fmax(z, -1.0);
+    const double r = hypot(p, q);
+    if (!(r > 0.0)) return false;
+    double z = bi / r;
+    if (!(z < 1.0)) return false;
+    z = fmax(z, -1.0);
+    double tau, phi;
+    if (sizeof(T) == 4 && fabs(z) <= 0.99) {
+        tau = static_cast<double>(atan2f(static_cast<float>(q), static_cast<float>(p)));
+        phi = static_cast<double>(acosf(static_cast<float>(z)));
+    } else {
         tau = atan2(q, p);
         phi = acos(z);
     }
@@ -562,13 +561,16 @@ __global__ void zero_ints(int* p, int n) {
 template <int NB>
 struct BucketLds {
     unsigned long long G[NB];          // bucket max beta, then prefix max
-    double sa[SMAX], sb[SMAX];         // survivors: alpha, beta
+    signed char head[NB];              // last survivor of each bucket, -1 if none
+    double sa[SMAX];                   // survivors: alpha
     int si[SMAX], sk[SMAX];            // survivors: row, bucket
+    signed char nxt[SMAX];             // previous survivor of the same bucket, -1 if none
     unsigned long long sm[SMAX];       // survivors: in-bucket predecessor max
     double lo[SMAX + 1], hi[SMAX + 1];
+    double len[SMAX + 1], cum[SMAX + 1];   // candidate lengths, their running sums
     double red[4];
-    double gtot;
-    int scount;
+    double gtot, total, u;
+    int scount, kstar, klast;
     double theta;
 };
 
@@ -578,7 +580,10 @@ template <typename T, int RPT, int NB>
 __device__ bool bucket_chain(const ChainRef<T>& r, int sel, BucketLds<NB>& L) {
     const int tid = threadIdx.x;
     constexpr double kBucket = NB / kTwoPi;
-    for (int b = tid; b < NB; b += 256) L.G[b] = 0ull;
+    for (int b = tid; b < NB; b += 256) {
+        L.G[b] = 0ull;
+        L.head[b] = -1;
+    }
     if (tid == 0) L.scount = 0;
 
     // roots of this thread's rows (row i = tid + 256 r); beta = 0 marks no crossing
@@ -637,7 +642,6 @@ __device__ bool bucket_chain(const ChainRef<T>& r, int sel, BucketLds<NB>& L) {
             const int k = atomicAdd(&L.scount, 1);
             if (k < SMAX) {
                 L.sa[k] = al[j];
-                L.sb[k] = be[j];
                 L.si[k] = tid + 256 * j;
                 L.sk[k] = bk[j];
                 L.sm[k] = 0ull;
@@ -648,13 +652,34 @@ __device__ bool bucket_chain(const ChainRef<T>& r, int sel, BucketLds<NB>& L) {
     const int S = L.scount;
     if (S > SMAX) return false;
 
+    // survivors chained per bucket, so a row meets only its own bucket's
+    // survivors (a row-by-survivor scan cost tens of microseconds per chain):
+    // survivor s links to the previous survivor of its bucket, and the last
+    // one heads the bucket; meanwhile another wave draws this step's uniform
+    static_assert(SMAX <= 128, "survivor links are bytes");
+    if (tid < S) {
+        const int b = L.sk[tid];
+        int prev = -1;
+        bool last = true;
+        for (int s = 0; s < S; ++s) {
+            if (L.sk[s] == b) {
+                if (s < tid) prev = s;
+                else if (s > tid) last = false;
+            }
+        }
+        L.nxt[tid] = static_cast<signed char>(prev);
+        if (last) L.head[b] = static_cast<signed char>(tid);
+    }
+    if (tid == 64) L.u = theta_uniform(r);
+    __syncthreads();
+
     // exact predecessor max inside each survivor's bucket (ties by row index)
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
         if (be[j] > 0.0) {
             const int i = tid + 256 * j;
-            for (int s = 0; s < S; ++s) {
-                if (L.sk[s] == bk[j] && (al[j] < L.sa[s] || (al[j] == L.sa[s] && i < L.si[s])))
+            for (int s = L.head[bk[j]]; s >= 0; s = L.nxt[s]) {
+                if (al[j] < L.sa[s] || (al[j] == L.sa[s] && i < L.si[s]))
                     atomicMax(&L.sm[s], obits(be[j]));
             }
         }
@@ -682,47 +707,100 @@ __device__ bool bucket_chain(const ChainRef<T>& r, int sel, BucketLds<NB>& L) {
         const double g = L.gtot;
         L.lo[S] = g > 0.0 ? g + eps : g;
         L.hi[S] = kTwoPi;
+        L.kstar = 1 << 30;
+        L.klast = -1;
     }
     __syncthreads();
 
-    // inverse CDF over the S + 1 candidates in order (a sequential sum, so the
-    // running sums are those of a left-to-right cumulative sum)
-    if (tid == 0) {
-        double total = 0.0;
-        for (int k = 0; k <= S; ++k) total += fmax(L.hi[k] - L.lo[k], 0.0);
-        double theta = 0.0;
-        if (total > 0.0) {
-            const double s = theta_uniform(r) * total;
-            double run = 0.0;
-            int last = -1;
-            bool found = false;
-            for (int k = 0; k <= S; ++k) {
-                const double len = fmax(L.hi[k] - L.lo[k], 0.0);
-                if (len > 0.0) {
-                    last = k;
-                    if (!found && run + len > s) {
-                        theta = fmax(L.lo[k], fmin(L.lo[k] + (s - run), L.hi[k]));
-                        found = true;
+    // inverse CDF over the S + 1 candidates in order: the running sums are a
+    // sequential left-to-right sum (those of a cumulative sum), and theta lies
+    // in the first non-empty candidate whose running sum exceeds s = u L.  Few
+    // candidates: one thread walks them.  Many: the lengths are formed in
+    // parallel, one thread keeps the running sums, and the search is
+    // parallel.  Both give the same theta bit for bit.
+    if (S < 16) {
+        if (tid == 0) {
+            double total = 0.0;
+            for (int k = 0; k <= S; ++k) total += fmax(L.hi[k] - L.lo[k], 0.0);
+            double theta = 0.0;
+            if (total > 0.0) {
+                const double sv = L.u * total;
+                double run = 0.0;
+                int last = -1;
+                bool found = false;
+                for (int k = 0; k <= S; ++k) {
+                    const double len = fmax(L.hi[k] - L.lo[k], 0.0);
+                    if (len > 0.0) {
+                        last = k;
+                        if (!found && run + len > sv) {
+                            theta = fmax(L.lo[k], fmin(L.lo[k] + (sv - run), L.hi[k]));
+                            found = true;
+                        }
                     }
+                    run += len;
                 }
-                run += len;
+                if (!found) theta = L.hi[last];   // rounding put s at the total
+            } else {
+                *r.flag = 1;   // empty active set: stay, counted as a rejection
             }
-            if (!found) theta = L.hi[last];
-        } else {
+            L.theta = theta;
+        }
+    } else {
+        if (tid <= S) L.len[tid] = fmax(L.hi[tid] - L.lo[tid], 0.0);
+        __syncthreads();
+        if (tid == 0) {
+            double run = 0.0;
+            int k = 0;
+            for (; k + 4 <= S + 1; k += 4) {
+                const double l0 = L.len[k], l1 = L.len[k + 1], l2 = L.len[k + 2], l3 = L.len[k + 3];
+                run += l0;
+                L.cum[k] = run;
+                run += l1;
+                L.cum[k + 1] = run;
+                run += l2;
+                L.cum[k + 2] = run;
+                run += l3;
+                L.cum[k + 3] = run;
+            }
+            for (; k <= S; ++k) {
+                run += L.len[k];
+                L.cum[k] = run;
+            }
+            L.total = run;
+        }
+        __syncthreads();
+        const double total = L.total;
+        if (total > 0.0) {
+            const double sv = L.u * total;
+            if (tid <= S && L.len[tid] > 0.0) {
+                if (L.cum[tid] > sv) atomicMin(&L.kstar, tid);
+                atomicMax(&L.klast, tid);
+            }
+            __syncthreads();
+            if (tid == 0) {
+                const int k = L.kstar;
+                if (k <= S) {
+                    const double before = k > 0 ? L.cum[k - 1] : 0.0;
+                    L.theta = fmax(L.lo[k], fmin(L.lo[k] + (sv - before), L.hi[k]));
+                } else {
+                    L.theta = L.hi[L.klast];   // rounding put s at the total
+                }
+            }
+        } else if (tid == 0) {
+            L.theta = 0.0;
             *r.flag = 1;   // empty active set: stay, counted as a rejection
         }
-        L.theta = theta;
-        if (r.intervals) {
-            int w = 0;
-            for (int k = 0; k <= S; ++k) {
-                if (L.hi[k] - L.lo[k] > 0.0) {
-                    r.intervals[2 * w] = L.lo[k];
-                    r.intervals[2 * w + 1] = L.hi[k];
-                    ++w;
-                }
+    }
+    if (tid == 0 && r.intervals) {
+        int w = 0;
+        for (int k = 0; k <= S; ++k) {
+            if (L.hi[k] - L.lo[k] > 0.0) {
+                r.intervals[2 * w] = L.lo[k];
+                r.intervals[2 * w + 1] = L.hi[k];
+                ++w;
             }
-            if (r.n_intervals) *r.n_intervals = w;
         }
+        if (r.n_intervals) *r.n_intervals = w;
     }
     __syncthreads();
     move_chain<T>(r, L.theta);

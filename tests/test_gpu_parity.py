@@ -276,6 +276,19 @@ def test_sorting_reduction_takes_full_path(E, precision):
     assert not fails, fails[:5]
 
 
+@pytest.mark.parametrize("precision,n_arcs", [(32, 20), (32, 100), (64, 60)])
+def test_many_survivors_stay_on_the_bucket_path(E, precision, n_arcs):
+    """Section 3.1's construction with fewer gaps than the bucket path holds:
+    every row is a survivor (20 to 100 of them), so the inverse CDF runs over
+    many candidates on the bucket path (its parallel form from 16 on)."""
+    rng = np.random.default_rng(11 + n_arcs)
+    c = 0.1 + 5.9 * (np.arange(n_arcs) + rng.uniform(0.2, 0.4, n_arcs)) / n_arcs
+    Ab, b, x, nu, u, g, ref = run_arcs(E, c, c + 0.005, precision)
+    assert (g["n_intervals"] == n_arcs + 1).all(), g["n_intervals"]
+    fails, _ = compare_transition(Ab, b, x, nu, u, g, ref)
+    assert not fails, fails[:5]
+
+
 @pytest.mark.parametrize("precision,m", [(32, 7), (64, 14)])
 def test_appendix_d_nested_arcs_in_one_bucket(E, precision, m):
     """Appendix D's worst case, I_i = [0, 3^-i] U [2 3^-i, 1] (scaled by 2 pi),
