@@ -108,7 +108,9 @@ __device__ __forceinline__ bool solve_roots(double p, double q, double bi, doubl
         if (static_cast<float>(bi) / sqrtf(pf * pf + qf * qf) >= 1.01f)
             return false;   // also r = 0 (z = +inf) for b > 0
     }
-    const double r = hypot(p, q);
+    // float p, q: their squares are exact in float64 and their sum can
+    // neither overflow nor underflow, so the plain root is within an ulp
+    const double r = sizeof(T) == 4 ? sqrt(p * p + q * q) : hypot(p, q);
     if (!(r > 0.0)) return false;
     double z = bi / r;
     if (!(z < 1.0)) return false;
