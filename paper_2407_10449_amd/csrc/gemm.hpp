@@ -32,10 +32,12 @@ struct ProjOut {
     int strict;       // 1: violation is p >= b (start check), 0: p > b (safeguard)
 };
 
-// Four consecutive rows i0 .. i0 + 3 of virtual column n.
+// Four consecutive rows i0 .. i0 + 3 of virtual column n.  bpre, when given
+// and b is shared by all chains, holds b of those rows (+inf past m), loaded
+// by the caller ahead of time.
 template <typename T>
 __device__ __forceinline__ void proj_store4(const ProjOut& o, int n, int i0, T v0, T v1, T v2,
-                                            T v3) {
+                                            T v3, const double* bpre = nullptr) {
     if (n < o.Cg) {
         const int c = o.c0 + n;
         const int s = o.sel[c];
@@ -52,8 +54,10 @@ __device__ __forceinline__ void proj_store4(const ProjOut& o, int n, int i0, T v
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int i = i0 + r;
-                if (i < o.m) {
-                    const double pv = static_cast<double>(vv[r]);
+                const double pv = static_cast<double>(vv[r]);
+                if (bpre != nullptr && o.bstride == 0) {
+                    bad |= o.strict ? (pv >= bpre[r]) : (pv > bpre[r]);
+                } else if (i < o.m) {
                     const double bi = o.b[static_cast<size_t>(c) * o.bstride + i];
                     bad |= o.strict ? (pv >= bi) : (pv > bi);
                 }
@@ -161,6 +165,21 @@ __device__ __forceinline__ void gemm_tile_f32(const float* __restrict__ A,
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+    // b of this thread's output rows, read before the main loop so that its
+    // latency hides there (with one b for all chains; a b per chain is read
+    // per element in the epilogue).  Stores to P may alias b for the compiler,
+    // which otherwise reloads it after every store.
+    double brow[TM][4];
+    if (n0 < o.Cg && o.bstride == 0) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + wm * WM + i * 16 + (lane >> 4) * 4 + r;
+                brow[i][r] = row < o.m ? o.b[row] : __builtin_inf();
+            }
+    }
+
     const int KT = K / BK;
     gload(0);
     lstore(0);
@@ -200,7 +219,8 @@ __device__ __forceinline__ void gemm_tile_f32(const float* __restrict__ A,
         for (int j = 0; j < TN; ++j) {
             const int i0 = m0 + wm * WM + i * 16 + (lane >> 4) * 4;
             const int n = n0 + wn * WN + j * 16 + (lane & 15);
-            proj_store4<float>(o, n, i0, acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]);
+            proj_store4<float>(o, n, i0, acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3],
+                               brow[i]);
         }
 }
 
