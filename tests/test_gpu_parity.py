@@ -145,6 +145,77 @@ def test_no_constraint_crosses_the_ellipse(E):
     assert not fails
 
 
+def fig2_rows():
+    import os
+    rows = []
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fig2_edge_cases.txt")
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            f = line.split()
+            if f[2] != "invalid":
+                rows.append((float(f[0]), f[2]))
+    return rows
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+@pytest.mark.parametrize("c,case", fig2_rows(), ids=[r[1] for r in fig2_rows()])
+def test_figure_2_edge_cases_on_the_gpu(E, precision, c, case):
+    """Figure 2's cases through the kernels (x = (2, 0), nu = (0, 1), feasible
+    side x_1 >= c), untrimmed: no root and the tangent leave the whole
+    ellipse, and two roots cut out (2 pi / 3, 4 pi / 3).  With c = 2 the
+    figure's x_t lies on the boundary (b / r = -1), which the library refuses:
+    it requires a strictly interior state."""
+    npdt = np.float32 if precision == 32 else np.float64
+    A = np.array([[-1.0, 0.0]])
+    b = np.array([-c])
+    C = 4
+    x = np.tile(np.array([2.0, 0.0], npdt), (C, 1))
+    nu = np.tile(np.array([0.0, 1.0], npdt), (C, 1))
+    u = (np.arange(C) + 0.5) / C
+    s = E.Sampler(A, b, np.array([3.0, 0.0]), C, seed=0, precision=precision, trim_eps=0.0)
+    if case == "single_root_boundary":
+        with pytest.raises(E.EssError, match="not strictly feasible"):
+            s.transition_explicit(x, nu, u)
+        s.close()
+        return
+    g = {k: v.cpu().numpy() for k, v in s.transition_explicit(x, nu, u).items()}
+    s.close()
+    want = ([(0.0, 2 * math.pi)] if case != "two_roots"
+            else [(0.0, 2 * math.pi / 3), (4 * math.pi / 3, 2 * math.pi)])
+    tol = 1e-6 if precision == 32 else 1e-12
+    for ch in range(C):
+        got = pieces(g["intervals"][ch], g["n_intervals"][ch], 0.0)
+        assert len(got) == len(want), (ch, got)
+        for (lo, hi), (wlo, whi) in zip(got, want):
+            assert abs(lo - wlo) <= tol and abs(hi - whi) <= tol, (ch, got)
+    assert (g["rejected"] == 0).all()
+
+
+@pytest.mark.parametrize("precision,gap,eps", [(64, 1e-7, 1e-6), (32, 1e-5, 1e-4)])
+def test_trimmed_away_active_set_stays_and_counts_a_rejection(E, precision, gap, eps):
+    """Two forbidden arcs leave only [0, gap/2] and [2 pi - gap/2, 2 pi] around
+    the current state; trimming by eps > gap/2 empties both (Section 3.3), so
+    the chain stays where it is, the step is reported as rejected, and each
+    chain's rejection counter grows by one."""
+    alpha = np.array([gap / 2, 3.0])
+    beta = np.array([3.0, 2 * math.pi - gap / 2])
+    A, b = arcs_problem(alpha, beta)
+    npdt = np.float32 if precision == 32 else np.float64
+    C = 8
+    x = np.tile(np.array([1.0, 0.0], npdt), (C, 1))
+    nu = np.tile(np.array([0.0, 1.0], npdt), (C, 1))
+    u = (np.arange(C) + 0.5) / C
+    s = E.Sampler(A, b, x, C, seed=0, precision=precision, trim_eps=eps)
+    g = {k: v.cpu().numpy() for k, v in s.transition_explicit(x, nu, u).items()}
+    assert (g["n_intervals"] == 0).all() and (g["rejected"] == 1).all()
+    assert np.array_equal(g["x_new"], x)
+    assert (s.rejections() == 1).all()
+    ref = ref_ess.transition(A.astype(npdt).astype(np.float64), b, x.astype(np.float64),
+                             nu.astype(np.float64), u, eps=eps, store=npdt)
+    assert np.asarray(ref["rejected"]).all()
+    s.close()
+
+
 @pytest.mark.parametrize("precision", [32, 64])
 def test_philox_stream_matches_oracle(E, precision):
     pr = synth.small_fp64(d=33, m=20, n_chains=70)
