@@ -171,8 +171,9 @@ struct SumOp {
     __device__ double operator()(double a, double b) const { return a + b; }
 };
 
-// Exclusive scan of one value per thread (thread order), identity `id`.
-template <typename Op>
+// Exclusive scan of one value per thread (thread order), identity `id`, over
+// a block of NW waves; s_w holds NW values.
+template <typename Op, int NW = 4>
 __device__ __forceinline__ double block_excl_scan(double v, double id, Op op, double* s_w) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     double x = v;
@@ -187,7 +188,7 @@ __device__ __forceinline__ double block_excl_scan(double v, double id, Op op, do
     __syncthreads();
     double pre = id;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < NW; ++i)
         if (i < w) pre = op(pre, s_w[i]);
     __syncthreads();
     return (lane == 0) ? pre : op(pre, ex);
@@ -558,7 +559,8 @@ __global__ void zero_ints(int* p, int n) {
 }
 
 // ---------------------------------------------------------------------------
-// Bucket path.  RPT rows per thread (m <= 256 RPT), NB angle buckets.
+// Bucket path.  BS threads per chain (256 or 512), RPT rows per thread
+// (m <= BS RPT), NB angle buckets.
 // ---------------------------------------------------------------------------
 template <int NB>
 struct BucketLds {
@@ -570,7 +572,7 @@ struct BucketLds {
     unsigned long long sm[SMAX];       // survivors: in-bucket predecessor max
     double lo[SMAX + 1], hi[SMAX + 1];
     double len[SMAX + 1], cum[SMAX + 1];   // candidate lengths, their running sums
-    double red[4];
+    double red[8];
     double gtot, total, u;
     int scount, kstar, klast;
     double theta;
@@ -578,23 +580,24 @@ struct BucketLds {
 
 // Returns false when the chain has more than SMAX survivors: nothing has been
 // moved and the caller hands the chain to the full path.
-template <typename T, int RPT, int NB>
+template <typename T, int RPT, int NB, int BS = 256>
 __device__ bool bucket_chain(const ChainRef<T>& r, int sel, BucketLds<NB>& L) {
+    static_assert(BS == 256 || BS == 512, "one chain per 256 or 512 threads");
     const int tid = threadIdx.x;
     constexpr double kBucket = NB / kTwoPi;
-    for (int b = tid; b < NB; b += 256) {
+    for (int b = tid; b < NB; b += BS) {
         L.G[b] = 0ull;
         L.head[b] = -1;
     }
     if (tid == 0) L.scount = 0;
 
-    // roots of this thread's rows (row i = tid + 256 r); beta = 0 marks no crossing
+    // roots of this thread's rows (row i = tid + BS r); beta = 0 marks no crossing
     const T* Pc = r.P0 + static_cast<size_t>(sel) * r.pstride;
     double al[RPT], be[RPT];
     int bk[RPT];
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
-        const int i = tid + 256 * j;
+        const int i = tid + BS * j;
         al[j] = 0.0;
         be[j] = 0.0;
         bk[j] = 0;
@@ -619,12 +622,13 @@ __device__ bool bucket_chain(const ChainRef<T>& r, int sel, BucketLds<NB>& L) {
     __syncthreads();
 
     // exclusive prefix max over buckets, in place: G[b] = max beta of rows in
-    // buckets < b (0 if none); thread t owns buckets [t NB/256, (t+1) NB/256)
-    constexpr int BPT = NB / 256;
+    // buckets < b (0 if none); thread t owns buckets [t NB/BS, (t+1) NB/BS)
+    constexpr int BPT = NB / BS;
+    static_assert(BPT >= 1, "at least one bucket per thread");
     double tmax = 0.0;
 #pragma unroll
     for (int j = 0; j < BPT; ++j) tmax = fmax(tmax, ofloat(L.G[tid * BPT + j]));
-    const double g_in = block_excl_scan(tmax, 0.0, MaxOp(), L.red);
+    const double g_in = block_excl_scan<MaxOp, BS / 64>(tmax, 0.0, MaxOp(), L.red);
     {
         double run = g_in;
 #pragma unroll
@@ -633,7 +637,7 @@ __device__ bool bucket_chain(const ChainRef<T>& r, int sel, BucketLds<NB>& L) {
             L.G[tid * BPT + j] = obits(run);
             run = fmax(run, v);
         }
-        if (tid == 255) L.gtot = run;   // gamma_n: max beta over all rows
+        if (tid == BS - 1) L.gtot = run;   // gamma_n: max beta over all rows
     }
     __syncthreads();
 
@@ -644,7 +648,7 @@ __device__ bool bucket_chain(const ChainRef<T>& r, int sel, BucketLds<NB>& L) {
             const int k = atomicAdd(&L.scount, 1);
             if (k < SMAX) {
                 L.sa[k] = al[j];
-                L.si[k] = tid + 256 * j;
+                L.si[k] = tid + BS * j;
                 L.sk[k] = bk[j];
                 L.sm[k] = 0ull;
             }
@@ -679,7 +683,7 @@ __device__ bool bucket_chain(const ChainRef<T>& r, int sel, BucketLds<NB>& L) {
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
         if (be[j] > 0.0) {
-            const int i = tid + 256 * j;
+            const int i = tid + BS * j;
             for (int s = L.head[bk[j]]; s >= 0; s = L.nxt[s]) {
                 if (al[j] < L.sa[s] || (al[j] == L.sa[s] && i < L.si[s]))
                     atomicMax(&L.sm[s], obits(be[j]));
@@ -809,15 +813,15 @@ __device__ bool bucket_chain(const ChainRef<T>& r, int sel, BucketLds<NB>& L) {
     return true;
 }
 
-template <typename T, int RPT, int NB>
-__global__ __launch_bounds__(256) void sample_bucket_kernel(SampleArgs a) {
+template <typename T, int RPT, int NB, int BS = 256>
+__global__ __launch_bounds__(BS, (BS == 512 && RPT <= 4) ? 8 : 1) void sample_bucket_kernel(SampleArgs a) {
     __shared__ BucketLds<NB> lds;
     const int c = a.c0 + blockIdx.x;
     const ChainRef<T> r = make_ref<T>(a, c);
     const int sel = a.has_pending ? commit_chain<T>(r) : *r.sel;
     const uint32_t step = r.step;
     if (blockIdx.x == 0 && threadIdx.x == 0) a.fb_count[(step + 1) & 1] = 0;   // next step's list
-    const bool done = !a.force_full && bucket_chain<T, RPT, NB>(r, sel, lds);
+    const bool done = !a.force_full && bucket_chain<T, RPT, NB, BS>(r, sel, lds);
     if (!done && threadIdx.x == 0) a.fb_list[atomicAdd(a.fb_count + (step & 1), 1)] = c;
 }
 
