@@ -150,6 +150,34 @@ def bench_warm_start(E, torch, log, steps=48000):
     return cmp
 
 
+def bench_paper_timing(E, torch, dims=(100, 250, 500, 1000, 2000, 4000)):
+    """Section 4.2's timing protocol on its own instances (A d x d N(0, 1),
+    x0 N(0, I), b = A x0 + U[0, 1]^d, so m = d): wall time for 1000 samples
+    as one chain x 1000 steps and as 10 chains x 100 steps, no burn-in or
+    thinning, float32, after one untimed run of the same shape (graph
+    capture)."""
+    import numpy as np
+    import synth
+    out = []
+    for d in dims:
+        row = {"d": d, "m": d}
+        for chains, steps in ((1, 1000), (10, 100)):
+            pr = synth.paper_highdim(d=d, n_chains=chains, n_steps=steps)
+            s = E.Sampler(pr.A, pr.b, pr.x0, chains, seed=0, precision=32)
+            s.run(steps, keep_trace=False, count_rejections=False)      # capture
+            s.set_state(torch.as_tensor(np.broadcast_to(pr.x0, (chains, d)).copy()), 0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, nrej = s.run(steps, keep_trace=False)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            s.close()
+            row[f"{chains}x{steps}_ms"] = dt * 1e3
+            row[f"{chains}x{steps}_rejections"] = int(nrej)
+        out.append(row)
+    return {"workload": "Section 4.2 instances, float32, 1000 samples per run", "rows": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -165,6 +193,8 @@ def main():
                     help="run only the warm-start comparison and print its JSON")
     ap.add_argument("--warm-steps", type=int, default=48000,
                     help="steps per arm of the warm-start comparison")
+    ap.add_argument("--paper-timing-only", action="store_true",
+                    help="run only Section 4.2's timing protocol and print its JSON")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain elementwise copy of 256 MiB (reference for "
                          "hardware byte counters)")
@@ -193,6 +223,9 @@ def main():
         del src, dst
     if args.batched_only:
         print(json.dumps({"batched": bench_batched(E, torch, steps=args.steps)}), flush=True)
+        return
+    if args.paper_timing_only:
+        print(json.dumps({"paper_timing": bench_paper_timing(E, torch)}), flush=True)
         return
     if args.warm_only:
         log = lambda msg: print(msg, file=sys.stderr, flush=True)
@@ -261,6 +294,7 @@ def main():
         log = lambda msg: print(msg, file=sys.stderr, flush=True)
         out["batched"] = bench_batched(E, torch)
         out["warm_start"] = bench_warm_start(E, torch, log, args.warm_steps)
+        out["paper_timing"] = bench_paper_timing(E, torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pr, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -146,11 +146,14 @@ __device__ __forceinline__ ChainRef<float> batch_ref(const BatchArgs& a, const P
     return r;
 }
 
+// rows of 40 floats (conflict-free fragment reads, as in the single-problem
+// kernel); the largest shape takes 40 KB, so four workgroups share a CU
+constexpr int kBatchPadK = 8;
 union BatchGemmLds {
-    GemmLds<64, 64> s0;
-    GemmLds<32, 64> s1;
-    GemmLds<64, 32> s2;
-    GemmLds<32, 32> s3;
+    GemmLds<64, 64, kBatchPadK> s0;
+    GemmLds<32, 64, kBatchPadK> s1;
+    GemmLds<64, 32, kBatchPadK> s2;
+    GemmLds<32, 32, kBatchPadK> s3;
 };
 
 // Tile (tm, tn) of problem pd in its own shape (skipped when outside the
@@ -167,10 +170,10 @@ __device__ __forceinline__ void batch_tile(const BatchArgs& a, const ProbDesc& p
     const float* B1 = a.N + pd.x_off;
     const int m0 = tm * bm;
     switch (pd.shape) {
-        case 0: gemm_tile_f32<64, 64>(A, B0, B1, pd.dp, m0, n0, o, L.s0); break;
-        case 1: gemm_tile_f32<32, 64>(A, B0, B1, pd.dp, m0, n0, o, L.s1); break;
-        case 2: gemm_tile_f32<64, 32>(A, B0, B1, pd.dp, m0, n0, o, L.s2); break;
-        default: gemm_tile_f32<32, 32>(A, B0, B1, pd.dp, m0, n0, o, L.s3); break;
+        case 0: gemm_tile_f32<64, 64, 2, 2, kBatchPadK>(A, B0, B1, pd.dp, m0, n0, o, L.s0); break;
+        case 1: gemm_tile_f32<32, 64, 2, 2, kBatchPadK>(A, B0, B1, pd.dp, m0, n0, o, L.s1); break;
+        case 2: gemm_tile_f32<64, 32, 2, 2, kBatchPadK>(A, B0, B1, pd.dp, m0, n0, o, L.s2); break;
+        default: gemm_tile_f32<32, 32, 2, 2, kBatchPadK>(A, B0, B1, pd.dp, m0, n0, o, L.s3); break;
     }
 }
 
