@@ -261,10 +261,38 @@ void launch_f32(const ess_ctx* c, const Group& g, hipStream_t st, const float* B
 
 // Projections of group g's columns selected by `cols`: rows of Y (x or x')
 // and/or the current nu rows.
+template <typename T, int CM>
+void launch_gemv(const ess_ctx* c, hipStream_t st, const T* B0, const T* B1, int cols,
+                 const ProjOut& o) {
+    const int waves = (c->m + 3) / 4;
+    hipLaunchKernelGGL((proj_gemv<T, CM>), dim3((waves + 3) / 4), dim3(256), 0, st,
+                       static_cast<const T*>(c->A), B0, B1, c->dp, cols, o);
+}
+
+// Groups of at most kGemvChains chains take the row-parallel kernel.
+constexpr int kGemvChains = 12;
+
 ess_status launch_proj(const ess_ctx* c, const Group& g, hipStream_t st, const void* Y, int cols,
                        int p_direct, int strict) {
     const ProjOut o = proj_out(c, g, p_direct, strict);
     const size_t off = static_cast<size_t>(g.c0) * c->dp;
+    if (g.n <= kGemvChains) {
+        if (c->prec == 32) {
+            const float* B0 = static_cast<const float*>(Y) + off;
+            const float* B1 = static_cast<const float*>(c->N) + off;
+            if (g.n <= 2) launch_gemv<float, 2>(c, st, B0, B1, cols, o);
+            else if (g.n <= 4) launch_gemv<float, 4>(c, st, B0, B1, cols, o);
+            else launch_gemv<float, kGemvChains>(c, st, B0, B1, cols, o);
+        } else {
+            const double* B0 = static_cast<const double*>(Y) + off;
+            const double* B1 = static_cast<const double*>(c->N) + off;
+            if (g.n <= 2) launch_gemv<double, 2>(c, st, B0, B1, cols, o);
+            else if (g.n <= 4) launch_gemv<double, 4>(c, st, B0, B1, cols, o);
+            else launch_gemv<double, kGemvChains>(c, st, B0, B1, cols, o);
+        }
+        HIP_TRY(hipGetLastError());
+        return ESS_OK;
+    }
     if (c->prec == 32) {
         const float* B0 = static_cast<const float*>(Y) + off;
         if (c->bm == 128 && c->bn == 128) launch_f32<128, 128, 4, 2>(c, g, st, B0, cols, o);
