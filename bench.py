@@ -195,10 +195,13 @@ def main():
                     help="steps per arm of the warm-start comparison")
     ap.add_argument("--paper-timing-only", action="store_true",
                     help="run only Section 4.2's timing protocol and print its JSON")
+    ap.add_argument("--paper-dims", default="100,250,500,1000,2000,4000",
+                    help="comma-separated d values of the Section 4.2 timing protocol")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain elementwise copy of 256 MiB (reference for "
                          "hardware byte counters)")
     args = ap.parse_args()
+    paper_dims = tuple(int(v) for v in args.paper_dims.split(",") if v)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: chains shard across GPUs with no per-step traffic, "
@@ -225,7 +228,7 @@ def main():
         print(json.dumps({"batched": bench_batched(E, torch, steps=args.steps)}), flush=True)
         return
     if args.paper_timing_only:
-        print(json.dumps({"paper_timing": bench_paper_timing(E, torch)}), flush=True)
+        print(json.dumps({"paper_timing": bench_paper_timing(E, torch, paper_dims)}), flush=True)
         return
     if args.warm_only:
         log = lambda msg: print(msg, file=sys.stderr, flush=True)
@@ -294,7 +297,7 @@ def main():
         log = lambda msg: print(msg, file=sys.stderr, flush=True)
         out["batched"] = bench_batched(E, torch)
         out["warm_start"] = bench_warm_start(E, torch, log, args.warm_steps)
-        out["paper_timing"] = bench_paper_timing(E, torch)
+        out["paper_timing"] = bench_paper_timing(E, torch, paper_dims)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pr, args.cpu_seconds)
     print(json.dumps(out), flush=True)

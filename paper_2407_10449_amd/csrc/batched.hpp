@@ -249,16 +249,20 @@ __global__ __launch_bounds__(256, RPT <= 8 ? 6 : 1) void batched_chain_kernel(Ba
     }
 }
 
-// Chains the batched step handed over, sorted in full.
+// Chains the batched step handed over: the bucket path with refinement of
+// crowded buckets, else the full sort.
 template <int NMAX>
 __global__ __launch_bounds__(256) void batched_fallback_kernel(BatchArgs a) {
     ESS_FULL_LDS(NMAX)
+    __shared__ BucketLds<2048> blds;
     const int par = static_cast<int>(abs_step(a) & 1u);
     const int count = a.fb_count[par];
     for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
         const int2 ch = a.fb_list[idx];
         const ChainRef<float> r = batch_ref(a, a.descs[ch.x], ch.x, ch.y);
-        full_chain<float>(r, *r.sel, full_lds);
+        const int sel = *r.sel;
+        if (!bucket_chain<float, NMAX / 256, 2048, 256, true>(r, sel, blds))
+            full_chain<float>(r, sel, full_lds);
         __syncthreads();
     }
 }

@@ -25,6 +25,7 @@
 
 #include "ess.h"
 #include "gemm.hpp"
+#include "gemv.hpp"
 #include "philox.hpp"
 #include "sample.hpp"
 #include "batched.hpp"
@@ -260,12 +261,11 @@ void launch_f32(const ess_ctx* c, const Group& g, hipStream_t st, const float* B
 }
 
 // Projections of group g's columns selected by `cols`: rows of Y (x or x')
-// and/or the current nu rows.
-template <typename T, int CM>
+// and/or the current nu rows.  One workgroup per four rows.
+template <typename T, int CW, int NG>
 void launch_gemv(const ess_ctx* c, hipStream_t st, const T* B0, const T* B1, int cols,
                  const ProjOut& o) {
-    const int waves = (c->m + 3) / 4;
-    hipLaunchKernelGGL((proj_gemv<T, CM>), dim3((waves + 3) / 4), dim3(256), 0, st,
+    hipLaunchKernelGGL((proj_gemv<T, CW, NG>), dim3((c->m + 3) / 4), dim3(256), 0, st,
                        static_cast<const T*>(c->A), B0, B1, c->dp, cols, o);
 }
 
@@ -280,15 +280,15 @@ ess_status launch_proj(const ess_ctx* c, const Group& g, hipStream_t st, const v
         if (c->prec == 32) {
             const float* B0 = static_cast<const float*>(Y) + off;
             const float* B1 = static_cast<const float*>(c->N) + off;
-            if (g.n <= 2) launch_gemv<float, 2>(c, st, B0, B1, cols, o);
-            else if (g.n <= 4) launch_gemv<float, 4>(c, st, B0, B1, cols, o);
-            else launch_gemv<float, kGemvChains>(c, st, B0, B1, cols, o);
+            if (g.n <= 2) launch_gemv<float, 2, 1>(c, st, B0, B1, cols, o);
+            else if (g.n <= 4) launch_gemv<float, 4, 1>(c, st, B0, B1, cols, o);
+            else launch_gemv<float, kGemvChains / 2, 2>(c, st, B0, B1, cols, o);
         } else {
             const double* B0 = static_cast<const double*>(Y) + off;
             const double* B1 = static_cast<const double*>(c->N) + off;
-            if (g.n <= 2) launch_gemv<double, 2>(c, st, B0, B1, cols, o);
-            else if (g.n <= 4) launch_gemv<double, 4>(c, st, B0, B1, cols, o);
-            else launch_gemv<double, kGemvChains>(c, st, B0, B1, cols, o);
+            if (g.n <= 2) launch_gemv<double, 2, 1>(c, st, B0, B1, cols, o);
+            else if (g.n <= 4) launch_gemv<double, 4, 1>(c, st, B0, B1, cols, o);
+            else launch_gemv<double, kGemvChains / 2, 2>(c, st, B0, B1, cols, o);
         }
         HIP_TRY(hipGetLastError());
         return ESS_OK;
@@ -350,11 +350,28 @@ void launch_sample_t(const ess_ctx* c, const Group& g, hipStream_t st, const Sam
     const int rpt = (c->m + 255) / 256;
     // more than 1024 rows: 512 threads per chain (measured 12 % faster at
     // m = 2000: the latency-bound phases have half the rows per thread)
-    if (rpt <= 1) hipLaunchKernelGGL((sample_bucket_kernel<T, 1, 256>), grid, b, 0, st, a);
-    else if (rpt <= 2) hipLaunchKernelGGL((sample_bucket_kernel<T, 2, 2048>), grid, b, 0, st, a);
-    else if (rpt <= 4) hipLaunchKernelGGL((sample_bucket_kernel<T, 4, 2048>), grid, b, 0, st, a);
-    else if (rpt <= 8) hipLaunchKernelGGL((sample_bucket_kernel<T, 4, 2048, 512>), grid, b2, 0, st, a);
-    else hipLaunchKernelGGL((sample_bucket_kernel<T, 8, 2048, 512>), grid, b2, 0, st, a);
+    // With no more chains than compute units, occupancy does not matter and
+    // the kernel carries the bucket refinement itself, so a chain with crowded
+    // buckets is resolved in place instead of by the second kernel.
+    // Few chains also take 512 threads at every m: the phases are latency-bound
+    // and halving the rows per thread shortens them (one chain at m = 1000:
+    // 22 -> 16 us).
+    if (g.n <= 256) {
+        if (rpt <= 2) hipLaunchKernelGGL((sample_bucket_kernel<T, 1, 2048, 512, true>), grid, b2, 0, st, a);
+        else if (rpt <= 4) hipLaunchKernelGGL((sample_bucket_kernel<T, 2, 2048, 512, true>), grid, b2, 0, st, a);
+        else if (rpt <= 8) hipLaunchKernelGGL((sample_bucket_kernel<T, 4, 2048, 512, true>), grid, b2, 0, st, a);
+        else hipLaunchKernelGGL((sample_bucket_kernel<T, 8, 2048, 512, true>), grid, b2, 0, st, a);
+    } else if (rpt <= 1) {
+        hipLaunchKernelGGL((sample_bucket_kernel<T, 1, 256>), grid, b, 0, st, a);
+    } else if (rpt <= 2) {
+        hipLaunchKernelGGL((sample_bucket_kernel<T, 2, 2048>), grid, b, 0, st, a);
+    } else if (rpt <= 4) {
+        hipLaunchKernelGGL((sample_bucket_kernel<T, 4, 2048>), grid, b, 0, st, a);
+    } else if (rpt <= 8) {
+        hipLaunchKernelGGL((sample_bucket_kernel<T, 4, 2048, 512>), grid, b2, 0, st, a);
+    } else {
+        hipLaunchKernelGGL((sample_bucket_kernel<T, 8, 2048, 512>), grid, b2, 0, st, a);
+    }
     // the full-sort pass is usually empty: a small grid keeps its launch cheap,
     // unless every chain takes it (ESS_SORT_FULL)
     const dim3 fg(a.force_full ? std::min(g.n, 768) : std::min(g.n, 32));

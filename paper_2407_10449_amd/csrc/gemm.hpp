@@ -242,81 +242,6 @@ __global__ __launch_bounds__(64 * NW_M * NW_N) void proj_gemm_f32(const float* _
     gemm_tile_f32<BM, BN, NW_M, NW_N, 8>(A, B0, B1, K, tm * BM, tn * BN, o, lds);
 }
 
-// Projections of a few chains (at most CM in the group).  The tile GEMM pads
-// the chain axis to whole tiles, so with one or ten chains nearly all of its
-// matrix work is padding and its time is the latency of a long K loop.  Here
-// each wave takes four rows of A; its lanes stride along K four elements at a
-// time and keep the 4 x 2 CM partial sums (x' and nu of every chain) in
-// registers; a butterfly over the wave finishes them in a fixed order.  A is
-// streamed once per launch, the chain rows come from the caches.  Rows are
-// padded to mp (a multiple of 128) and K to a multiple of 32, so every read
-// stays inside the buffers.
-template <typename T, int CM>
-__global__ __launch_bounds__(256) void proj_gemv(const T* __restrict__ A,
-                                                 const T* __restrict__ B0,
-                                                 const T* __restrict__ B1, int K, int cols,
-                                                 ProjOut o) {
-    constexpr int R = 4;
-    const int lane = threadIdx.x & 63;
-    const int i0 = (blockIdx.x * 4 + static_cast<int>(threadIdx.x >> 6)) * R;
-    if (i0 >= o.m) return;   // whole waves leave together
-    const int nch = min(o.C - o.c0, o.Cg);
-    const bool do_x = cols != 1, do_n = cols != 0;   // 0: x' only, 1: nu only, 2: both
-    T ax[R][CM], an[R][CM];
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-#pragma unroll
-        for (int c = 0; c < CM; ++c) {
-            ax[r][c] = T(0);
-            an[r][c] = T(0);
-        }
-#pragma unroll 2
-    for (int k = 4 * lane; k < K; k += 256) {
-        T a[R][4];
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) a[r][e] = A[static_cast<size_t>(i0 + r) * K + k + e];
-#pragma unroll
-        for (int c = 0; c < CM; ++c) {
-            if (c < nch) {
-                T xv[4], nv[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    xv[e] = do_x ? B0[static_cast<size_t>(c) * K + k + e] : T(0);
-                    nv[e] = do_n ? B1[static_cast<size_t>(c) * K + k + e] : T(0);
-                }
-#pragma unroll
-                for (int r = 0; r < R; ++r)
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        ax[r][c] += a[r][e] * xv[e];
-                        an[r][c] += a[r][e] * nv[e];
-                    }
-            }
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-#pragma unroll
-        for (int c = 0; c < CM; ++c)
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                ax[r][c] += __shfl_xor(ax[r][c], off, 64);
-                an[r][c] += __shfl_xor(an[r][c], off, 64);
-            }
-    // lane 2 c stores chain c's rows i0 .. i0 + 3 of A x', lane 2 c + 1 of A nu
-#pragma unroll
-    for (int c = 0; c < CM; ++c) {
-        if (c < nch) {
-            if (do_x && lane == 2 * c)
-                proj_store4<T>(o, c, i0, ax[0][c], ax[1][c], ax[2][c], ax[3][c]);
-            if (do_n && lane == 2 * c + 1)
-                proj_store4<T>(o, o.Cg + c, i0, an[0][c], an[1][c], an[2][c], an[3][c]);
-        }
-    }
-}
-
 // float64 projections on the vector ALUs (MI355X runs float64 FMA on the
 // vector units at the same rate as its float64 matrix cores).  64 x 64 tile,
 // each thread a 4 x 4 block: rows 4 ty .. 4 ty + 3, columns tx + 16 u.

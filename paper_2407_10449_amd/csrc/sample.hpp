@@ -540,19 +540,7 @@ __device__ void full_chain(const ChainRef<T>& r, int sel, const FullLds& L) {
     __shared__ double s_theta[2];                           \
     const FullLds full_lds{s_alpha, s_beta, s_key, s_red, s_cnt, s_bcast, &s_kstar, s_theta};
 
-// Chains the bucket path handed over (a.fb_list[0 .. fb_count[step & 1])),
-// processed by a grid-stride loop.  The bucket kernel of the next step clears
-// this count; the host clears both counts when a call starts.
-template <typename T, int NMAX>
-__global__ __launch_bounds__(256) void fallback_kernel(SampleArgs a) {
-    ESS_FULL_LDS(NMAX)
-    const int count = a.fb_count[abs_step(a) & 1];
-    for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
-        const ChainRef<T> r = make_ref<T>(a, a.fb_list[idx]);
-        full_chain<T>(r, *r.sel, full_lds);
-        __syncthreads();
-    }
-}
+
 
 __global__ void zero_ints(int* p, int n) {
     if (static_cast<int>(threadIdx.x) < n) p[threadIdx.x] = 0;
@@ -575,16 +563,128 @@ struct BucketLds {
     double red[8];
     double gtot, total, u;
     int scount, kstar, klast;
+    int smin, smax;                    // bucket range of the survivors (refinement)
     double theta;
 };
 
-// Returns false when the chain has more than SMAX survivors: nothing has been
+// Levels of bucket refinement before a chain goes to the full path, and the
+// survivor count below which refinement stops.
+constexpr int kRefineLevels = 3;
+constexpr int kRefineTarget = 16;
+
+// Refinement levels in use (block-uniform, kept in scalar registers).  Level
+// l keeps the rows of buckets [lo[l], hi[l]] and maps them to the bucket
+// coordinate (alpha NB / 2 pi - off[l]) sc[l], clamped to the f[l]
+// sub-buckets of the row's bucket one level up, so rounding of the composed
+// map cannot reorder buckets.
+struct RefineMap {
+    int n;
+    int lo[kRefineLevels], hi[kRefineLevels], f[kRefineLevels];
+    double off[kRefineLevels], sc[kRefineLevels];
+};
+
+__device__ __forceinline__ double uniform_double(double v) {
+    const unsigned long long u = static_cast<unsigned long long>(__double_as_longlong(v));
+    const unsigned lo = static_cast<unsigned>(__builtin_amdgcn_readfirstlane(static_cast<int>(u)));
+    const unsigned hi = static_cast<unsigned>(__builtin_amdgcn_readfirstlane(static_cast<int>(u >> 32)));
+    return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+
+// Bucket of alpha at the current refinement level, -1 once the row has left
+// the search.  Recomputed from alpha wherever it is needed, so no per-row
+// bucket stays in registers.
+template <int NB>
+__device__ __forceinline__ int bucket_of(const RefineMap& R, double a) {
+    constexpr double kBucket = NB / kTwoPi;
+    int b = min(static_cast<int>(a * kBucket), NB - 1);
+#pragma unroll
+    for (int l = 0; l < kRefineLevels; ++l) {
+        if (l >= R.n) break;
+        if (b < R.lo[l] || b > R.hi[l]) return -1;
+        const int first = (b - R.lo[l]) * R.f[l];
+        const double t = (a * kBucket - R.off[l]) * R.sc[l];
+        b = min(max(static_cast<int>(t), first), first + R.f[l] - 1);
+    }
+    return b;
+}
+
+// G[b] = max beta of the rows in bucket b (G cleared before).
+template <int RPT, int NB>
+__device__ __forceinline__ void bucket_max_pass(BucketLds<NB>& L, const RefineMap& R,
+                                                const double (&al)[RPT], const double (&be)[RPT]) {
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        if (be[j] > 0.0) {
+            const int b = bucket_of<NB>(R, al[j]);
+            if (b >= 0) atomicMax(&L.G[b], obits(be[j]));
+        }
+    }
+    __syncthreads();
+}
+
+// Exclusive prefix max over buckets, in place: G[b] = max(g0, max beta of
+// rows in buckets < b); thread t owns buckets [t NB/BS, (t+1) NB/BS).  With
+// `top`, gamma_n (max beta over all rows) goes to gtot.
+template <int NB, int BS>
+__device__ __forceinline__ void bucket_prefix_max(BucketLds<NB>& L, double g0, bool top) {
+    constexpr int BPT = NB / BS;
+    static_assert(BPT >= 1, "at least one bucket per thread");
+    const int tid = threadIdx.x;
+    double tmax = 0.0;
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) tmax = fmax(tmax, ofloat(L.G[tid * BPT + j]));
+    const double g_in = block_excl_scan<MaxOp, BS / 64>(tmax, 0.0, MaxOp(), L.red);
+    double run = fmax(g0, g_in);
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+        const double v = ofloat(L.G[tid * BPT + j]);
+        L.G[tid * BPT + j] = obits(run);
+        run = fmax(run, v);
+    }
+    if (top && tid == BS - 1) L.gtot = run;
+    __syncthreads();
+}
+
+// Survivors: rows whose candidate can be non-empty (alpha >= G of their
+// bucket); the first SMAX are listed.  Returns their number.
+template <int RPT, int NB, int BS>
+__device__ __forceinline__ int find_survivors(BucketLds<NB>& L, const RefineMap& R,
+                                              const double (&al)[RPT], const double (&be)[RPT]) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        if (be[j] > 0.0) {
+            const int b = bucket_of<NB>(R, al[j]);
+            if (b >= 0 && al[j] >= ofloat(L.G[b])) {
+                const int k = atomicAdd(&L.scount, 1);
+                if (k < SMAX) {
+                    L.sa[k] = al[j];
+                    L.si[k] = tid + BS * j;
+                    L.sk[k] = b;
+                    L.sm[k] = 0ull;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    return L.scount;
+}
+
+// When more than SMAX rows survive, the survivors' buckets [blo, bhi] are
+// split again: every row whose bucket lies in that range moves to one of
+// floor(NB / (bhi - blo + 1)) sub-buckets of its bucket (an affine map of its
+// bucket coordinate, so the order of alpha is kept), every other row leaves
+// the search (its candidate is empty already), and the max-scan restarts from
+// G[blo].  Angles that crowd a few buckets (as on unnormalised instances whose
+// state sits close to many constraints, where alpha piles up just above 0)
+// then spread over all NB buckets again.  Returns false when the survivors
+// still exceed SMAX once refinement stops (kRefineLevels levels, a level that
+// did not halve them, or a range that cannot be split): nothing has been
 // moved and the caller hands the chain to the full path.
-template <typename T, int RPT, int NB, int BS = 256>
+template <typename T, int RPT, int NB, int BS = 256, bool REFINE = false>
 __device__ bool bucket_chain(const ChainRef<T>& r, int sel, BucketLds<NB>& L) {
     static_assert(BS == 256 || BS == 512, "one chain per 256 or 512 threads");
     const int tid = threadIdx.x;
-    constexpr double kBucket = NB / kTwoPi;
     for (int b = tid; b < NB; b += BS) {
         L.G[b] = 0ull;
         L.head[b] = -1;
@@ -594,20 +694,17 @@ __device__ bool bucket_chain(const ChainRef<T>& r, int sel, BucketLds<NB>& L) {
     // roots of this thread's rows (row i = tid + BS r); beta = 0 marks no crossing
     const T* Pc = r.P0 + static_cast<size_t>(sel) * r.pstride;
     double al[RPT], be[RPT];
-    int bk[RPT];
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
         const int i = tid + BS * j;
         al[j] = 0.0;
         be[j] = 0.0;
-        bk[j] = 0;
         if (i < r.m) {
             const T p = Pc[i], q = r.q[i];
             double x0, x1;
             if (solve_roots<T>(static_cast<double>(p), static_cast<double>(q), r.b[i], x0, x1)) {
                 al[j] = x0;
                 be[j] = x1;
-                bk[j] = min(static_cast<int>(x0 * kBucket), NB - 1);
             }
             if (r.p_out) {
                 r.p_out[i] = p;
@@ -616,47 +713,81 @@ __device__ bool bucket_chain(const ChainRef<T>& r, int sel, BucketLds<NB>& L) {
         }
     }
     __syncthreads();
-#pragma unroll
-    for (int j = 0; j < RPT; ++j)
-        if (be[j] > 0.0) atomicMax(&L.G[bk[j]], obits(be[j]));
-    __syncthreads();
+    RefineMap R;
+    R.n = 0;
+    bucket_max_pass<RPT, NB>(L, R, al, be);
+    bucket_prefix_max<NB, BS>(L, 0.0, true);
+    int S = find_survivors<RPT, NB, BS>(L, R, al, be);
 
-    // exclusive prefix max over buckets, in place: G[b] = max beta of rows in
-    // buckets < b (0 if none); thread t owns buckets [t NB/BS, (t+1) NB/BS)
-    constexpr int BPT = NB / BS;
-    static_assert(BPT >= 1, "at least one bucket per thread");
-    double tmax = 0.0;
-#pragma unroll
-    for (int j = 0; j < BPT; ++j) tmax = fmax(tmax, ofloat(L.G[tid * BPT + j]));
-    const double g_in = block_excl_scan<MaxOp, BS / 64>(tmax, 0.0, MaxOp(), L.red);
-    {
-        double run = g_in;
-#pragma unroll
-        for (int j = 0; j < BPT; ++j) {
-            const double v = ofloat(L.G[tid * BPT + j]);
-            L.G[tid * BPT + j] = obits(run);
-            run = fmax(run, v);
+    // refinement (rare on well-scaled problems, so only the variants for few
+    // chains and the second attempt on a chain carry its code and registers).
+    // Beyond overflow it also pays when survivors crowd a few buckets: every
+    // row then meets all survivors of its bucket in the predecessor pass.
+    // Below overflow it stops once a level no longer halves the survivors.
+    if (!REFINE && S > SMAX) return false;
+    int s_prev = 1 << 30;
+    while (REFINE && S > kRefineTarget) {
+        if (R.n == kRefineLevels || (S <= SMAX && 2 * S > s_prev)) {
+            if (S > SMAX) return false;
+            break;
         }
-        if (tid == BS - 1) L.gtot = run;   // gamma_n: max beta over all rows
-    }
-    __syncthreads();
-
-    // survivors: rows whose candidate can be non-empty
+        s_prev = S;
+        if (tid == 0) {
+            L.smin = NB;
+            L.smax = -1;
+        }
+        __syncthreads();
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-        if (be[j] > 0.0 && al[j] >= ofloat(L.G[bk[j]])) {
-            const int k = atomicAdd(&L.scount, 1);
-            if (k < SMAX) {
-                L.sa[k] = al[j];
-                L.si[k] = tid + BS * j;
-                L.sk[k] = bk[j];
-                L.sm[k] = 0ull;
+        for (int j = 0; j < RPT; ++j) {
+            if (be[j] > 0.0) {
+                const int b = bucket_of<NB>(R, al[j]);
+                if (b >= 0 && al[j] >= ofloat(L.G[b])) {
+                    atomicMin(&L.smin, b);
+                    atomicMax(&L.smax, b);
+                }
             }
         }
+        __syncthreads();
+        const int blo = __builtin_amdgcn_readfirstlane(L.smin);
+        const int bhi = __builtin_amdgcn_readfirstlane(L.smax);
+        const int f = NB / (bhi - blo + 1);
+        if (f < 2) {
+            if (S > SMAX) return false;
+            break;
+        }
+        const double g0 = ofloat(L.G[blo]);
+        double off = 0.0, sc = 1.0;   // the map one level up
+#pragma unroll
+        for (int l = 0; l < kRefineLevels; ++l) {
+            if (l + 1 == R.n) {
+                off = R.off[l];
+                sc = R.sc[l];
+            }
+        }
+        off = uniform_double(off + blo / sc);
+        sc = uniform_double(sc * f);
+#pragma unroll
+        for (int l = 0; l < kRefineLevels; ++l) {
+            if (l == R.n) {
+                R.lo[l] = blo;
+                R.hi[l] = bhi;
+                R.f[l] = f;
+                R.off[l] = off;
+                R.sc[l] = sc;
+            }
+        }
+        ++R.n;
+        __syncthreads();   // every read of G and of the range precedes the reset
+        for (int b = tid; b < NB; b += BS) {
+            L.G[b] = 0ull;
+            L.head[b] = -1;
+        }
+        if (tid == 0) L.scount = 0;
+        __syncthreads();
+        bucket_max_pass<RPT, NB>(L, R, al, be);
+        bucket_prefix_max<NB, BS>(L, g0, false);
+        S = find_survivors<RPT, NB, BS>(L, R, al, be);
     }
-    __syncthreads();
-    const int S = L.scount;
-    if (S > SMAX) return false;
 
     // survivors chained per bucket, so a row meets only its own bucket's
     // survivors (a row-by-survivor scan cost tens of microseconds per chain):
@@ -682,9 +813,10 @@ __device__ bool bucket_chain(const ChainRef<T>& r, int sel, BucketLds<NB>& L) {
     // exact predecessor max inside each survivor's bucket (ties by row index)
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
-        if (be[j] > 0.0) {
+        const int b = be[j] > 0.0 ? bucket_of<NB>(R, al[j]) : -1;
+        if (b >= 0) {
             const int i = tid + BS * j;
-            for (int s = L.head[bk[j]]; s >= 0; s = L.nxt[s]) {
+            for (int s = L.head[b]; s >= 0; s = L.nxt[s]) {
                 if (al[j] < L.sa[s] || (al[j] == L.sa[s] && i < L.si[s]))
                     atomicMax(&L.sm[s], obits(be[j]));
             }
@@ -813,16 +945,35 @@ __device__ bool bucket_chain(const ChainRef<T>& r, int sel, BucketLds<NB>& L) {
     return true;
 }
 
-template <typename T, int RPT, int NB, int BS = 256>
-__global__ __launch_bounds__(BS, (BS == 512 && RPT <= 4) ? 8 : 1) void sample_bucket_kernel(SampleArgs a) {
+template <typename T, int RPT, int NB, int BS = 256, bool REFINE = false>
+__global__ __launch_bounds__(BS, (BS == 512 && RPT <= 4 && !REFINE) ? 8 : 1) void sample_bucket_kernel(SampleArgs a) {
     __shared__ BucketLds<NB> lds;
     const int c = a.c0 + blockIdx.x;
     const ChainRef<T> r = make_ref<T>(a, c);
     const int sel = a.has_pending ? commit_chain<T>(r) : *r.sel;
     const uint32_t step = r.step;
     if (blockIdx.x == 0 && threadIdx.x == 0) a.fb_count[(step + 1) & 1] = 0;   // next step's list
-    const bool done = !a.force_full && bucket_chain<T, RPT, NB, BS>(r, sel, lds);
+    const bool done = !a.force_full && bucket_chain<T, RPT, NB, BS, REFINE>(r, sel, lds);
     if (!done && threadIdx.x == 0) a.fb_list[atomicAdd(a.fb_count + (step & 1), 1)] = c;
+}
+
+// Chains the bucket kernel handed over (a.fb_list[0 .. fb_count[step & 1])),
+// processed by a grid-stride loop: first the bucket path with refinement of
+// crowded buckets, then, if that still leaves too many survivors (or the full
+// path is requested), the full sort.  The bucket kernel of the next step
+// clears this count; the host clears both counts when a call starts.
+template <typename T, int NMAX>
+__global__ __launch_bounds__(256) void fallback_kernel(SampleArgs a) {
+    ESS_FULL_LDS(NMAX)
+    __shared__ BucketLds<2048> blds;
+    const int count = a.fb_count[abs_step(a) & 1];
+    for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
+        const ChainRef<T> r = make_ref<T>(a, a.fb_list[idx]);
+        const int sel = *r.sel;
+        if (a.force_full || !bucket_chain<T, NMAX / 256, 2048, 256, true>(r, sel, blds))
+            full_chain<T>(r, sel, full_lds);
+        __syncthreads();
+    }
 }
 
 }  // namespace ess

@@ -59,6 +59,12 @@ CASES = [
     ("univariate_f32", 1, 2, 64, 32, 0.0),
     ("one_chain_f32", 50, 100, 1, 32, 1e-6),
     ("max_m_f32", 64, 4096, 64, 32, 1e-6),
+    # more than 256 chains take the kernels tuned for occupancy; 256 or fewer
+    # take the 512-thread kernels with bucket refinement
+    ("many_m500_f64", 30, 500, 300, 64, 0.0),
+    ("many_m1000_f32", 40, 1000, 300, 32, 1e-6),
+    ("many_m3000_f32", 40, 3000, 270, 32, 1e-6),
+    ("many_max_m_f64", 20, 4096, 260, 64, 0.0),
 ]
 
 
@@ -371,6 +377,75 @@ def test_appendix_d_nested_arcs_in_one_bucket(E, precision, m):
     assert (g["n_intervals"] == m + 1).all(), g["n_intervals"]
     fails, _ = compare_transition(Ab, b, x, nu, u, g, ref)
     assert not fails, fails[:5]
+
+
+def coarse_survivors(alpha, beta, nb=2048):
+    """Rows whose alpha reaches the running max of beta over all rows of
+    earlier buckets, with nb equal buckets of [0, 2 pi) (counted per chain)."""
+    out = []
+    for a, be in zip(alpha, beta):
+        hit = be > 0
+        a, be = a[hit], be[hit]
+        bk = np.minimum((a * nb / (2 * math.pi)).astype(int), nb - 1)
+        top = np.zeros(nb)
+        np.maximum.at(top, bk, be)
+        g = np.concatenate([[0.0], np.maximum.accumulate(top)[:-1]])
+        out.append(int((a >= g[bk]).sum()))
+    return out
+
+
+def assert_same_as_full_sort(E, A, b, x, nu, u, precision, eps):
+    outs = []
+    for full in (False, True):
+        s = E.Sampler(A, b, x, x.shape[0], seed=5, precision=precision, trim_eps=eps,
+                      full_sort=full)
+        outs.append({k: v.cpu().numpy() for k, v in s.transition_explicit(x, nu, u).items()})
+        s.close()
+    a, f = outs
+    assert np.array_equal(a["n_intervals"], f["n_intervals"])
+    assert np.abs(a["intervals"] - f["intervals"]).max() <= 1e-13
+    assert np.abs(a["theta"] - f["theta"]).max() <= 1e-12
+    assert np.array_equal(a["rejected"], f["rejected"])
+    return a
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_section_4_2_crowded_buckets_are_refined(E, precision):
+    """Section 4.2's unnormalised instance at d = m = 4000 from its start x0:
+    the state sits within [0, 1] of every constraint while |a_i| is about 63,
+    so the alphas crowd the first buckets and about 300 rows survive the
+    2048-bucket filter.  The chain leaves the fast kernel and the bucket path
+    with refined buckets must give what the oracle and the full sort give."""
+    pr = synth.paper_highdim(d=4000)
+    C = 3
+    npdt = np.float32 if precision == 32 else np.float64
+    rng = np.random.default_rng(42)
+    x = np.tile(pr.x0, (C, 1)).astype(npdt)
+    nu = rng.standard_normal(x.shape).astype(npdt)
+    u = rng.uniform(size=C)
+    Ab = pr.A.astype(npdt).astype(np.float64)
+    ref = ref_ess.transition(Ab, pr.b, x.astype(np.float64), nu.astype(np.float64), u,
+                             eps=1e-6, store=npdt)
+    surv = coarse_survivors(ref["alpha"], ref["beta"])
+    say("coarse survivors", surv)
+    assert min(surv) > 128
+    g = assert_same_as_full_sort(E, pr.A, pr.b, x, nu, u, precision, 1e-6)
+    fails, _ = compare_transition(Ab, pr.b, x.astype(np.float64), nu, u, g, ref)
+    assert not fails, fails[:5]
+
+
+def test_two_refinement_levels(E):
+    """600 rows whose alphas lie within 6e-7 rad (one bucket, and still one
+    sub-bucket after the first split) and whose arcs overlap: two levels of
+    refinement leave a single survivor.  Float64 resolves the spacing."""
+    n = 600
+    al = 1.0 + 1e-9 * np.arange(n)
+    Ab, b, x, nu, u, g, ref = run_arcs(E, al, al + 1.0, 64)
+    assert coarse_survivors(ref["alpha"], ref["beta"])[0] == n
+    assert (g["n_intervals"] == 2).all(), g["n_intervals"]
+    fails, _ = compare_transition(Ab, b, x, nu, u, g, ref)
+    assert not fails, fails[:5]
+    assert_same_as_full_sort(E, Ab, b, x, nu, u, 64, 0.0)
 
 
 @pytest.mark.parametrize("name,d,m,C,precision,eps", CASES[:4], ids=[c[0] for c in CASES[:4]])
