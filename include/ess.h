@@ -61,7 +61,10 @@ typedef enum {
  * zero-length single-root case of Figure 2(d). */
 typedef struct {
     int32_t d;            /* dimension, >= 1                                  */
-    int32_t m;            /* number of constraints, 1 .. 4096                 */
+    int32_t m;            /* number of constraints, 1 .. 16384 (1 .. 4096 in a
+                             batched context); above 4096 every pass over the
+                             rows is made in chunks of 4096 and the full sort
+                             keeps keys only                                  */
     int32_t n_chains;     /* independent chains, >= 1                         */
     int32_t precision;    /* 32: float storage and projections, float64 roots,
                              interval ends and sampling; 64: float64 throughout */

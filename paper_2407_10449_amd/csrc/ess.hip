@@ -348,6 +348,13 @@ template <typename T>
 void launch_sample_t(const ess_ctx* c, const Group& g, hipStream_t st, const SampleArgs& a) {
     const dim3 grid(g.n), b(256), b2(512);
     const int rpt = (c->m + 255) / 256;
+    const dim3 fg(a.force_full ? std::min(g.n, 768) : std::min(g.n, 32));
+    if (c->m > 4096) {
+        // rows in chunks of 4096 per pass; the full sort keeps keys only
+        hipLaunchKernelGGL((sample_large_kernel<T>), grid, b2, 0, st, a);
+        hipLaunchKernelGGL((fallback_large_kernel<T>), fg, b, 0, st, a);
+        return;
+    }
     // more than 1024 rows: 512 threads per chain (measured 12 % faster at
     // m = 2000: the latency-bound phases have half the rows per thread)
     // With no more chains than compute units, occupancy does not matter and
@@ -374,7 +381,6 @@ void launch_sample_t(const ess_ctx* c, const Group& g, hipStream_t st, const Sam
     }
     // the full-sort pass is usually empty: a small grid keeps its launch cheap,
     // unless every chain takes it (ESS_SORT_FULL)
-    const dim3 fg(a.force_full ? std::min(g.n, 768) : std::min(g.n, 32));
     switch (c->nmax) {
         case 512: hipLaunchKernelGGL((fallback_kernel<T, 512>), fg, b, 0, st, a); break;
         case 1024: hipLaunchKernelGGL((fallback_kernel<T, 1024>), fg, b, 0, st, a); break;
@@ -1284,7 +1290,9 @@ ess_status ess_init(const ess_problem* pr, void* stream, ess_ctx** out) {
         return fail(ESS_ERR_INVALID_ARG, "precision must be 32 or 64 (got %d)", pr->precision);
     if (!(pr->trim_eps >= 0.0) || pr->trim_eps > 1.0)
         return fail(ESS_ERR_INVALID_ARG, "trim_eps must lie in [0, 1] (got %g)", pr->trim_eps);
-    if (pr->m > 4096) return fail(ESS_ERR_UNSUPPORTED, "m = %d exceeds the 4096 rows one workgroup sorts", pr->m);
+    if (pr->m > kMaxRowsLarge)
+        return fail(ESS_ERR_UNSUPPORTED, "m = %d exceeds the %d rows one workgroup sorts", pr->m,
+                    kMaxRowsLarge);
     if (pr->d > (1 << 20) || pr->n_chains > (1 << 24))
         return fail(ESS_ERR_UNSUPPORTED, "d or n_chains too large");
 

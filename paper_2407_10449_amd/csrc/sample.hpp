@@ -368,7 +368,9 @@ struct FullLds {
     double* theta;    // [1]
 };
 
-template <typename T>
+// LARGE: only the keys live in LDS (room for 16384 rows).  They carry the row
+// index instead of a slot, and every sweep solves the row's roots again.
+template <typename T, bool LARGE = false>
 __device__ void full_chain(const ChainRef<T>& r, int sel, const FullLds& L) {
     const int tid = threadIdx.x;
     const T* Pc = r.P0 + static_cast<size_t>(sel) * r.pstride;
@@ -389,9 +391,13 @@ __device__ void full_chain(const ChainRef<T>& r, int sel, const FullLds& L) {
         const int pos = block_count_prefix(hit, L.cnt, tot);
         if (hit) {
             const int slot = n + pos;
-            L.alpha[slot] = al;
-            L.beta[slot] = be;
-            L.key[slot] = sort_key(al, slot);
+            if constexpr (LARGE) {
+                L.key[slot] = sort_key(al, i);
+            } else {
+                L.alpha[slot] = al;
+                L.beta[slot] = be;
+                L.key[slot] = sort_key(al, slot);
+            }
         }
         n += tot;
     }
@@ -406,16 +412,31 @@ __device__ void full_chain(const ChainRef<T>& r, int sel, const FullLds& L) {
     const int k0 = tid * per;
     const int k1 = min(k0 + per, n);
     const double eps = r.eps;
+    // alpha and beta of the k-th key in order
+    auto ab = [&](int k, double& a, double& bt) {
+        const int s = static_cast<int>(L.key[k] & 0xFFFF);
+        if constexpr (LARGE) {
+            solve_roots<T>(static_cast<double>(Pc[s]), static_cast<double>(r.q[s]), r.b[s], a, bt);
+        } else {
+            a = L.alpha[s];
+            bt = L.beta[s];
+        }
+    };
     double tmax = 0.0;
-    for (int k = k0; k < k1; ++k) tmax = fmax(tmax, L.beta[L.key[k] & 0xFFFF]);
+    for (int k = k0; k < k1; ++k) {
+        double a, bt;
+        ab(k, a, bt);
+        tmax = fmax(tmax, bt);
+    }
     const double g_in = block_excl_scan(tmax, 0.0, MaxOp(), L.red);
     const bool owns_last = (tid == 255);
 
     auto cand = [&](int k, double& g, double& lo, double& hi) {
-        const int slot = static_cast<int>(L.key[k] & 0xFFFF);
+        double a, bt;
+        ab(k, a, bt);
         lo = g;
-        hi = L.alpha[slot];
-        g = fmax(g, L.beta[slot]);
+        hi = a;
+        g = fmax(g, bt);
         if (lo > 0.0) lo += eps;
         if (hi < kTwoPi) hi -= eps;
     };
@@ -608,6 +629,32 @@ __device__ __forceinline__ int bucket_of(const RefineMap& R, double a) {
     return b;
 }
 
+// Roots of rows row0 + tid + BS j (j < RPT) of the chain; beta = 0 marks a
+// row past m or one the ellipse does not cross.  With `out`, the chain's p
+// and q of those rows go to the optional output.
+template <typename T, int RPT, int BS>
+__device__ __forceinline__ void block_roots(const ChainRef<T>& r, const T* Pc, int row0, bool out,
+                                            double (&al)[RPT], double (&be)[RPT]) {
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int i = row0 + static_cast<int>(threadIdx.x) + BS * j;
+        al[j] = 0.0;
+        be[j] = 0.0;
+        if (i < r.m) {
+            const T p = Pc[i], q = r.q[i];
+            double x0, x1;
+            if (solve_roots<T>(static_cast<double>(p), static_cast<double>(q), r.b[i], x0, x1)) {
+                al[j] = x0;
+                be[j] = x1;
+            }
+            if (out && r.p_out) {
+                r.p_out[i] = p;
+                r.q_out[i] = q;
+            }
+        }
+    }
+}
+
 // G[b] = max beta of the rows in bucket b (G cleared before).
 template <int RPT, int NB>
 __device__ __forceinline__ void bucket_max_pass(BucketLds<NB>& L, const RefineMap& R,
@@ -645,11 +692,13 @@ __device__ __forceinline__ void bucket_prefix_max(BucketLds<NB>& L, double g0, b
     __syncthreads();
 }
 
-// Survivors: rows whose candidate can be non-empty (alpha >= G of their
-// bucket); the first SMAX are listed.  Returns their number.
+// Survivors among rows row0 + tid + BS j: rows whose candidate can be
+// non-empty (alpha >= G of their bucket); the first SMAX of the chain are
+// listed.  Returns the chain's count so far.
 template <int RPT, int NB, int BS>
 __device__ __forceinline__ int find_survivors(BucketLds<NB>& L, const RefineMap& R,
-                                              const double (&al)[RPT], const double (&be)[RPT]) {
+                                              const double (&al)[RPT], const double (&be)[RPT],
+                                              int row0 = 0) {
     const int tid = threadIdx.x;
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
@@ -659,7 +708,7 @@ __device__ __forceinline__ int find_survivors(BucketLds<NB>& L, const RefineMap&
                 const int k = atomicAdd(&L.scount, 1);
                 if (k < SMAX) {
                     L.sa[k] = al[j];
-                    L.si[k] = tid + BS * j;
+                    L.si[k] = row0 + tid + BS * j;
                     L.sk[k] = b;
                     L.sm[k] = 0ull;
                 }
@@ -668,6 +717,176 @@ __device__ __forceinline__ int find_survivors(BucketLds<NB>& L, const RefineMap&
     }
     __syncthreads();
     return L.scount;
+}
+
+// Survivors chained per bucket, so a row meets only its own bucket's
+// survivors (a row-by-survivor scan cost tens of microseconds per chain):
+// survivor s links to the previous survivor of its bucket, and the last one
+// heads the bucket; meanwhile another wave draws this step's uniform.
+template <typename T, int NB>
+__device__ __forceinline__ void link_survivors(const ChainRef<T>& r, BucketLds<NB>& L, int S) {
+    const int tid = threadIdx.x;
+    static_assert(SMAX <= 128, "survivor links are bytes");
+    if (tid < S) {
+        const int b = L.sk[tid];
+        int prev = -1;
+        bool last = true;
+        for (int s = 0; s < S; ++s) {
+            if (L.sk[s] == b) {
+                if (s < tid) prev = s;
+                else if (s > tid) last = false;
+            }
+        }
+        L.nxt[tid] = static_cast<signed char>(prev);
+        if (last) L.head[b] = static_cast<signed char>(tid);
+    }
+    if (tid == 64) L.u = theta_uniform(r);
+    __syncthreads();
+}
+
+// Exact predecessor max inside each survivor's bucket (ties by row index),
+// for rows row0 + tid + BS j.  No barrier at the end.
+template <int RPT, int NB, int BS>
+__device__ __forceinline__ void pred_max_pass(BucketLds<NB>& L, const RefineMap& R,
+                                              const double (&al)[RPT], const double (&be)[RPT],
+                                              int row0) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int b = be[j] > 0.0 ? bucket_of<NB>(R, al[j]) : -1;
+        if (b >= 0) {
+            const int i = row0 + tid + BS * j;
+            for (int s = L.head[b]; s >= 0; s = L.nxt[s]) {
+                if (al[j] < L.sa[s] || (al[j] == L.sa[s] && i < L.si[s]))
+                    atomicMax(&L.sm[s], obits(be[j]));
+            }
+        }
+    }
+}
+
+// The survivors' candidates in ascending (alpha, row) order, theta by inverse
+// CDF, the optional interval output, and the move.
+template <typename T, int NB>
+__device__ __forceinline__ void finish_bucket(const ChainRef<T>& r, BucketLds<NB>& L, int S) {
+    const int tid = threadIdx.x;
+    // the survivors' candidates, placed in ascending (alpha, row) order
+    const double eps = r.eps;
+    if (tid < S) {
+        const double alpha = L.sa[tid];
+        const int row = L.si[tid];
+        int rank = 0;
+        for (int s = 0; s < S; ++s) {
+            const double o = L.sa[s];
+            rank += (o < alpha) || (o == alpha && L.si[s] < row);
+        }
+        double lo = fmax(ofloat(L.G[L.sk[tid]]), ofloat(L.sm[tid]));
+        double hi = alpha;
+        if (lo > 0.0) lo += eps;
+        if (hi < kTwoPi) hi -= eps;
+        L.lo[rank] = lo;
+        L.hi[rank] = hi;
+    }
+    if (tid == 0) {
+        const double g = L.gtot;
+        L.lo[S] = g > 0.0 ? g + eps : g;
+        L.hi[S] = kTwoPi;
+        L.kstar = 1 << 30;
+        L.klast = -1;
+    }
+    __syncthreads();
+
+    // inverse CDF over the S + 1 candidates in order: the running sums are a
+    // sequential left-to-right sum (those of a cumulative sum), and theta lies
+    // in the first non-empty candidate whose running sum exceeds s = u L.  Few
+    // candidates: one thread walks them.  Many: the lengths are formed in
+    // parallel, one thread keeps the running sums, and the search is
+    // parallel.  Both give the same theta bit for bit.
+    if (S < 16) {
+        if (tid == 0) {
+            double total = 0.0;
+            for (int k = 0; k <= S; ++k) total += fmax(L.hi[k] - L.lo[k], 0.0);
+            double theta = 0.0;
+            if (total > 0.0) {
+                const double sv = L.u * total;
+                double run = 0.0;
+                int last = -1;
+                bool found = false;
+                for (int k = 0; k <= S; ++k) {
+                    const double len = fmax(L.hi[k] - L.lo[k], 0.0);
+                    if (len > 0.0) {
+                        last = k;
+                        if (!found && run + len > sv) {
+                            theta = fmax(L.lo[k], fmin(L.lo[k] + (sv - run), L.hi[k]));
+                            found = true;
+                        }
+                    }
+                    run += len;
+                }
+                if (!found) theta = L.hi[last];   // rounding put s at the total
+            } else {
+                *r.flag = 1;   // empty active set: stay, counted as a rejection
+            }
+            L.theta = theta;
+        }
+    } else {
+        if (tid <= S) L.len[tid] = fmax(L.hi[tid] - L.lo[tid], 0.0);
+        __syncthreads();
+        if (tid == 0) {
+            double run = 0.0;
+            int k = 0;
+            for (; k + 4 <= S + 1; k += 4) {
+                const double l0 = L.len[k], l1 = L.len[k + 1], l2 = L.len[k + 2], l3 = L.len[k + 3];
+                run += l0;
+                L.cum[k] = run;
+                run += l1;
+                L.cum[k + 1] = run;
+                run += l2;
+                L.cum[k + 2] = run;
+                run += l3;
+                L.cum[k + 3] = run;
+            }
+            for (; k <= S; ++k) {
+                run += L.len[k];
+                L.cum[k] = run;
+            }
+            L.total = run;
+        }
+        __syncthreads();
+        const double total = L.total;
+        if (total > 0.0) {
+            const double sv = L.u * total;
+            if (tid <= S && L.len[tid] > 0.0) {
+                if (L.cum[tid] > sv) atomicMin(&L.kstar, tid);
+                atomicMax(&L.klast, tid);
+            }
+            __syncthreads();
+            if (tid == 0) {
+                const int k = L.kstar;
+                if (k <= S) {
+                    const double before = k > 0 ? L.cum[k - 1] : 0.0;
+                    L.theta = fmax(L.lo[k], fmin(L.lo[k] + (sv - before), L.hi[k]));
+                } else {
+                    L.theta = L.hi[L.klast];   // rounding put s at the total
+                }
+            }
+        } else if (tid == 0) {
+            L.theta = 0.0;
+            *r.flag = 1;   // empty active set: stay, counted as a rejection
+        }
+    }
+    if (tid == 0 && r.intervals) {
+        int w = 0;
+        for (int k = 0; k <= S; ++k) {
+            if (L.hi[k] - L.lo[k] > 0.0) {
+                r.intervals[2 * w] = L.lo[k];
+                r.intervals[2 * w + 1] = L.hi[k];
+                ++w;
+            }
+        }
+        if (r.n_intervals) *r.n_intervals = w;
+    }
+    __syncthreads();
+    move_chain<T>(r, L.theta);
 }
 
 // When more than SMAX rows survive, the survivors' buckets [blo, bhi] are
@@ -789,159 +1008,122 @@ __device__ bool bucket_chain(const ChainRef<T>& r, int sel, BucketLds<NB>& L) {
         S = find_survivors<RPT, NB, BS>(L, R, al, be);
     }
 
-    // survivors chained per bucket, so a row meets only its own bucket's
-    // survivors (a row-by-survivor scan cost tens of microseconds per chain):
-    // survivor s links to the previous survivor of its bucket, and the last
-    // one heads the bucket; meanwhile another wave draws this step's uniform
-    static_assert(SMAX <= 128, "survivor links are bytes");
-    if (tid < S) {
-        const int b = L.sk[tid];
-        int prev = -1;
-        bool last = true;
-        for (int s = 0; s < S; ++s) {
-            if (L.sk[s] == b) {
-                if (s < tid) prev = s;
-                else if (s > tid) last = false;
-            }
-        }
-        L.nxt[tid] = static_cast<signed char>(prev);
-        if (last) L.head[b] = static_cast<signed char>(tid);
-    }
-    if (tid == 64) L.u = theta_uniform(r);
+    link_survivors<T, NB>(r, L, S);
+    pred_max_pass<RPT, NB, BS>(L, R, al, be, 0);
     __syncthreads();
+    finish_bucket<T, NB>(r, L, S);
+    return true;
+}
 
-    // exact predecessor max inside each survivor's bucket (ties by row index)
+// Rows beyond what one pass holds in registers (m > BS RPT): the same bucket
+// path with refinement, each pass over the rows in chunks of BS RPT whose
+// roots are solved again (three passes, plus three per refinement level).
+// The roots depend only on the row, so every pass sees the same alpha and
+// beta.  Returns false, with nothing moved, as bucket_chain does.
+template <typename T, int RPT, int NB, int BS>
+__device__ bool bucket_chain_large(const ChainRef<T>& r, int sel, BucketLds<NB>& L) {
+    const int tid = threadIdx.x;
+    constexpr int CH = BS * RPT;
+    for (int b = tid; b < NB; b += BS) {
+        L.G[b] = 0ull;
+        L.head[b] = -1;
+    }
+    if (tid == 0) L.scount = 0;
+    __syncthreads();
+    const T* Pc = r.P0 + static_cast<size_t>(sel) * r.pstride;
+    double al[RPT], be[RPT];
+    RefineMap R;
+    R.n = 0;
+    for (int c0 = 0; c0 < r.m; c0 += CH) {
+        block_roots<T, RPT, BS>(r, Pc, c0, true, al, be);
+        bucket_max_pass<RPT, NB>(L, R, al, be);
+    }
+    bucket_prefix_max<NB, BS>(L, 0.0, true);
+    int S = 0;
+    for (int c0 = 0; c0 < r.m; c0 += CH) {
+        block_roots<T, RPT, BS>(r, Pc, c0, false, al, be);
+        S = find_survivors<RPT, NB, BS>(L, R, al, be, c0);
+    }
+    int s_prev = 1 << 30;
+    while (S > kRefineTarget) {
+        if (R.n == kRefineLevels || (S <= SMAX && 2 * S > s_prev)) {
+            if (S > SMAX) return false;
+            break;
+        }
+        s_prev = S;
+        if (tid == 0) {
+            L.smin = NB;
+            L.smax = -1;
+        }
+        __syncthreads();
+        for (int c0 = 0; c0 < r.m; c0 += CH) {
+            block_roots<T, RPT, BS>(r, Pc, c0, false, al, be);
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-        const int b = be[j] > 0.0 ? bucket_of<NB>(R, al[j]) : -1;
-        if (b >= 0) {
-            const int i = tid + BS * j;
-            for (int s = L.head[b]; s >= 0; s = L.nxt[s]) {
-                if (al[j] < L.sa[s] || (al[j] == L.sa[s] && i < L.si[s]))
-                    atomicMax(&L.sm[s], obits(be[j]));
-            }
-        }
-    }
-    __syncthreads();
-
-    // the survivors' candidates, placed in ascending (alpha, row) order
-    const double eps = r.eps;
-    if (tid < S) {
-        const double alpha = L.sa[tid];
-        const int row = L.si[tid];
-        int rank = 0;
-        for (int s = 0; s < S; ++s) {
-            const double o = L.sa[s];
-            rank += (o < alpha) || (o == alpha && L.si[s] < row);
-        }
-        double lo = fmax(ofloat(L.G[L.sk[tid]]), ofloat(L.sm[tid]));
-        double hi = alpha;
-        if (lo > 0.0) lo += eps;
-        if (hi < kTwoPi) hi -= eps;
-        L.lo[rank] = lo;
-        L.hi[rank] = hi;
-    }
-    if (tid == 0) {
-        const double g = L.gtot;
-        L.lo[S] = g > 0.0 ? g + eps : g;
-        L.hi[S] = kTwoPi;
-        L.kstar = 1 << 30;
-        L.klast = -1;
-    }
-    __syncthreads();
-
-    // inverse CDF over the S + 1 candidates in order: the running sums are a
-    // sequential left-to-right sum (those of a cumulative sum), and theta lies
-    // in the first non-empty candidate whose running sum exceeds s = u L.  Few
-    // candidates: one thread walks them.  Many: the lengths are formed in
-    // parallel, one thread keeps the running sums, and the search is
-    // parallel.  Both give the same theta bit for bit.
-    if (S < 16) {
-        if (tid == 0) {
-            double total = 0.0;
-            for (int k = 0; k <= S; ++k) total += fmax(L.hi[k] - L.lo[k], 0.0);
-            double theta = 0.0;
-            if (total > 0.0) {
-                const double sv = L.u * total;
-                double run = 0.0;
-                int last = -1;
-                bool found = false;
-                for (int k = 0; k <= S; ++k) {
-                    const double len = fmax(L.hi[k] - L.lo[k], 0.0);
-                    if (len > 0.0) {
-                        last = k;
-                        if (!found && run + len > sv) {
-                            theta = fmax(L.lo[k], fmin(L.lo[k] + (sv - run), L.hi[k]));
-                            found = true;
-                        }
+            for (int j = 0; j < RPT; ++j) {
+                if (be[j] > 0.0) {
+                    const int b = bucket_of<NB>(R, al[j]);
+                    if (b >= 0 && al[j] >= ofloat(L.G[b])) {
+                        atomicMin(&L.smin, b);
+                        atomicMax(&L.smax, b);
                     }
-                    run += len;
-                }
-                if (!found) theta = L.hi[last];   // rounding put s at the total
-            } else {
-                *r.flag = 1;   // empty active set: stay, counted as a rejection
-            }
-            L.theta = theta;
-        }
-    } else {
-        if (tid <= S) L.len[tid] = fmax(L.hi[tid] - L.lo[tid], 0.0);
-        __syncthreads();
-        if (tid == 0) {
-            double run = 0.0;
-            int k = 0;
-            for (; k + 4 <= S + 1; k += 4) {
-                const double l0 = L.len[k], l1 = L.len[k + 1], l2 = L.len[k + 2], l3 = L.len[k + 3];
-                run += l0;
-                L.cum[k] = run;
-                run += l1;
-                L.cum[k + 1] = run;
-                run += l2;
-                L.cum[k + 2] = run;
-                run += l3;
-                L.cum[k + 3] = run;
-            }
-            for (; k <= S; ++k) {
-                run += L.len[k];
-                L.cum[k] = run;
-            }
-            L.total = run;
-        }
-        __syncthreads();
-        const double total = L.total;
-        if (total > 0.0) {
-            const double sv = L.u * total;
-            if (tid <= S && L.len[tid] > 0.0) {
-                if (L.cum[tid] > sv) atomicMin(&L.kstar, tid);
-                atomicMax(&L.klast, tid);
-            }
-            __syncthreads();
-            if (tid == 0) {
-                const int k = L.kstar;
-                if (k <= S) {
-                    const double before = k > 0 ? L.cum[k - 1] : 0.0;
-                    L.theta = fmax(L.lo[k], fmin(L.lo[k] + (sv - before), L.hi[k]));
-                } else {
-                    L.theta = L.hi[L.klast];   // rounding put s at the total
                 }
             }
-        } else if (tid == 0) {
-            L.theta = 0.0;
-            *r.flag = 1;   // empty active set: stay, counted as a rejection
+        }
+        __syncthreads();
+        const int blo = __builtin_amdgcn_readfirstlane(L.smin);
+        const int bhi = __builtin_amdgcn_readfirstlane(L.smax);
+        const int f = NB / (bhi - blo + 1);
+        if (f < 2) {
+            if (S > SMAX) return false;
+            break;
+        }
+        const double g0 = ofloat(L.G[blo]);
+        double off = 0.0, sc = 1.0;
+#pragma unroll
+        for (int l = 0; l < kRefineLevels; ++l) {
+            if (l + 1 == R.n) {
+                off = R.off[l];
+                sc = R.sc[l];
+            }
+        }
+        off = uniform_double(off + blo / sc);
+        sc = uniform_double(sc * f);
+#pragma unroll
+        for (int l = 0; l < kRefineLevels; ++l) {
+            if (l == R.n) {
+                R.lo[l] = blo;
+                R.hi[l] = bhi;
+                R.f[l] = f;
+                R.off[l] = off;
+                R.sc[l] = sc;
+            }
+        }
+        ++R.n;
+        __syncthreads();   // every read of G and of the range precedes the reset
+        for (int b = tid; b < NB; b += BS) {
+            L.G[b] = 0ull;
+            L.head[b] = -1;
+        }
+        if (tid == 0) L.scount = 0;
+        __syncthreads();
+        for (int c0 = 0; c0 < r.m; c0 += CH) {
+            block_roots<T, RPT, BS>(r, Pc, c0, false, al, be);
+            bucket_max_pass<RPT, NB>(L, R, al, be);
+        }
+        bucket_prefix_max<NB, BS>(L, g0, false);
+        for (int c0 = 0; c0 < r.m; c0 += CH) {
+            block_roots<T, RPT, BS>(r, Pc, c0, false, al, be);
+            S = find_survivors<RPT, NB, BS>(L, R, al, be, c0);
         }
     }
-    if (tid == 0 && r.intervals) {
-        int w = 0;
-        for (int k = 0; k <= S; ++k) {
-            if (L.hi[k] - L.lo[k] > 0.0) {
-                r.intervals[2 * w] = L.lo[k];
-                r.intervals[2 * w + 1] = L.hi[k];
-                ++w;
-            }
-        }
-        if (r.n_intervals) *r.n_intervals = w;
+    if (S > SMAX) return false;
+    link_survivors<T, NB>(r, L, S);
+    for (int c0 = 0; c0 < r.m; c0 += CH) {
+        block_roots<T, RPT, BS>(r, Pc, c0, false, al, be);
+        pred_max_pass<RPT, NB, BS>(L, R, al, be, c0);
     }
     __syncthreads();
-    move_chain<T>(r, L.theta);
+    finish_bucket<T, NB>(r, L, S);
     return true;
 }
 
@@ -955,6 +1137,39 @@ __global__ __launch_bounds__(BS, (BS == 512 && RPT <= 4 && !REFINE) ? 8 : 1) voi
     if (blockIdx.x == 0 && threadIdx.x == 0) a.fb_count[(step + 1) & 1] = 0;   // next step's list
     const bool done = !a.force_full && bucket_chain<T, RPT, NB, BS, REFINE>(r, sel, lds);
     if (!done && threadIdx.x == 0) a.fb_list[atomicAdd(a.fb_count + (step & 1), 1)] = c;
+}
+
+// Rows beyond 4096: 512 threads per chain, the chunked bucket path with
+// refinement; chains it cannot resolve go to the full sort of keys only.
+constexpr int kMaxRowsLarge = 16384;
+
+template <typename T>
+__global__ __launch_bounds__(512) void sample_large_kernel(SampleArgs a) {
+    __shared__ BucketLds<2048> lds;
+    const int c = a.c0 + blockIdx.x;
+    const ChainRef<T> r = make_ref<T>(a, c);
+    const int sel = a.has_pending ? commit_chain<T>(r) : *r.sel;
+    const uint32_t step = r.step;
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.fb_count[(step + 1) & 1] = 0;   // next step's list
+    const bool done = !a.force_full && bucket_chain_large<T, 8, 2048, 512>(r, sel, lds);
+    if (!done && threadIdx.x == 0) a.fb_list[atomicAdd(a.fb_count + (step & 1), 1)] = c;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void fallback_large_kernel(SampleArgs a) {
+    __shared__ uint64_t s_key[kMaxRowsLarge];
+    __shared__ double s_red[4];
+    __shared__ int s_cnt[4];
+    __shared__ double s_bcast[2];
+    __shared__ int s_kstar;
+    __shared__ double s_theta[2];
+    const FullLds L{nullptr, nullptr, s_key, s_red, s_cnt, s_bcast, &s_kstar, s_theta};
+    const int count = a.fb_count[abs_step(a) & 1];
+    for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
+        const ChainRef<T> r = make_ref<T>(a, a.fb_list[idx]);
+        full_chain<T, true>(r, *r.sel, L);
+        __syncthreads();
+    }
 }
 
 // Chains the bucket kernel handed over (a.fb_list[0 .. fb_count[step & 1])),

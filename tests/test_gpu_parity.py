@@ -65,7 +65,13 @@ CASES = [
     ("many_m1000_f32", 40, 1000, 300, 32, 1e-6),
     ("many_m3000_f32", 40, 3000, 270, 32, 1e-6),
     ("many_max_m_f64", 20, 4096, 260, 64, 0.0),
+    # more than 4096 rows: chunked passes, keys-only full sort
+    ("large_m_f32", 40, 6000, 24, 32, 1e-6),
+    ("large_m_f64", 30, 9000, 8, 64, 0.0),
+    ("large_m_many_f32", 30, 5000, 300, 32, 1e-6),
+    ("max_large_m_f32", 20, 16384, 4, 32, 1e-6),
 ]
+LARGE = [c for c in CASES if c[0].startswith("large_m")]
 
 
 @pytest.mark.parametrize("name,d,m,C,precision,eps", CASES, ids=[c[0] for c in CASES])
@@ -306,7 +312,7 @@ def test_errors_are_reported(E):
         E.Sampler(pr.A, pr.b, np.full(pr.d, 50.0), 4, precision=64)
     assert ei.value.status == E.ESS_ERR_INFEASIBLE_START and "chain 0" in str(ei.value)
     with pytest.raises(E.EssError) as ei:
-        E.Sampler(np.zeros((5000, 3)), np.ones(5000), np.zeros(3), 2)
+        E.Sampler(np.zeros((20000, 3)), np.ones(20000), np.zeros(3), 2)
     assert ei.value.status == E.ESS_ERR_UNSUPPORTED
     with pytest.raises(E.EssError) as ei:
         E.Sampler(pr.A, pr.b, pr.x0, 4, precision=16)
@@ -434,6 +440,50 @@ def test_section_4_2_crowded_buckets_are_refined(E, precision):
     assert not fails, fails[:5]
 
 
+@pytest.mark.parametrize("precision", [32, 64])
+def test_large_m_overflow_takes_keys_only_full_sort(E, precision):
+    """300 disjoint arcs (Section 3.1's reduction) among 6000 rows that never
+    meet the ellipse (b / r = 5): more than 4096 rows, survivors spread over
+    the circle, so refinement cannot help and the keys-only full sort runs."""
+    rng = np.random.default_rng(17)
+    c = 0.1 + 5.9 * (np.arange(300) + rng.uniform(0.2, 0.4, 300)) / 300
+    A1, b1 = arcs_problem(c, c + 0.005)
+    ang = rng.uniform(0, 2 * np.pi, 6000)
+    A = np.vstack([A1, np.stack([np.cos(ang), np.sin(ang)], axis=1)])
+    b = np.concatenate([b1, np.full(6000, 5.0)])
+    perm = rng.permutation(len(b))
+    A, b = A[perm], b[perm]
+    C = 4
+    npdt = np.float32 if precision == 32 else np.float64
+    x = np.tile(np.array([1.0, 0.0], npdt), (C, 1))
+    nu = np.tile(np.array([0.0, 1.0], npdt), (C, 1))
+    u = (np.arange(C) + 0.5) / C
+    Ab = A.astype(npdt).astype(np.float64)
+    ref = ref_ess.transition(Ab, b, x.astype(np.float64), nu.astype(np.float64), u, store=npdt)
+    g = assert_same_as_full_sort(E, Ab, b, x, nu, u, precision, 0.0)
+    assert (g["n_intervals"] == 301).all(), g["n_intervals"]
+    fails, _ = compare_transition(Ab, b, x.astype(np.float64), nu, u, g, ref)
+    assert not fails, fails[:5]
+
+
+def test_section_4_2_at_d_8000(E):
+    """Section 4.2's instance beyond 4096 rows (d = m = 8000) from x0: crowded
+    buckets on the chunked path, against the oracle and the full sort."""
+    pr = synth.paper_highdim(d=8000)
+    C = 2
+    rng = np.random.default_rng(43)
+    x = np.tile(pr.x0, (C, 1)).astype(np.float32)
+    nu = rng.standard_normal(x.shape).astype(np.float32)
+    u = rng.uniform(size=C)
+    Ab = pr.A.astype(np.float32).astype(np.float64)
+    ref = ref_ess.transition(Ab, pr.b, x.astype(np.float64), nu.astype(np.float64), u,
+                             eps=1e-6, store=np.float32)
+    say("coarse survivors", coarse_survivors(ref["alpha"], ref["beta"]))
+    g = assert_same_as_full_sort(E, pr.A, pr.b, x, nu, u, 32, 1e-6)
+    fails, _ = compare_transition(Ab, pr.b, x.astype(np.float64), nu, u, g, ref)
+    assert not fails, fails[:5]
+
+
 def test_two_refinement_levels(E):
     """600 rows whose alphas lie within 6e-7 rad (one bucket, and still one
     sub-bucket after the first split) and whose arcs overlap: two levels of
@@ -448,7 +498,8 @@ def test_two_refinement_levels(E):
     assert_same_as_full_sort(E, Ab, b, x, nu, u, 64, 0.0)
 
 
-@pytest.mark.parametrize("name,d,m,C,precision,eps", CASES[:4], ids=[c[0] for c in CASES[:4]])
+@pytest.mark.parametrize("name,d,m,C,precision,eps", CASES[:4] + LARGE,
+                         ids=[c[0] for c in CASES[:4] + LARGE])
 def test_full_sort_path_matches_bucket_path(E, name, d, m, C, precision, eps):
     rng = np.random.default_rng(d * 7 + m)
     A = rng.standard_normal((m, d)) / math.sqrt(d)
