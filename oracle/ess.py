@@ -11,8 +11,10 @@ Implementation for Linearly Truncated Multivariate Normal Distributions"
   the active intervals I_act, draw theta uniformly on I_act, move;
 * per-constraint roots of p cos(theta) + q sin(theta) = b (Section 2, eq.
   "trigonometry-equation"; Appendix B, eq. "roots");
-* the active intervals by brute force (Algorithm 2) and by sort + cumulative
-  max (Algorithm 3 / Proposition 1), with the no-root padding of Section 3.2;
+* the active intervals by brute force (Algorithm 2), by sort + cumulative
+  max (Algorithm 3 / Proposition 1), with the no-root padding of Section 3.2,
+  and by likelihood testing at midpoints (Section 3.1, the quadratic method
+  the paper compares against);
 * the two safeguards of Section 3.3: trimming by epsilon and reject-and-stay.
 
 Readings taken where the paper is silent (each is listed with its reason in
@@ -29,6 +31,8 @@ the design notes):
 Everything is float64; x and nu may be handed in already rounded to the
 storage precision of the code under test.
 """
+import math
+
 import numpy as np
 
 from . import philox
@@ -127,6 +131,42 @@ def alg3_candidates(alpha, beta):
 def nonempty(lo, hi, min_len=0.0):
     """Pieces of one chain's candidate list with length > min_len, in order."""
     return [(float(l), float(h)) for l, h in zip(lo, hi) if h - l > min_len]
+
+
+# --------------------------------------------------------------------------
+# Section 3.1: likelihood testing at midpoints (the quadratic comparator)
+# --------------------------------------------------------------------------
+def likelihood(p, q, b, theta):
+    """Section 3.1's likelihood: 1 when x(theta) satisfies every constraint,
+    evaluated from the cached projections p = A x_t and q = A nu_t."""
+    return bool(np.all(p * math.cos(theta) + q * math.sin(theta) <= b))
+
+
+def midpoint_intervals(p, q, b):
+    """Active intervals of one chain by likelihood testing at midpoints
+    (Section 3.1, the variant that tests the point halfway between two
+    consecutive intersection angles instead of a fixed offset).
+
+    The intersection angles of the crossing rows are sorted, with 0 and 2 pi
+    as the outer ends; every gap of positive length whose midpoint has
+    likelihood 1 is active, and touching active gaps merge.  Each test reads
+    all m rows, so the whole is O(m^2).  Returns the list of (lo, hi).
+    """
+    p = np.asarray(p, dtype=np.float64)
+    q = np.asarray(q, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    alpha, beta, hit = roots(p, q, b)
+    ends = np.concatenate([[0.0], np.sort(np.concatenate([alpha[hit], beta[hit]])), [TWO_PI]])
+    out = []
+    for lo, hi in zip(ends[:-1], ends[1:]):
+        if hi <= lo:
+            continue
+        if likelihood(p, q, b, 0.5 * (lo + hi)):
+            if out and out[-1][1] == lo:
+                out[-1] = (out[-1][0], float(hi))
+            else:
+                out.append((float(lo), float(hi)))
+    return out
 
 
 # --------------------------------------------------------------------------

@@ -7,7 +7,8 @@ function for a plausibly wrong one and check that some pin fails.
 Sources of truth:
 * the worked examples drawn in Figures 1 and 2 (golden files, cited there);
 * Algorithm 2 (the definition of I_act) and a dense theta grid that tests
-  feasibility of x(theta) directly;
+  feasibility of x(theta) directly (they pin Algorithm 3 and the midpoint
+  likelihood testing of Section 3.1 alike);
 * closed forms: Appendix D's worst case, the sorting reduction of Section 3.1,
   the residual of the trigonometric equation, rotation covariance;
 * textbook distributions: uniformity of theta (Kolmogorov-Smirnov), moments
@@ -220,6 +221,31 @@ def pin_alg3_equals_alg2(seed=13, n_sets=3000):
     return []
 
 
+def pin_midpoint_equals_alg2(seed=21, n_cases=400):
+    """Section 3.1's likelihood testing at midpoints finds the set that
+    Algorithm 2 defines, on random polytopes through random ellipses."""
+    rng = np.random.default_rng(seed)
+    for case in range(n_cases):
+        d = int(rng.integers(1, 5))
+        m = int(rng.integers(1, 12))
+        A = rng.standard_normal((m, d))
+        b = rng.uniform(0.05, 1.5, m)
+        x = np.zeros(d)
+        for _ in range(200):
+            y = rng.standard_normal(d)
+            if (A @ y < b).all():
+                x = y
+                break
+        nu = rng.standard_normal(d)
+        p, q = A @ x, A @ nu
+        al, be, _ = ess.roots(p, q, b)
+        want = [pc for pc in ess.alg2_brute_force(al, be) if pc[1] > pc[0]]
+        got = ess.midpoint_intervals(p, q, b)
+        if not _same_sets(got, want, 1e-12):
+            return [f"midpoint != alg2 (case {case}): {got} vs {want}"]
+    return []
+
+
 def pin_dense_grid(seed=14, n_cases=150, n_grid=4001):
     """Active intervals agree with the feasibility of x(theta) on a dense grid."""
     rng = np.random.default_rng(seed)
@@ -416,6 +442,7 @@ def pin_rejection_sampling_reference(seed=19, n_chains=200, n_steps=100, burn=20
 
 
 FAST_PINS = [pin_fig1, pin_fig2, pin_root_residual, pin_rotation_covariance,
-             pin_alg3_equals_alg2, pin_dense_grid, pin_appendix_d, pin_sorting_reduction,
+             pin_alg3_equals_alg2, pin_midpoint_equals_alg2, pin_dense_grid, pin_appendix_d,
+             pin_sorting_reduction,
              pin_theta_uniform, pin_philox_kat, pin_box_muller]
 CHAIN_PINS = [pin_chain_box_moments, pin_exp1_table, pin_rejection_sampling_reference]

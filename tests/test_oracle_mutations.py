@@ -3,7 +3,9 @@
 Every mutation below is a plausible slip when writing the oracle from the
 paper: a flipped sign or swapped argument in the root formula, a missing
 cumulative max, an off-by-one in gamma, a wrong interpolation in the inverse
-CDF, swapped ellipse terms, an inverted safeguard, a wrong Philox constant.
+CDF, swapped ellipse terms, an inverted safeguard, a wrong Philox constant,
+a likelihood test that reads one row or swaps inside and outside, a gap
+tested at its end instead of its middle.
 """
 import numpy as np
 import pytest
@@ -98,6 +100,24 @@ def _box_muller_cos_twice(u1, u2):
     return rad * np.cos(TWO_PI * u2), rad * np.cos(TWO_PI * u2)
 
 
+def _likelihood_first_row_only(p, q, b, theta):
+    return bool(p[0] * np.cos(theta) + q[0] * np.sin(theta) <= b[0])
+
+
+def _likelihood_strict_reversed(p, q, b, theta):
+    return bool(np.all(p * np.cos(theta) + q * np.sin(theta) >= b))   # inside / outside swapped
+
+
+def _midpoint_tests_lower_end(p, q, b):
+    alpha, beta, hit = ess.roots(p, q, b)
+    ends = np.concatenate([[0.0], np.sort(np.concatenate([alpha[hit], beta[hit]])), [TWO_PI]])
+    out = []
+    for lo, hi in zip(ends[:-1], ends[1:]):
+        if hi > lo and ess.likelihood(p, q, b, lo):     # the gap's end, not its middle
+            out.append((float(lo), float(hi)))
+    return out
+
+
 ORIG = {"roots": ess.roots, "alg3_candidates": ess.alg3_candidates,
         "transition": ess.transition, "philox4x32_10": philox.philox4x32_10}
 
@@ -113,6 +133,9 @@ MUTATIONS = [
     (ess, "transition", _transition_inverted_safeguard),
     (philox, "philox4x32_10", _philox_wrong_weyl),
     (philox, "box_muller", _box_muller_cos_twice),
+    (ess, "likelihood", _likelihood_first_row_only),
+    (ess, "likelihood", _likelihood_strict_reversed),
+    (ess, "midpoint_intervals", _midpoint_tests_lower_end),
 ]
 
 
