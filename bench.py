@@ -161,21 +161,30 @@ def bench_paper_timing(E, torch, dims=(100, 250, 500, 1000, 2000, 4000)):
     out = []
     for d in dims:
         row = {"d": d, "m": d}
-        for chains, steps in ((1, 1000), (10, 100)):
-            pr = synth.paper_highdim(d=d, n_chains=chains, n_steps=steps)
-            s = E.Sampler(pr.A, pr.b, pr.x0, chains, seed=0, precision=32)
-            s.run(steps, keep_trace=False, count_rejections=False)      # capture
-            s.set_state(torch.as_tensor(np.broadcast_to(pr.x0, (chains, d)).copy()), 0)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            _, nrej = s.run(steps, keep_trace=False)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-            s.close()
-            row[f"{chains}x{steps}_ms"] = dt * 1e3
-            row[f"{chains}x{steps}_rejections"] = int(nrej)
+        pr = synth.paper_highdim(d=d)
+        # Algorithm 3, and up to 4096 rows the quadratic comparator (Section
+        # 3.1's likelihood testing at midpoints) on the same instance
+        methods = (("alg3", ""), ("midpoint", "_midpoint")) if d <= 4096 else (("alg3", ""),)
+        for method, tag in methods:
+            for chains, steps in ((1, 1000), (10, 100)):
+                s = E.Sampler(pr.A, pr.b, pr.x0, chains, seed=0, precision=32, method=method)
+                s.run(steps, keep_trace=False, count_rejections=False)      # capture
+                s.set_state(torch.as_tensor(np.broadcast_to(pr.x0, (chains, d)).copy()), 0)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, nrej = s.run(steps, keep_trace=False)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                s.close()
+                row[f"{chains}x{steps}{tag}_ms"] = dt * 1e3
+                row[f"{chains}x{steps}{tag}_rejections"] = int(nrej)
+        if "1x1000_midpoint_ms" in row:
+            row["midpoint_over_alg3_1x1000"] = row["1x1000_midpoint_ms"] / row["1x1000_ms"]
+        print(f"# paper timing d={d}: {row}", file=sys.stderr, flush=True)
         out.append(row)
-    return {"workload": "Section 4.2 instances, float32, 1000 samples per run", "rows": out}
+    return {"workload": "Section 4.2 instances, float32, 1000 samples per run; *_midpoint: "
+                        "likelihood testing at midpoints (O(m^2)) on the same instances",
+            "rows": out}
 
 
 def main():
@@ -195,7 +204,7 @@ def main():
                     help="steps per arm of the warm-start comparison")
     ap.add_argument("--paper-timing-only", action="store_true",
                     help="run only Section 4.2's timing protocol and print its JSON")
-    ap.add_argument("--paper-dims", default="100,250,500,1000,2000,4000",
+    ap.add_argument("--paper-dims", default="100,250,500,1000,2000,4000,8000,16000",
                     help="comma-separated d values of the Section 4.2 timing protocol")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain elementwise copy of 256 MiB (reference for "

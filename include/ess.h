@@ -54,6 +54,11 @@ typedef enum {
 #define ESS_SORT_FULL 2u      /* build every chain's active intervals with a full
                                  sort of all crossing rows instead of the bucketed
                                  sort (same intervals; for comparison) */
+#define ESS_LIKELIHOOD_MIDPOINT 16u  /* comparator, not Algorithm 3: find the
+                                 active intervals by likelihood testing at the
+                                 midpoints between sorted intersection angles
+                                 (Section 3.1), O(m^2) per chain; m <= 4096,
+                                 single-problem contexts only */
 
 /* A whitened problem: N(0, I_d) truncated to {x : A x <= b} (Section 1).
  * The polytope must have a non-empty interior; x0 must be strictly inside
@@ -180,6 +185,30 @@ ess_status ess_profile(ess_ctx* ctx, int enable);
 ess_status ess_profile_read(ess_ctx* ctx, int kind, double* total_ms, int64_t* count);
 
 void ess_destroy(ess_ctx* ctx);
+
+/* ---- Non-standard normal front end (Appendix A) ----------------------------
+ * x ~ N(mu, Sigma) truncated to {A x <= b}, with Sigma = L L^T, is x = L u + mu
+ * for u ~ N(0, I_d) truncated to {(A L) u <= b - A mu}: whiten the problem,
+ * sample u with ess_init / ess_run, and map the states or traces back.
+ * Matrices are row-major; L is lower triangular, d x d, float64. */
+
+/* L = the Cholesky factor of sigma (both host, d x d, float64; only the lower
+ * triangle of sigma is read, the upper triangle of L is zero).
+ * ESS_ERR_INVALID_ARG when sigma is not positive definite. */
+ess_status ess_cholesky(const double* sigma, int32_t d, double* L);
+
+/* A_out (m x d, T) = A (m x d, T) L and b_out (m, float64) = b - A mu, float64
+ * sums; T is float for precision 32, double for 64.  All pointers device;
+ * A_out must not alias A.  Work is queued on `stream` (nullable). */
+ess_status ess_whiten(const void* A, const double* b, const double* L, const double* mu,
+                      int32_t m, int32_t d, int32_t precision, void* A_out, double* b_out,
+                      void* stream);
+
+/* X_out (n x d, T) = U (n x d, T) L^T + mu: every row u of U becomes L u + mu
+ * (states, or traces flattened to rows).  Device pointers; X_out must not
+ * alias U. */
+ess_status ess_unwhiten(const void* U, int64_t n, int32_t d, const double* L, const double* mu,
+                        int32_t precision, void* X_out, void* stream);
 
 /* ---- The warm-start network ------------------------------------------------
  * A fully connected network y = W_L g(... g(W_1 x + c_1) ...) + c_L with the

@@ -15,7 +15,8 @@ Implementation for Linearly Truncated Multivariate Normal Distributions"
   max (Algorithm 3 / Proposition 1), with the no-root padding of Section 3.2,
   and by likelihood testing at midpoints (Section 3.1, the quadratic method
   the paper compares against);
-* the two safeguards of Section 3.3: trimming by epsilon and reject-and-stay.
+* the two safeguards of Section 3.3: trimming by epsilon and reject-and-stay;
+* Appendix A's change of variables for N(mu, Sigma), Sigma = L L^T.
 
 Readings taken where the paper is silent (each is listed with its reason in
 the design notes):
@@ -204,14 +205,15 @@ def sample_theta(lo, hi, u):
 # --------------------------------------------------------------------------
 # Algorithm 1: one transition for a batch of chains
 # --------------------------------------------------------------------------
-def transition(A, b, x, nu, u, eps=0.0, pq=None, store=np.float64):
+def transition(A, b, x, nu, u, eps=0.0, pq=None, store=np.float64, method="alg3"):
     """One transition for C chains.
 
     A (m, d), b (m,) or (C, m) (one polytope per chain), x (C, d), nu (C, d),
     u (C,).  If pq = (P, Q) (each
     (C, m)) is given, those projections are used instead of A x and A nu.
     The proposal is rounded to `store` before the feasibility check, as the
-    code under test stores it.
+    code under test stores it.  method="midpoint" builds the active intervals
+    by Section 3.1's likelihood testing instead of Algorithm 3.
     Returns a dict with x_new, rejected, theta, intervals (list per chain of
     the non-empty trimmed pieces), alpha, beta, p, q, x_prop.
     """
@@ -226,15 +228,24 @@ def transition(A, b, x, nu, u, eps=0.0, pq=None, store=np.float64):
         P, Q = (np.asarray(t, dtype=np.float64) for t in pq)
     bb = b[None, :] if b.ndim == 1 else b
     alpha, beta, _ = roots(P, Q, bb)
-    lo, hi = alg3_candidates(alpha, beta)
-    lo, hi = trim(lo, hi, eps)
     C = x.shape[0]
+    if method == "alg3":
+        lo, hi = alg3_candidates(alpha, beta)
+        lo, hi = trim(lo, hi, eps)
+        pieces = [(lo[c], hi[c]) for c in range(C)]
+    else:
+        pieces = []
+        for c in range(C):
+            ivs = midpoint_intervals(P[c], Q[c], bb[c if bb.shape[0] > 1 else 0])
+            lo_c = np.array([v[0] for v in ivs] or [0.0])
+            hi_c = np.array([v[1] for v in ivs] or [0.0])
+            pieces.append(trim(lo_c, hi_c, eps))
     theta = np.zeros(C)
     total = np.zeros(C)
     intervals = []
     for c in range(C):
-        theta[c], total[c] = sample_theta(lo[c], hi[c], u[c])
-        intervals.append(nonempty(lo[c], hi[c]))
+        theta[c], total[c] = sample_theta(pieces[c][0], pieces[c][1], u[c])
+        intervals.append(nonempty(pieces[c][0], pieces[c][1]))
     ct, st = np.cos(theta), np.sin(theta)
     x_prop = x * ct[:, None] + nu * st[:, None]
     x_prop = x_prop.astype(store).astype(np.float64)
@@ -270,6 +281,21 @@ def run(A, b, x0, n_chains, n_steps, seed, eps=0.0, store=np.float64,
         if (t + 1) % thin == 0:
             trace.append(x.copy())
     return np.array(trace).reshape(-1, n_chains, d), x, rej
+
+
+# --------------------------------------------------------------------------
+# Appendix A: a non-standard normal through the change of variables
+# --------------------------------------------------------------------------
+def whiten(A, b, mu, L):
+    """x ~ N(mu, L L^T) truncated to {A x <= b} is x = L u + mu with
+    u ~ N(0, I) truncated to {(A L) u <= b - A mu}: returns (A L, b - A mu)."""
+    A = np.asarray(A, dtype=np.float64)
+    return A @ np.asarray(L, dtype=np.float64), np.asarray(b, dtype=np.float64) - A @ np.asarray(mu, dtype=np.float64)
+
+
+def unwhiten(U, L, mu):
+    """x = L u + mu for every row u of U."""
+    return np.asarray(U, dtype=np.float64) @ np.asarray(L, dtype=np.float64).T + np.asarray(mu, dtype=np.float64)
 
 
 # --------------------------------------------------------------------------

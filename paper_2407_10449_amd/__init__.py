@@ -24,6 +24,7 @@ ESS_ERR_OOM = 4
 ESS_ERR_UNSUPPORTED = 5
 ESS_X0_BROADCAST = 1
 ESS_SORT_FULL = 2
+ESS_LIKELIHOOD_MIDPOINT = 16
 ESS_PER_CHAIN_B = 4
 ESS_EAGER = 8
 
@@ -74,6 +75,11 @@ _SIGS = {
     "ess_mlp_destroy": ([_P], None),
     "ess_autotune": ([_P, ctypes.c_int32, ctypes.c_char_p, ctypes.c_int32], ctypes.c_int),
     "ess_destroy": ([_P], None),
+    "ess_cholesky": ([_P, ctypes.c_int32, _P], ctypes.c_int),
+    "ess_whiten": ([_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P, _P],
+                   ctypes.c_int),
+    "ess_unwhiten": ([_P, ctypes.c_int64, ctypes.c_int32, _P, _P, ctypes.c_int32, _P, _P],
+                     ctypes.c_int),
     "ess_last_error": ([], ctypes.c_char_p),
 }
 
@@ -247,6 +253,63 @@ def ess_last_error():
 
 
 # ----------------------------------------------------------- convenience
+def ess_cholesky(sigma):
+    """Host Cholesky factor (float64, lower) of a host matrix."""
+    sig = np.ascontiguousarray(np.asarray(sigma, dtype=np.float64))
+    d = sig.shape[0]
+    L = np.empty_like(sig)
+    _check(lib().ess_cholesky(sig.ctypes.data_as(_P), d, L.ctypes.data_as(_P)))
+    return L
+
+
+def ess_whiten(A, b, L, mu, A_out, b_out, precision, stream=None):
+    m, d = A.shape
+    _check(lib().ess_whiten(_ptr(A), _ptr(b), _ptr(L), _ptr(mu), m, d, precision, _ptr(A_out),
+                            _ptr(b_out), _stream_handle(stream)))
+
+
+def ess_unwhiten(U, L, mu, X_out, precision, stream=None):
+    d = U.shape[-1]
+    n = U.numel() // d
+    _check(lib().ess_unwhiten(_ptr(U), n, d, _ptr(L), _ptr(mu), precision, _ptr(X_out),
+                              _stream_handle(stream)))
+
+
+class Gaussian:
+    """Appendix A: x ~ N(mu, Sigma) truncated to {A x <= b} as x = L u + mu,
+    u ~ N(0, I) truncated to {(A L) u <= b - A mu}.  Give Sigma (factored by
+    the library's host Cholesky) or its lower factor L.  `A`, `b` hold the
+    whitened problem on the device (for Sampler, whose start is given in u:
+    u = 0 is x = mu); map() takes states or traces of u back to x."""
+
+    def __init__(self, A, b, mu, Sigma=None, L=None, precision=32, device="cuda", stream=None):
+        import torch
+        if (Sigma is None) == (L is None):
+            raise ValueError("give exactly one of Sigma and L")
+        self.torch = torch
+        self.precision = precision
+        self.dtype = torch.float32 if precision == 32 else torch.float64
+        self.device = torch.device(device)
+        self.stream = stream
+        if L is None:
+            L = ess_cholesky(np.asarray(Sigma, dtype=np.float64))
+        self.L = torch.as_tensor(np.asarray(L, dtype=np.float64)).to(self.device).contiguous()
+        self.mu = torch.as_tensor(np.asarray(mu, dtype=np.float64)).to(self.device).contiguous()
+        A_in = torch.as_tensor(np.asarray(A)).to(self.device, self.dtype).contiguous()
+        b_in = torch.as_tensor(np.asarray(b, dtype=np.float64)).to(self.device).contiguous()
+        self.A = torch.empty_like(A_in)
+        self.b = torch.empty_like(b_in)
+        ess_whiten(A_in, b_in, self.L, self.mu, self.A, self.b, precision, stream)
+
+    def map(self, U, out=None):
+        """x = L u + mu for every row u of U (states (C, d) or traces (T, C, d))."""
+        U = U.contiguous()
+        if out is None:
+            out = self.torch.empty_like(U)
+        ess_unwhiten(U, self.L, self.mu, out, self.precision, self.stream)
+        return out
+
+
 def _same_device(a, b):
     import torch
     a, b = torch.device(a), torch.device(b)
@@ -270,7 +333,7 @@ class Sampler:
     are copied to the device in the working precision before ess_init."""
 
     def __init__(self, A, b, x0, n_chains, seed=0, precision=32, trim_eps=None,
-                 device="cuda", stream=None, full_sort=False, eager=False):
+                 device="cuda", stream=None, full_sort=False, eager=False, method="alg3"):
         import torch
         self.torch = torch
         self.dtype = torch.float32 if precision == 32 else torch.float64
@@ -290,6 +353,10 @@ class Sampler:
             flags |= ESS_PER_CHAIN_B
         if eager:
             flags |= ESS_EAGER
+        if method == "midpoint":    # Section 3.1's likelihood testing (comparator)
+            flags |= ESS_LIKELIHOOD_MIDPOINT
+        elif method != "alg3":
+            raise ValueError("method must be 'alg3' or 'midpoint'")
         if trim_eps is None:
             trim_eps = 1e-6 if precision == 32 else 0.0
         self.trim_eps = float(trim_eps)

@@ -30,6 +30,7 @@
 #include "sample.hpp"
 #include "batched.hpp"
 #include "mlp.hpp"
+#include "gauss.hpp"
 
 using namespace ess;
 
@@ -348,6 +349,10 @@ template <typename T>
 void launch_sample_t(const ess_ctx* c, const Group& g, hipStream_t st, const SampleArgs& a) {
     const dim3 grid(g.n), b(256), b2(512);
     const int rpt = (c->m + 255) / 256;
+    if (c->flags & ESS_LIKELIHOOD_MIDPOINT) {
+        hipLaunchKernelGGL((sample_midpoint_kernel<T>), grid, b, 0, st, a);
+        return;
+    }
     const dim3 fg(a.force_full ? std::min(g.n, 768) : std::min(g.n, 32));
     if (c->m > 4096) {
         // rows in chunks of 4096 per pass; the full sort keeps keys only
@@ -1293,6 +1298,9 @@ ess_status ess_init(const ess_problem* pr, void* stream, ess_ctx** out) {
     if (pr->m > kMaxRowsLarge)
         return fail(ESS_ERR_UNSUPPORTED, "m = %d exceeds the %d rows one workgroup sorts", pr->m,
                     kMaxRowsLarge);
+    if ((pr->flags & ESS_LIKELIHOOD_MIDPOINT) && pr->m > kMidpointMaxRows)
+        return fail(ESS_ERR_UNSUPPORTED, "likelihood testing takes m <= %d (got %d)",
+                    kMidpointMaxRows, pr->m);
     if (pr->d > (1 << 20) || pr->n_chains > (1 << 24))
         return fail(ESS_ERR_UNSUPPORTED, "d or n_chains too large");
 
@@ -1551,8 +1559,9 @@ ess_status ess_init_batched(const ess_problem* pr, int32_t n_problems, void* str
             return fail(ESS_ERR_INVALID_ARG, "problem %d: trim_eps must lie in [0, 1]", p);
         if (q.m > 4096) return fail(ESS_ERR_UNSUPPORTED, "problem %d: m = %d exceeds 4096", p, q.m);
         if (q.d > (1 << 20)) return fail(ESS_ERR_UNSUPPORTED, "problem %d: d too large", p);
-        if (q.flags & ESS_SORT_FULL)
-            return fail(ESS_ERR_UNSUPPORTED, "problem %d: ESS_SORT_FULL is not offered for batches", p);
+        if (q.flags & (ESS_SORT_FULL | ESS_LIKELIHOOD_MIDPOINT))
+            return fail(ESS_ERR_UNSUPPORTED,
+                        "problem %d: ESS_SORT_FULL and ESS_LIKELIHOOD_MIDPOINT are not offered for batches", p);
         total_chains += q.n_chains;
     }
     if (total_chains > (1 << 24)) return fail(ESS_ERR_UNSUPPORTED, "too many chains in the batch");
@@ -1631,6 +1640,83 @@ ess_status ess_set_state_gated(ess_ctx* c, const void* x_candidate, const void* 
         for (int i = 0; i < c->C; ++i) accepted[i] = acc[i];
     ESS_TRY(launch_step_counter(c, c->st, step, 0));
     c->step = step;
+    return ESS_OK;
+}
+
+// ---- Appendix A: non-standard normal front end ----
+
+ess_status ess_cholesky(const double* sigma, int32_t d, double* L) {
+    g_err.clear();
+    if (!sigma || !L || d < 1) return fail(ESS_ERR_INVALID_ARG, "need sigma, L and d >= 1");
+    const size_t n = static_cast<size_t>(d);
+    std::vector<double> out(n * n, 0.0);
+    for (size_t j = 0; j < n; ++j) {
+        double s = sigma[j * n + j];
+        for (size_t k = 0; k < j; ++k) s -= out[j * n + k] * out[j * n + k];
+        if (!(s > 0.0))
+            return fail(ESS_ERR_INVALID_ARG, "sigma is not positive definite (pivot %zu is %g)", j, s);
+        const double ljj = std::sqrt(s);
+        out[j * n + j] = ljj;
+        for (size_t i = j + 1; i < n; ++i) {
+            double t = sigma[i * n + j];
+            for (size_t k = 0; k < j; ++k) t -= out[i * n + k] * out[j * n + k];
+            out[i * n + j] = t / ljj;
+        }
+    }
+    std::memcpy(L, out.data(), sizeof(double) * n * n);
+    return ESS_OK;
+}
+
+ess_status ess_whiten(const void* A, const double* b, const double* L, const double* mu, int32_t m,
+                      int32_t d, int32_t precision, void* A_out, double* b_out, void* stream) {
+    g_err.clear();
+    if (!A || !b || !L || !mu || !A_out || !b_out)
+        return fail(ESS_ERR_INVALID_ARG, "null argument to ess_whiten");
+    if (m < 1 || d < 1) return fail(ESS_ERR_INVALID_ARG, "m and d must be >= 1 (got %d, %d)", m, d);
+    if (precision != 32 && precision != 64)
+        return fail(ESS_ERR_INVALID_ARG, "precision must be 32 or 64 (got %d)", precision);
+    if (A_out == A) return fail(ESS_ERR_INVALID_ARG, "A_out must not alias A");
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    const long long tiles = static_cast<long long>((d + 15) / 16) * ((m + 15) / 16);
+    if (tiles > (1ll << 31) - 1) return fail(ESS_ERR_UNSUPPORTED, "A too large for one launch");
+    const dim3 g(static_cast<unsigned>(tiles)), blk(256);
+    if (precision == 32) {
+        hipLaunchKernelGGL((gemm_tiled_f64<float, float>), g, blk, 0, st, static_cast<const float*>(A), L,
+                           m, d, d, 0, nullptr, static_cast<float*>(A_out));
+        hipLaunchKernelGGL((shift_rhs<float>), dim3((m + 3) / 4), blk, 0, st, static_cast<const float*>(A),
+                           b, mu, m, d, b_out);
+    } else {
+        hipLaunchKernelGGL((gemm_tiled_f64<double, double>), g, blk, 0, st, static_cast<const double*>(A),
+                           L, m, d, d, 0, nullptr, static_cast<double*>(A_out));
+        hipLaunchKernelGGL((shift_rhs<double>), dim3((m + 3) / 4), blk, 0, st,
+                           static_cast<const double*>(A), b, mu, m, d, b_out);
+    }
+    HIP_TRY(hipGetLastError());
+    return ESS_OK;
+}
+
+ess_status ess_unwhiten(const void* U, int64_t n, int32_t d, const double* L, const double* mu,
+                        int32_t precision, void* X_out, void* stream) {
+    g_err.clear();
+    if (!U || !L || !mu || !X_out) return fail(ESS_ERR_INVALID_ARG, "null argument to ess_unwhiten");
+    if (n < 1 || d < 1 || n > (1ll << 31) - 16)
+        return fail(ESS_ERR_INVALID_ARG, "need 1 <= n < 2^31 and d >= 1 (got %lld, %d)",
+                    static_cast<long long>(n), d);
+    if (precision != 32 && precision != 64)
+        return fail(ESS_ERR_INVALID_ARG, "precision must be 32 or 64 (got %d)", precision);
+    if (X_out == U) return fail(ESS_ERR_INVALID_ARG, "X_out must not alias U");
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    const int rows = static_cast<int>(n);
+    const long long tiles = static_cast<long long>((d + 15) / 16) * ((rows + 15) / 16);
+    if (tiles > (1ll << 31) - 1) return fail(ESS_ERR_UNSUPPORTED, "too many rows for one launch");
+    const dim3 g(static_cast<unsigned>(tiles)), blk(256);
+    if (precision == 32)
+        hipLaunchKernelGGL((gemm_tiled_f64<float, float>), g, blk, 0, st, static_cast<const float*>(U), L,
+                           rows, d, d, 1, mu, static_cast<float*>(X_out));
+    else
+        hipLaunchKernelGGL((gemm_tiled_f64<double, double>), g, blk, 0, st, static_cast<const double*>(U),
+                           L, rows, d, d, 1, mu, static_cast<double*>(X_out));
+    HIP_TRY(hipGetLastError());
     return ESS_OK;
 }
 

@@ -1139,6 +1139,195 @@ __global__ __launch_bounds__(BS, (BS == 512 && RPT <= 4 && !REFINE) ? 8 : 1) voi
     if (!done && threadIdx.x == 0) a.fb_list[atomicAdd(a.fb_count + (step & 1), 1)] = c;
 }
 
+// ---------------------------------------------------------------------------
+// Comparator: likelihood testing at midpoints (Section 3.1), O(m^2) per chain.
+// The 2n intersection angles of the n crossing rows are sorted (48-bit keys
+// carrying 2 row + end); each gap between consecutive angles, with 0 and
+// 2 pi as the outer ends, is active when x(theta) at its midpoint satisfies
+// all m constraints, tested from the cached projections.  Active gaps of
+// positive length are the active intervals: consecutive gaps share an angle
+// that is a crossing of some row, which is violated on one side, so two
+// active gaps never touch except across a gap of length zero (tied angles),
+// where this kernel keeps two pieces of the same set.
+// ---------------------------------------------------------------------------
+constexpr int kMidpointMaxRows = 4096;
+
+template <typename T>
+struct MidLds {
+    uint64_t key[2 * kMidpointMaxRows];   // sort keys, then the angles' bits
+    T p[kMidpointMaxRows], q[kMidpointMaxRows];
+    unsigned char ok[2 * kMidpointMaxRows + 1];
+    double red[4];
+    int cnt[4];
+    double bcast[2];
+    int kstar;
+    double theta;
+};
+
+template <typename T>
+__device__ void midpoint_chain(const ChainRef<T>& r, int sel, MidLds<T>& L) {
+    const int tid = threadIdx.x;
+    const T* Pc = r.P0 + static_cast<size_t>(sel) * r.pstride;
+    // roots, both angles of each crossing row as keys; p and q kept in LDS
+    int n = 0;
+    for (int i0 = 0; i0 < r.m; i0 += 256) {
+        const int i = i0 + tid;
+        double al = 0.0, be = 0.0;
+        bool hit = false;
+        if (i < r.m) {
+            const T p = Pc[i], q = r.q[i];
+            L.p[i] = p;
+            L.q[i] = q;
+            hit = solve_roots<T>(static_cast<double>(p), static_cast<double>(q), r.b[i], al, be);
+            if (r.p_out) {
+                r.p_out[i] = p;
+                r.q_out[i] = q;
+            }
+        }
+        int tot;
+        const int pos = block_count_prefix(hit, L.cnt, tot);
+        if (hit) {
+            L.key[n + 2 * pos] = sort_key(al, 2 * i);
+            L.key[n + 2 * pos + 1] = sort_key(be, 2 * i + 1);
+        }
+        n += 2 * tot;
+    }
+    int n2 = 512;
+    while (n2 < n) n2 <<= 1;
+    for (int k = n + tid; k < n2; k += 256) L.key[k] = ~0ull;
+    __syncthreads();
+    bitonic_sort_lds(L.key, n2);
+    // the exact angle of every key, in place of the key
+    for (int k = tid; k < n; k += 256) {
+        const int s = static_cast<int>(L.key[k] & 0xFFFF);
+        const int i = s >> 1;
+        double al, be;
+        solve_roots<T>(static_cast<double>(L.p[i]), static_cast<double>(L.q[i]), r.b[i], al, be);
+        L.key[k] = static_cast<uint64_t>(__double_as_longlong((s & 1) ? be : al));
+    }
+    __syncthreads();
+    auto ang = [&](int k) { return __longlong_as_double(static_cast<long long>(L.key[k])); };
+    // gap g runs from angle g - 1 (0 for g = 0) to angle g (2 pi for g = n)
+    auto gap = [&](int g, double& lo, double& hi) {
+        lo = g == 0 ? 0.0 : ang(g - 1);
+        hi = g == n ? kTwoPi : ang(g);
+    };
+    // the likelihood at every gap's midpoint: all m rows, no early exit
+    for (int g = tid; g <= n; g += 256) {
+        double lo, hi;
+        gap(g, lo, hi);
+        bool ok = false;
+        if (hi > lo) {
+            double sm, cm;
+            sincos(0.5 * (lo + hi), &sm, &cm);
+            bool inside = true;
+            for (int i = 0; i < r.m; ++i)
+                inside &= static_cast<double>(L.p[i]) * cm + static_cast<double>(L.q[i]) * sm <= r.b[i];
+            ok = inside;
+        }
+        L.ok[g] = ok ? 1 : 0;
+    }
+    if (tid == 0) L.kstar = 0x7FFFFFFF;
+    __syncthreads();
+
+    // inverse CDF over the active gaps in ascending order (trimmed at real
+    // ends), each thread a contiguous range of gaps
+    const double eps = r.eps;
+    const int per = (n + 1 + 255) / 256;
+    const int g0 = tid * per, g1 = min(g0 + per, n + 1);
+    auto piece = [&](int g, double& lo, double& hi) {
+        gap(g, lo, hi);
+        if (!L.ok[g]) {
+            hi = lo;
+            return;
+        }
+        if (lo > 0.0) lo += eps;
+        if (hi < kTwoPi) hi -= eps;
+    };
+    double tsum = 0.0;
+    for (int g = g0; g < g1; ++g) {
+        double lo, hi;
+        piece(g, lo, hi);
+        tsum += fmax(hi - lo, 0.0);
+    }
+    const double s_in = block_excl_scan(tsum, 0.0, SumOp(), L.red);
+    if (tid == 255) L.bcast[0] = s_in + tsum;
+    __syncthreads();
+    const double total = L.bcast[0];
+    const double sv = theta_uniform(r) * total;
+    double my_theta = 0.0, last_hi = 0.0;
+    int my_g = 0x7FFFFFFF, last_g = -1;
+    if (total > 0.0) {
+        double run = s_in;
+        for (int g = g0; g < g1; ++g) {
+            double lo, hi;
+            piece(g, lo, hi);
+            const double len = fmax(hi - lo, 0.0);
+            if (len > 0.0) {
+                if (my_g == 0x7FFFFFFF && run + len > sv) {
+                    my_g = g;
+                    my_theta = fmax(lo, fmin(lo + (sv - run), hi));
+                }
+                last_g = g;
+                last_hi = hi;
+            }
+            run += len;
+        }
+        if (my_g != 0x7FFFFFFF) atomicMin(&L.kstar, my_g);
+    }
+    __syncthreads();
+    const int kstar = L.kstar;
+    __syncthreads();   // every thread has read kstar before it is reused
+    if (total > 0.0) {
+        if (kstar == 0x7FFFFFFF) {
+            // s rounded up to the total: the upper end of the last piece
+            if (tid == 0) L.kstar = -1;
+            __syncthreads();
+            if (last_g >= 0) atomicMax(&L.kstar, last_g);
+            __syncthreads();
+            if (last_g >= 0 && last_g == L.kstar) L.theta = last_hi;
+        } else if (my_g == kstar) {
+            L.theta = my_theta;
+        }
+    } else if (tid == 0) {
+        L.theta = 0.0;
+        *r.flag = 1;   // empty active set: stay, counted as a rejection
+    }
+
+    // optional: the active trimmed pieces, ascending
+    if (r.intervals) {
+        int cnt = 0;
+        for (int g = g0; g < g1; ++g) {
+            double lo, hi;
+            piece(g, lo, hi);
+            cnt += (hi - lo > 0.0);
+        }
+        const double base = block_excl_scan(static_cast<double>(cnt), 0.0, SumOp(), L.red);
+        int w = static_cast<int>(base);
+        for (int g = g0; g < g1; ++g) {
+            double lo, hi;
+            piece(g, lo, hi);
+            if (hi - lo > 0.0) {
+                r.intervals[2 * w] = lo;
+                r.intervals[2 * w + 1] = hi;
+                ++w;
+            }
+        }
+        if (tid == 255 && r.n_intervals) *r.n_intervals = w;
+    }
+    __syncthreads();
+    move_chain<T>(r, L.theta);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void sample_midpoint_kernel(SampleArgs a) {
+    __shared__ MidLds<T> lds;
+    const int c = a.c0 + blockIdx.x;
+    const ChainRef<T> r = make_ref<T>(a, c);
+    const int sel = a.has_pending ? commit_chain<T>(r) : *r.sel;
+    midpoint_chain<T>(r, sel, lds);
+}
+
 // Rows beyond 4096: 512 threads per chain, the chunked bucket path with
 // refinement; chains it cannot resolve go to the full sort of keys only.
 constexpr int kMaxRowsLarge = 16384;

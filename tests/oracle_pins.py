@@ -424,6 +424,32 @@ def pin_exp1_table(n_chains=400, n_steps=150, burn=30):
     return fails
 
 
+def pin_appendix_a_truncnorm(n_chains=400, n_steps=150, burn=30):
+    """Appendix A's change of variables: N(1, 2^2) truncated to [0, 3], sampled
+    as u ~ N(0, 1) on the whitened interval and mapped back, matches the
+    truncated normal's mean and variance (scipy.stats.truncnorm)."""
+    from scipy import stats
+    mu, sd, lo, hi = 1.0, 2.0, 0.0, 3.0
+    A = np.array([[1.0], [-1.0]])
+    b = np.array([hi, -lo])
+    L = np.array([[sd]])
+    Aw, bw = ess.whiten(A, b, np.array([mu]), L)
+    trace, _, _ = ess.run(Aw, bw, np.zeros(1), n_chains, n_steps, seed=31)
+    x = ess.unwhiten(trace[burn:].reshape(-1, 1), L, np.array([mu]))[:, 0]
+    ref = stats.truncnorm((lo - mu) / sd, (hi - mu) / sd, loc=mu, scale=sd)
+    fails = []
+    # chains are independent; steps within a chain are close to independent
+    # here, and the bounds allow a few standard errors
+    se = math.sqrt(ref.var() / (n_chains * 20))
+    if abs(x.mean() - ref.mean()) > 5 * se:
+        fails.append(f"mean {x.mean():.4f} vs {ref.mean():.4f}")
+    if abs(x.var() - ref.var()) > 0.05 * ref.var():
+        fails.append(f"variance {x.var():.4f} vs {ref.var():.4f}")
+    if x.min() < lo - 1e-12 or x.max() > hi + 1e-12:
+        fails.append("sample outside [0, 3]")
+    return fails
+
+
 def pin_rejection_sampling_reference(seed=19, n_chains=200, n_steps=100, burn=20):
     """A small polytope where plain rejection sampling from N(0, I) is exact:
     the chain's mean matches the i.i.d. reference within Monte Carlo error."""
@@ -445,4 +471,5 @@ FAST_PINS = [pin_fig1, pin_fig2, pin_root_residual, pin_rotation_covariance,
              pin_alg3_equals_alg2, pin_midpoint_equals_alg2, pin_dense_grid, pin_appendix_d,
              pin_sorting_reduction,
              pin_theta_uniform, pin_philox_kat, pin_box_muller]
-CHAIN_PINS = [pin_chain_box_moments, pin_exp1_table, pin_rejection_sampling_reference]
+CHAIN_PINS = [pin_chain_box_moments, pin_exp1_table, pin_rejection_sampling_reference,
+              pin_appendix_a_truncnorm]

@@ -332,17 +332,19 @@ def arcs_problem(alpha, beta):
     return A, np.cos(phi)
 
 
-def run_arcs(E, alpha, beta, precision, full_sort=False, C=8):
+def run_arcs(E, alpha, beta, precision, full_sort=False, C=8, method="alg3"):
     A, b = arcs_problem(alpha, beta)
     npdt = np.float32 if precision == 32 else np.float64
     x = np.tile(np.array([1.0, 0.0], npdt), (C, 1))
     nu = np.tile(np.array([0.0, 1.0], npdt), (C, 1))
     u = (np.arange(C) + 0.5) / C
-    s = E.Sampler(A, b, x, C, seed=0, precision=precision, trim_eps=0.0, full_sort=full_sort)
+    s = E.Sampler(A, b, x, C, seed=0, precision=precision, trim_eps=0.0, full_sort=full_sort,
+                  method=method)
     g = {k: v.cpu().numpy() for k, v in s.transition_explicit(x, nu, u).items()}
     s.close()
     Ab = A.astype(npdt).astype(np.float64)
-    ref = ref_ess.transition(Ab, b, x.astype(np.float64), nu.astype(np.float64), u, store=npdt)
+    ref = ref_ess.transition(Ab, b, x.astype(np.float64), nu.astype(np.float64), u, store=npdt,
+                             method=method)
     return Ab, b, x.astype(np.float64), nu, u, g, ref
 
 
@@ -481,6 +483,61 @@ def test_section_4_2_at_d_8000(E):
     say("coarse survivors", coarse_survivors(ref["alpha"], ref["beta"]))
     g = assert_same_as_full_sort(E, pr.A, pr.b, x, nu, u, 32, 1e-6)
     fails, _ = compare_transition(Ab, pr.b, x.astype(np.float64), nu, u, g, ref)
+    assert not fails, fails[:5]
+
+
+MID_CASES = [
+    # name, d, m, C, precision, eps
+    ("mid_ragged_f32", 37, 150, 40, 32, 1e-6),
+    ("mid_f64", 20, 300, 16, 64, 0.0),
+    ("mid_m2000_f32", 40, 2000, 8, 32, 1e-6),
+    ("mid_max_m_f32", 30, 4096, 3, 32, 1e-6),
+]
+
+
+@pytest.mark.parametrize("name,d,m,C,precision,eps", MID_CASES, ids=[c[0] for c in MID_CASES])
+def test_midpoint_comparator_matches_oracle_and_alg3(E, name, d, m, C, precision, eps):
+    """Section 3.1's likelihood testing at midpoints (the quadratic
+    comparator) finds the same pieces as Algorithm 3 from the same
+    projections, and agrees with the oracle's midpoint method."""
+    say(f"[midpoint] {name} d={d} m={m} C={C} prec={precision}")
+    rng = np.random.default_rng(d * 5 + m)
+    A = rng.standard_normal((m, d)) / math.sqrt(d)
+    b = rng.uniform(0.5, 1.5, m)
+    npdt = np.float32 if precision == 32 else np.float64
+    x = synth.random_states(rng, A, b, C, scale=0.7, margin=1e-3).astype(npdt)
+    nu = rng.standard_normal(x.shape).astype(npdt)
+    u = rng.uniform(size=C)
+    outs = {}
+    for method in ("alg3", "midpoint"):
+        s = E.Sampler(A, b, x, C, seed=5, precision=precision, trim_eps=eps, method=method)
+        outs[method] = {k: v.cpu().numpy() for k, v in s.transition_explicit(x, nu, u).items()}
+        s.close()
+    a, g = outs["alg3"], outs["midpoint"]
+    assert np.array_equal(a["n_intervals"], g["n_intervals"])
+    assert np.abs(a["intervals"] - g["intervals"]).max() <= 1e-13
+    assert np.abs(a["theta"] - g["theta"]).max() <= 1e-12
+    assert np.array_equal(a["rejected"], g["rejected"])
+    Ab = A.astype(npdt).astype(np.float64)
+    ref = ref_ess.transition(Ab, b, x.astype(np.float64), nu.astype(np.float64), u, eps=eps,
+                             store=npdt, pq=(g["pq"][0], g["pq"][1]), method="midpoint")
+    # the root solve's rounding bounds the rest, as in the Algorithm 3 parity
+    # cases: float64 trig in float64 mode, float32 trig away from tangency
+    tol2 = 1e-9 if precision == 64 else 1e-5
+    for c in range(C):
+        gi = pieces(g["intervals"][c], g["n_intervals"][c], 0.0)
+        assert intervals_match(gi, ref["intervals"][c], tol2), (c, gi, ref["intervals"][c])
+        assert abs(g["theta"][c] - ref["theta"][c]) <= tol2 * max(1.0, len(gi)), c
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_midpoint_comparator_on_the_sorting_reduction(E, precision):
+    """Section 3.1's reduction (100 disjoint arcs) through the comparator."""
+    rng = np.random.default_rng(23)
+    c = 0.1 + 5.9 * (np.arange(100) + rng.uniform(0.2, 0.4, 100)) / 100
+    Ab, b, x, nu, u, g, ref = run_arcs(E, c, c + 0.005, precision, method="midpoint")
+    assert (g["n_intervals"] == 101).all(), g["n_intervals"]
+    fails, _ = compare_transition(Ab, b, x, nu, u, g, ref)
     assert not fails, fails[:5]
 
 

@@ -5,7 +5,8 @@ paper: a flipped sign or swapped argument in the root formula, a missing
 cumulative max, an off-by-one in gamma, a wrong interpolation in the inverse
 CDF, swapped ellipse terms, an inverted safeguard, a wrong Philox constant,
 a likelihood test that reads one row or swaps inside and outside, a gap
-tested at its end instead of its middle.
+tested at its end instead of its middle, a change of variables with the
+wrong sign of A mu or without the mean.
 """
 import numpy as np
 import pytest
@@ -118,6 +119,15 @@ def _midpoint_tests_lower_end(p, q, b):
     return out
 
 
+def _whiten_shift_sign(A, b, mu, L):
+    A = np.asarray(A, float)
+    return A @ np.asarray(L, float), np.asarray(b, float) + A @ np.asarray(mu, float)   # + A mu
+
+
+def _unwhiten_no_mean(U, L, mu):
+    return np.asarray(U, float) @ np.asarray(L, float).T                               # forgot + mu
+
+
 ORIG = {"roots": ess.roots, "alg3_candidates": ess.alg3_candidates,
         "transition": ess.transition, "philox4x32_10": philox.philox4x32_10}
 
@@ -136,6 +146,8 @@ MUTATIONS = [
     (ess, "likelihood", _likelihood_first_row_only),
     (ess, "likelihood", _likelihood_strict_reversed),
     (ess, "midpoint_intervals", _midpoint_tests_lower_end),
+    (ess, "whiten", _whiten_shift_sign),
+    (ess, "unwhiten", _unwhiten_no_mean),
 ]
 
 
