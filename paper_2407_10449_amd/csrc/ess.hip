@@ -103,6 +103,7 @@ struct ess_ctx {
     int* flag = nullptr;
     long long* rej = nullptr;
     int* fb_list = nullptr;    // chains handed to the full-sort path
+    void* AB = nullptr;        // [Cp][mp] double2: alpha, beta of every row (m > 4096)
     int* fb_count = nullptr;   // [2 per group]: list lengths by step parity
     int* accepted = nullptr;   // [Cp]: gated starts taken
     uint32_t* d_step = nullptr;   // device copy of the step counter, read by the kernels
@@ -340,6 +341,7 @@ SampleArgs sample_args(const ess_ctx* c, const Group& g, int gi) {
     a.fb_count = c->fb_count + 2 * gi;
     a.step_base = c->d_step;
     a.force_full = (c->flags & ESS_SORT_FULL) ? 1 : 0;
+    a.ab = c->AB;
     return a;
 }
 
@@ -1371,7 +1373,9 @@ ess_status ess_init(const ess_problem* pr, void* stream, ess_ctx** out) {
         (s = dalloc(c, reinterpret_cast<void**>(&c->accepted), sizeof(int) * c->Cp)) != ESS_OK ||
         (s = dalloc(c, reinterpret_cast<void**>(&c->d_step), sizeof(uint32_t))) != ESS_OK ||
         (s = create_run_streams(c)) != ESS_OK ||
-        (s = dalloc(c, reinterpret_cast<void**>(&c->fb_count), sizeof(int) * 2 * kMaxGroups)) != ESS_OK)
+        (s = dalloc(c, reinterpret_cast<void**>(&c->fb_count), sizeof(int) * 2 * kMaxGroups)) != ESS_OK ||
+        (c->m > 4096 &&
+         (s = dalloc(c, &c->AB, 2 * sizeof(double) * static_cast<size_t>(c->Cp) * c->mp)) != ESS_OK))
         return bail(s);
     {
         // every group stream and event exists from the start: the autotuner and

@@ -77,6 +77,7 @@ struct SampleArgs {
     int* fb_list;         // [C]: chains handed to the full path this step
     int* fb_count;        // [2]: list length, indexed by step parity
     int force_full;       // 1: every chain takes the full path
+    void* ab;             // more than 4096 rows: [Cp][mp] double2, alpha and beta per row
 };
 
 __device__ __forceinline__ uint32_t abs_step(const SampleArgs& a) {
@@ -1015,13 +1016,29 @@ __device__ bool bucket_chain(const ChainRef<T>& r, int sel, BucketLds<NB>& L) {
     return true;
 }
 
+// alpha, beta of rows row0 + tid + BS j kept by this thread in the first pass
+// (beta = 0: no crossing, or past m).  Each thread reads back only what it
+// wrote itself.
+template <int RPT, int BS>
+__device__ __forceinline__ void block_ab(const double2* ab, int row0, int m, double (&al)[RPT],
+                                         double (&be)[RPT]) {
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int i = row0 + static_cast<int>(threadIdx.x) + BS * j;
+        const double2 v = i < m ? ab[i] : make_double2(0.0, 0.0);
+        al[j] = v.x;
+        be[j] = v.y;
+    }
+}
+
 // Rows beyond what one pass holds in registers (m > BS RPT): the same bucket
-// path with refinement, each pass over the rows in chunks of BS RPT whose
-// roots are solved again (three passes, plus three per refinement level).
-// The roots depend only on the row, so every pass sees the same alpha and
-// beta.  Returns false, with nothing moved, as bucket_chain does.
+// path with refinement, each pass over the rows in chunks of BS RPT.  The
+// first pass solves the roots and keeps alpha and beta of every row in `ab`
+// (16 bytes per row, read back by the same thread in the later passes: three,
+// plus three per refinement level).  Returns false, with nothing moved, as
+// bucket_chain does.
 template <typename T, int RPT, int NB, int BS>
-__device__ bool bucket_chain_large(const ChainRef<T>& r, int sel, BucketLds<NB>& L) {
+__device__ bool bucket_chain_large(const ChainRef<T>& r, int sel, BucketLds<NB>& L, double2* ab) {
     const int tid = threadIdx.x;
     constexpr int CH = BS * RPT;
     for (int b = tid; b < NB; b += BS) {
@@ -1036,12 +1053,17 @@ __device__ bool bucket_chain_large(const ChainRef<T>& r, int sel, BucketLds<NB>&
     R.n = 0;
     for (int c0 = 0; c0 < r.m; c0 += CH) {
         block_roots<T, RPT, BS>(r, Pc, c0, true, al, be);
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            const int i = c0 + tid + BS * j;
+            if (i < r.m) ab[i] = make_double2(al[j], be[j]);
+        }
         bucket_max_pass<RPT, NB>(L, R, al, be);
     }
     bucket_prefix_max<NB, BS>(L, 0.0, true);
     int S = 0;
     for (int c0 = 0; c0 < r.m; c0 += CH) {
-        block_roots<T, RPT, BS>(r, Pc, c0, false, al, be);
+        block_ab<RPT, BS>(ab, c0, r.m, al, be);
         S = find_survivors<RPT, NB, BS>(L, R, al, be, c0);
     }
     int s_prev = 1 << 30;
@@ -1057,7 +1079,7 @@ __device__ bool bucket_chain_large(const ChainRef<T>& r, int sel, BucketLds<NB>&
         }
         __syncthreads();
         for (int c0 = 0; c0 < r.m; c0 += CH) {
-            block_roots<T, RPT, BS>(r, Pc, c0, false, al, be);
+            block_ab<RPT, BS>(ab, c0, r.m, al, be);
 #pragma unroll
             for (int j = 0; j < RPT; ++j) {
                 if (be[j] > 0.0) {
@@ -1107,19 +1129,19 @@ __device__ bool bucket_chain_large(const ChainRef<T>& r, int sel, BucketLds<NB>&
         if (tid == 0) L.scount = 0;
         __syncthreads();
         for (int c0 = 0; c0 < r.m; c0 += CH) {
-            block_roots<T, RPT, BS>(r, Pc, c0, false, al, be);
+            block_ab<RPT, BS>(ab, c0, r.m, al, be);
             bucket_max_pass<RPT, NB>(L, R, al, be);
         }
         bucket_prefix_max<NB, BS>(L, g0, false);
         for (int c0 = 0; c0 < r.m; c0 += CH) {
-            block_roots<T, RPT, BS>(r, Pc, c0, false, al, be);
+            block_ab<RPT, BS>(ab, c0, r.m, al, be);
             S = find_survivors<RPT, NB, BS>(L, R, al, be, c0);
         }
     }
     if (S > SMAX) return false;
     link_survivors<T, NB>(r, L, S);
     for (int c0 = 0; c0 < r.m; c0 += CH) {
-        block_roots<T, RPT, BS>(r, Pc, c0, false, al, be);
+        block_ab<RPT, BS>(ab, c0, r.m, al, be);
         pred_max_pass<RPT, NB, BS>(L, R, al, be, c0);
     }
     __syncthreads();
@@ -1340,7 +1362,8 @@ __global__ __launch_bounds__(512) void sample_large_kernel(SampleArgs a) {
     const int sel = a.has_pending ? commit_chain<T>(r) : *r.sel;
     const uint32_t step = r.step;
     if (blockIdx.x == 0 && threadIdx.x == 0) a.fb_count[(step + 1) & 1] = 0;   // next step's list
-    const bool done = !a.force_full && bucket_chain_large<T, 8, 2048, 512>(r, sel, lds);
+    double2* ab = static_cast<double2*>(a.ab) + static_cast<size_t>(c) * a.mp;
+    const bool done = !a.force_full && bucket_chain_large<T, 8, 2048, 512>(r, sel, lds, ab);
     if (!done && threadIdx.x == 0) a.fb_list[atomicAdd(a.fb_count + (step & 1), 1)] = c;
 }
 
