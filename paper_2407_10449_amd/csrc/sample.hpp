@@ -1,7 +1,7 @@
 // Per-chain part of one transition: commit the previous proposal, solve every
 // constraint's intersection angles, build the active intervals, draw theta,
-// move, and draw the next ellipse direction.  One 256-thread workgroup per
-// chain.
+// move, and draw the next ellipse direction.  One workgroup of 256 or 512
+// threads per chain.
 //
 // Roots (Appendix B): p = a_i^T x, q = a_i^T nu, r = hypot(p, q),
 // tau = atan2(q, p), phi = acos(b / r); the ellipse leaves the halfspace on the
@@ -31,14 +31,21 @@
 //   ("survivors", typically a handful) need their exact predecessor max inside
 //   their own bucket, found by comparing against the bucket's rows in float64.
 //   The survivors' candidates are then ranked by (alpha, row) and summed in
-//   ascending order.
+//   ascending order.  Crowded buckets are split again (refinement, below)
+//   in the kernels for few chains and in the second attempt on a chain.
 // * full path (fallback_kernel): a bitonic sort of all crossing rows in LDS,
-//   for chains with more than SMAX survivors (adversarial inputs such as many
-//   nested arcs in one bucket) or when the full sort is requested.  Keys are
+//   for chains whose survivors still exceed SMAX (adversarial inputs such as
+//   many disjoint arcs spread over the circle) or when the full sort is
+//   requested.  Keys are
 //   alpha mapped monotonically to a 48-bit fixed-point turn fraction
 //   floor(alpha * 2^48 / 2 pi) above a 16-bit slot index, so one 64-bit
 //   compare orders them; two alphas closer than 2 pi * 2^-48 (2.2e-14 rad)
 //   may swap, which moves the union by at most their distance.
+//
+// More than 4096 rows (up to 16384) take the same two paths with every pass
+// over the rows made in chunks (sample_large_kernel, fallback_large_kernel).
+// The quadratic comparator of Section 3.1 (likelihood testing at midpoints)
+// sits beside them (sample_midpoint_kernel).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
