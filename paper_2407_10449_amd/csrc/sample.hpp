@@ -298,15 +298,23 @@ __device__ __forceinline__ int commit_chain(const ChainRef<T>& r) {
         *r.flag = 0;
         if (r.rejected_out) *r.rejected_out = fl;
     }
-    for (int k = threadIdx.x; k < r.d; k += blockDim.x) {
-        T v;
-        if (!fl) {
-            v = r.xp[k];
-            r.x[k] = v;
-        } else {
-            v = r.x[k];
+    // four elements per thread and pass, all loaded before any store (the
+    // stores may alias the loads for the compiler, which would otherwise wait
+    // for memory once per element); a load past d reads element d - 1
+    const T* src = fl ? r.x : r.xp;
+    const int nt = static_cast<int>(blockDim.x);
+    for (int k0 = threadIdx.x; k0 < r.d; k0 += 4 * nt) {
+        T v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = src[min(k0 + u * nt, r.d - 1)];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = k0 + u * nt;
+            if (k < r.d) {
+                if (!fl) r.x[k] = v[u];
+                if (r.trace) r.trace[k] = v[u];
+            }
         }
-        if (r.trace) r.trace[k] = v;
     }
     return snew;
 }
@@ -349,7 +357,24 @@ __device__ __forceinline__ void move_chain(const ChainRef<T>& r, double theta) {
     double sd, cd;
     sincos(theta, &sd, &cd);
     const T ct = static_cast<T>(cd), st = static_cast<T>(sd);
-    for (int k = threadIdx.x; k < r.d; k += blockDim.x) r.xp[k] = r.x[k] * ct + r.nu[k] * st;
+    // loads of four elements per thread before their stores, as in the commit
+    const int nt = static_cast<int>(blockDim.x);
+    for (int k0 = threadIdx.x; k0 < r.d; k0 += 4 * nt) {
+        T xv[4], nv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = min(k0 + u * nt, r.d - 1);
+            xv[u] = r.x[k];
+            nv[u] = r.nu[k];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = k0 + u * nt;
+            // one explicit contraction, so that every kernel that moves a
+            // chain rounds it the same way
+            if (k < r.d) r.xp[k] = fma(xv[u], ct, nv[u] * st);
+        }
+    }
     if (r.gen_next) {
         __syncthreads();   // every read of this step's nu is done
         const Rng rng(r.seed);
@@ -639,25 +664,36 @@ __device__ __forceinline__ int bucket_of(const RefineMap& R, double a) {
 
 // Roots of rows row0 + tid + BS j (j < RPT) of the chain; beta = 0 marks a
 // row past m or one the ellipse does not cross.  With `out`, the chain's p
-// and q of those rows go to the optional output.
+// and q of those rows go to the optional output.  Every row's p, q and b are
+// loaded before any root is solved (a row past m reads row m - 1), so the
+// thread waits for memory once instead of once per row behind the branches
+// of the root solve.
 template <typename T, int RPT, int BS>
 __device__ __forceinline__ void block_roots(const ChainRef<T>& r, const T* Pc, int row0, bool out,
                                             double (&al)[RPT], double (&be)[RPT]) {
+    T pv[RPT], qv[RPT];
+    double bv[RPT];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int i = min(row0 + static_cast<int>(threadIdx.x) + BS * j, r.m - 1);
+        pv[j] = Pc[i];
+        qv[j] = r.q[i];
+        bv[j] = r.b[i];
+    }
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
         const int i = row0 + static_cast<int>(threadIdx.x) + BS * j;
         al[j] = 0.0;
         be[j] = 0.0;
         if (i < r.m) {
-            const T p = Pc[i], q = r.q[i];
             double x0, x1;
-            if (solve_roots<T>(static_cast<double>(p), static_cast<double>(q), r.b[i], x0, x1)) {
+            if (solve_roots<T>(static_cast<double>(pv[j]), static_cast<double>(qv[j]), bv[j], x0, x1)) {
                 al[j] = x0;
                 be[j] = x1;
             }
             if (out && r.p_out) {
-                r.p_out[i] = p;
-                r.q_out[i] = q;
+                r.p_out[i] = pv[j];
+                r.q_out[i] = qv[j];
             }
         }
     }
@@ -921,24 +957,7 @@ __device__ bool bucket_chain(const ChainRef<T>& r, int sel, BucketLds<NB>& L) {
     // roots of this thread's rows (row i = tid + BS r); beta = 0 marks no crossing
     const T* Pc = r.P0 + static_cast<size_t>(sel) * r.pstride;
     double al[RPT], be[RPT];
-#pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-        const int i = tid + BS * j;
-        al[j] = 0.0;
-        be[j] = 0.0;
-        if (i < r.m) {
-            const T p = Pc[i], q = r.q[i];
-            double x0, x1;
-            if (solve_roots<T>(static_cast<double>(p), static_cast<double>(q), r.b[i], x0, x1)) {
-                al[j] = x0;
-                be[j] = x1;
-            }
-            if (r.p_out) {
-                r.p_out[i] = p;
-                r.q_out[i] = q;
-            }
-        }
-    }
+    block_roots<T, RPT, BS>(r, Pc, 0, true, al, be);
     __syncthreads();
     RefineMap R;
     R.n = 0;
