@@ -541,6 +541,27 @@ def test_midpoint_comparator_on_the_sorting_reduction(E, precision):
     assert not fails, fails[:5]
 
 
+@pytest.mark.parametrize("method,m", [("midpoint", 300), ("alg3", 6000)])
+def test_per_chain_b_on_the_comparator_and_the_large_path(E, method, m):
+    """One right-hand side per chain (ESS_PER_CHAIN_B) through the quadratic
+    comparator and through the chunked path beyond 4096 rows."""
+    rng = np.random.default_rng(m + 3)
+    d, C = 25, 6
+    A = rng.standard_normal((m, d)) / math.sqrt(d)
+    b = rng.uniform(0.5, 1.5, (C, m))
+    x = np.zeros((C, d), np.float32)
+    nu = rng.standard_normal(x.shape).astype(np.float32)
+    u = rng.uniform(size=C)
+    s = E.Sampler(A, b, x, C, seed=4, precision=32, trim_eps=1e-6, method=method)
+    g = {k: v.cpu().numpy() for k, v in s.transition_explicit(x, nu, u).items()}
+    s.close()
+    Ab = A.astype(np.float32).astype(np.float64)
+    ref = ref_ess.transition(Ab, b, x.astype(np.float64), nu.astype(np.float64), u, eps=1e-6,
+                             store=np.float32, method=method)
+    fails, _ = compare_transition(Ab, b, x.astype(np.float64), nu, u, g, ref)
+    assert not fails, fails[:5]
+
+
 def test_two_refinement_levels(E):
     """600 rows whose alphas lie within 6e-7 rad (one bucket, and still one
     sub-bucket after the first split) and whose arcs overlap: two levels of
