@@ -373,11 +373,14 @@ void launch_sample_t(const ess_ctx* c, const Group& g, hipStream_t st, const Sam
     // Few chains also take 512 threads at every m: the phases are latency-bound
     // and halving the rows per thread shortens them (one chain at m = 1000:
     // 22 -> 16 us).
+    // These kernels also sort an unresolved chain in place, so no second
+    // launch follows them.
     if (g.n <= 256) {
         if (rpt <= 2) hipLaunchKernelGGL((sample_bucket_kernel<T, 1, 2048, 512, true>), grid, b2, 0, st, a);
         else if (rpt <= 4) hipLaunchKernelGGL((sample_bucket_kernel<T, 2, 2048, 512, true>), grid, b2, 0, st, a);
         else if (rpt <= 8) hipLaunchKernelGGL((sample_bucket_kernel<T, 4, 2048, 512, true>), grid, b2, 0, st, a);
         else hipLaunchKernelGGL((sample_bucket_kernel<T, 8, 2048, 512, true>), grid, b2, 0, st, a);
+        return;
     } else if (rpt <= 1) {
         hipLaunchKernelGGL((sample_bucket_kernel<T, 1, 256>), grid, b, 0, st, a);
     } else if (rpt <= 2) {

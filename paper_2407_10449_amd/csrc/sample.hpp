@@ -154,6 +154,7 @@ __device__ __forceinline__ double ofloat(unsigned long long v) {
 }
 
 // ---- block-wide helpers (256 threads = 4 waves of 64) ----
+template <int NW = 4>
 __device__ __forceinline__ int block_count_prefix(bool pred, int* s_w, int& total) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const unsigned long long mask = __ballot(pred);
@@ -162,7 +163,7 @@ __device__ __forceinline__ int block_count_prefix(bool pred, int* s_w, int& tota
     __syncthreads();
     int off = 0, tot = 0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < NW; ++i) {
         const int cnt = s_w[i];
         off += (i < w) ? cnt : 0;
         tot += cnt;
@@ -202,11 +203,12 @@ __device__ __forceinline__ double block_excl_scan(double v, double id, Op op, do
     return (lane == 0) ? pre : op(pre, ex);
 }
 
-// Ascending bitonic sort of key[0 .. n2), n2 a power of two >= 512.
+// Ascending bitonic sort of key[0 .. n2), n2 a power of two >= 512, by BS threads.
+template <int BS = 256>
 __device__ __forceinline__ void bitonic_sort_lds(uint64_t* key, int n2) {
     for (int k = 2; k <= n2; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int t = threadIdx.x; t < (n2 >> 1); t += 256) {
+            for (int t = threadIdx.x; t < (n2 >> 1); t += BS) {
                 const int lo = ((t & ~(j - 1)) << 1) | (t & (j - 1));
                 const int hi = lo | j;
                 const bool up = (lo & k) == 0;
@@ -394,8 +396,8 @@ struct FullLds {
     double* alpha;
     double* beta;
     uint64_t* key;
-    double* red;      // [4]
-    int* cnt;         // [4]
+    double* red;      // [BS / 64]
+    int* cnt;         // [BS / 64]
     double* bcast;    // [2]
     int* kstar;       // [1]
     double* theta;    // [1]
@@ -403,12 +405,14 @@ struct FullLds {
 
 // LARGE: only the keys live in LDS (room for 16384 rows).  They carry the row
 // index instead of a slot, and every sweep solves the row's roots again.
-template <typename T, bool LARGE = false>
+// BS threads (256 or 512) take part.
+template <typename T, bool LARGE = false, int BS = 256>
 __device__ void full_chain(const ChainRef<T>& r, int sel, const FullLds& L) {
+    constexpr int NW = BS / 64;
     const int tid = threadIdx.x;
     const T* Pc = r.P0 + static_cast<size_t>(sel) * r.pstride;
     int n = 0;
-    for (int i0 = 0; i0 < r.m; i0 += 256) {
+    for (int i0 = 0; i0 < r.m; i0 += BS) {
         const int i = i0 + tid;
         double al = 0.0, be = 0.0;
         bool hit = false;
@@ -421,7 +425,7 @@ __device__ void full_chain(const ChainRef<T>& r, int sel, const FullLds& L) {
             }
         }
         int tot;
-        const int pos = block_count_prefix(hit, L.cnt, tot);
+        const int pos = block_count_prefix<NW>(hit, L.cnt, tot);
         if (hit) {
             const int slot = n + pos;
             if constexpr (LARGE) {
@@ -436,12 +440,12 @@ __device__ void full_chain(const ChainRef<T>& r, int sel, const FullLds& L) {
     }
     int n2 = 512;
     while (n2 < n) n2 <<= 1;
-    for (int k = n + tid; k < n2; k += 256) L.key[k] = ~0ull;
+    for (int k = n + tid; k < n2; k += BS) L.key[k] = ~0ull;
     __syncthreads();
-    bitonic_sort_lds(L.key, n2);
+    bitonic_sort_lds<BS>(L.key, n2);
 
     // sweep: running max of beta in alpha order, candidate lengths
-    const int per = n2 >> 8;
+    const int per = n2 / BS;
     const int k0 = tid * per;
     const int k1 = min(k0 + per, n);
     const double eps = r.eps;
@@ -461,8 +465,8 @@ __device__ void full_chain(const ChainRef<T>& r, int sel, const FullLds& L) {
         ab(k, a, bt);
         tmax = fmax(tmax, bt);
     }
-    const double g_in = block_excl_scan(tmax, 0.0, MaxOp(), L.red);
-    const bool owns_last = (tid == 255);
+    const double g_in = block_excl_scan<MaxOp, NW>(tmax, 0.0, MaxOp(), L.red);
+    const bool owns_last = (tid == BS - 1);
 
     auto cand = [&](int k, double& g, double& lo, double& hi) {
         double a, bt;
@@ -483,7 +487,7 @@ __device__ void full_chain(const ChainRef<T>& r, int sel, const FullLds& L) {
         }
         gend = g;
     }
-    // The last candidate [gamma_n, 2 pi] belongs to thread 255, whose running
+    // The last candidate [gamma_n, 2 pi] belongs to the block's last thread, whose running
     // max at the end of its chunk is gamma_n.
     double last_lo = 0.0, last_len = 0.0;
     if (owns_last) {
@@ -491,7 +495,7 @@ __device__ void full_chain(const ChainRef<T>& r, int sel, const FullLds& L) {
         last_len = fmax(kTwoPi - last_lo, 0.0);
         tsum += last_len;
     }
-    const double s_in = block_excl_scan(tsum, 0.0, SumOp(), L.red);
+    const double s_in = block_excl_scan<SumOp, NW>(tsum, 0.0, SumOp(), L.red);
     if (owns_last) L.bcast[0] = s_in + tsum;
     if (tid == 0) *L.kstar = 0x7FFFFFFF;
     __syncthreads();
@@ -558,7 +562,7 @@ __device__ void full_chain(const ChainRef<T>& r, int sel, const FullLds& L) {
             }
             if (owns_last) cnt += (last_len > 0.0);
         }
-        const double base = block_excl_scan(static_cast<double>(cnt), 0.0, SumOp(), L.red);
+        const double base = block_excl_scan<SumOp, NW>(static_cast<double>(cnt), 0.0, SumOp(), L.red);
         int w = static_cast<int>(base);
         double g = g_in;
         for (int k = k0; k < k1; ++k) {
@@ -587,8 +591,8 @@ __device__ void full_chain(const ChainRef<T>& r, int sel, const FullLds& L) {
     __shared__ double s_alpha[NMAX];                        \
     __shared__ double s_beta[NMAX];                         \
     __shared__ uint64_t s_key[NMAX];                        \
-    __shared__ double s_red[4];                             \
-    __shared__ int s_cnt[4];                                \
+    __shared__ double s_red[8];                             \
+    __shared__ int s_cnt[8];                                \
     __shared__ double s_bcast[2];                           \
     __shared__ int s_kstar;                                 \
     __shared__ double s_theta[2];                           \
@@ -1184,7 +1188,16 @@ __global__ __launch_bounds__(BS, (BS == 512 && RPT <= 4 && !REFINE) ? 8 : 1) voi
     const uint32_t step = r.step;
     if (blockIdx.x == 0 && threadIdx.x == 0) a.fb_count[(step + 1) & 1] = 0;   // next step's list
     const bool done = !a.force_full && bucket_chain<T, RPT, NB, BS, REFINE>(r, sel, lds);
-    if (!done && threadIdx.x == 0) a.fb_list[atomicAdd(a.fb_count + (step & 1), 1)] = c;
+    if constexpr (REFINE) {
+        // the variant for few chains sorts a chain it could not resolve in
+        // place, so its launch needs no second kernel
+        if (!done) {
+            ESS_FULL_LDS(RPT * BS)
+            full_chain<T, false, BS>(r, sel, full_lds);
+        }
+    } else {
+        if (!done && threadIdx.x == 0) a.fb_list[atomicAdd(a.fb_count + (step & 1), 1)] = c;
+    }
 }
 
 // ---------------------------------------------------------------------------
