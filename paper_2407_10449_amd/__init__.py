@@ -330,7 +330,13 @@ def _check_out(out, shape, dtype, device):
 
 class Sampler:
     """Owns one ess_ctx.  A, b, x0 may be numpy arrays or torch tensors; they
-    are copied to the device in the working precision before ess_init."""
+    are copied to the device in the working precision before ess_init.
+
+    b of shape (n_chains, m) gives every chain its own right-hand side.
+    full_sort=True builds every chain's intervals with the full sort (the same
+    intervals); method="midpoint" uses Section 3.1's likelihood testing at
+    midpoints instead of Algorithm 3 (the quadratic comparator, m <= 4096);
+    eager=True launches kernel by kernel instead of replaying a HIP graph."""
 
     def __init__(self, A, b, x0, n_chains, seed=0, precision=32, trim_eps=None,
                  device="cuda", stream=None, full_sort=False, eager=False, method="alg3"):
