@@ -360,7 +360,10 @@ void launch_sample_t(const ess_ctx* c, const Group& g, hipStream_t st, const Sam
     }
     const dim3 fg(a.force_full ? std::min(g.n, 768) : std::min(g.n, 32));
     if (c->m > 4096) {
-        // rows in chunks of 4096 per pass; the full sort keeps keys only
+        // the roots over the whole device first, then rows in chunks of 4096
+        // per pass; the full sort keeps keys only
+        const long long blocks = static_cast<long long>((c->m + 255) / 256) * g.n;
+        hipLaunchKernelGGL((large_roots_kernel<T>), dim3(static_cast<unsigned>(blocks)), b, 0, st, a);
         hipLaunchKernelGGL((sample_large_kernel<T>), grid, b2, 0, st, a);
         hipLaunchKernelGGL((fallback_large_kernel<T>), fg, b, 0, st, a);
         return;

@@ -1062,11 +1062,11 @@ __device__ __forceinline__ void block_ab(const double2* ab, int row0, int m, dou
 }
 
 // Rows beyond what one pass holds in registers (m > BS RPT): the same bucket
-// path with refinement, each pass over the rows in chunks of BS RPT.  The
-// first pass solves the roots and keeps alpha and beta of every row in `ab`
-// (16 bytes per row, read back by the same thread in the later passes: three,
-// plus three per refinement level).  Returns false, with nothing moved, as
-// bucket_chain does.
+// path with refinement, each pass over the rows in chunks of BS RPT, reading
+// alpha and beta of every row from `ab` (16 bytes per row), which
+// large_roots_kernel filled before this launch (three passes, plus three per
+// refinement level).  Returns false, with nothing moved, as bucket_chain
+// does.
 template <typename T, int RPT, int NB, int BS>
 __device__ bool bucket_chain_large(const ChainRef<T>& r, int sel, BucketLds<NB>& L, double2* ab) {
     const int tid = threadIdx.x;
@@ -1081,13 +1081,9 @@ __device__ bool bucket_chain_large(const ChainRef<T>& r, int sel, BucketLds<NB>&
     double al[RPT], be[RPT];
     RefineMap R;
     R.n = 0;
+    (void)Pc;
     for (int c0 = 0; c0 < r.m; c0 += CH) {
-        block_roots<T, RPT, BS>(r, Pc, c0, true, al, be);
-#pragma unroll
-        for (int j = 0; j < RPT; ++j) {
-            const int i = c0 + tid + BS * j;
-            if (i < r.m) ab[i] = make_double2(al[j], be[j]);
-        }
+        block_ab<RPT, BS>(ab, c0, r.m, al, be);
         bucket_max_pass<RPT, NB>(L, R, al, be);
     }
     bucket_prefix_max<NB, BS>(L, 0.0, true);
@@ -1392,6 +1388,35 @@ __global__ __launch_bounds__(256) void sample_midpoint_kernel(SampleArgs a) {
 // Rows beyond 4096: 512 threads per chain, the chunked bucket path with
 // refinement; chains it cannot resolve go to the full sort of keys only.
 constexpr int kMaxRowsLarge = 16384;
+
+// Roots of every row of every chain ahead of sample_large_kernel: one thread
+// per row and many workgroups per chain, so the float64 solves spread over
+// the device instead of one workgroup per chain.  The projections are those
+// the per-chain kernel's commit will select (P[sel] after a rejection,
+// P[1 - sel] after an acceptance); flag and sel are only read here.  Also
+// writes the optional p, q output.
+template <typename T>
+__global__ __launch_bounds__(256) void large_roots_kernel(SampleArgs a) {
+    const int slabs = (a.m + 255) / 256;
+    const int c = a.c0 + static_cast<int>(blockIdx.x) / slabs;
+    const int i = (static_cast<int>(blockIdx.x) % slabs) * 256 + static_cast<int>(threadIdx.x);
+    if (i >= a.m) return;
+    const ChainRef<T> r = make_ref<T>(a, c);
+    const int s = *r.sel;
+    const int sel = a.has_pending ? (*r.flag ? s : (s ^ 1)) : s;
+    const T* Pc = r.P0 + static_cast<size_t>(sel) * r.pstride;
+    const T p = Pc[i], q = r.q[i];
+    double al = 0.0, be = 0.0, x0, x1;
+    if (solve_roots<T>(static_cast<double>(p), static_cast<double>(q), r.b[i], x0, x1)) {
+        al = x0;
+        be = x1;
+    }
+    static_cast<double2*>(a.ab)[static_cast<size_t>(c) * a.mp + i] = make_double2(al, be);
+    if (r.p_out) {
+        r.p_out[i] = p;
+        r.q_out[i] = q;
+    }
+}
 
 template <typename T>
 __global__ __launch_bounds__(512) void sample_large_kernel(SampleArgs a) {
