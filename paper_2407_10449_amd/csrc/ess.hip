@@ -103,7 +103,8 @@ struct ess_ctx {
     int* flag = nullptr;
     long long* rej = nullptr;
     int* fb_list = nullptr;    // chains handed to the full-sort path
-    void* AB = nullptr;        // [Cp][mp] double2: alpha, beta of every row (m > 4096)
+    void* AB = nullptr;        // [Cp][mp] double2: alpha, beta of every row (m > 4096, or
+                               // m > 2048 with at most 256 chains)
     int* fb_count = nullptr;   // [2 per group]: list lengths by step parity
     int* accepted = nullptr;   // [Cp]: gated starts taken
     uint32_t* d_step = nullptr;   // device copy of the step counter, read by the kernels
@@ -382,7 +383,15 @@ void launch_sample_t(const ess_ctx* c, const Group& g, hipStream_t st, const Sam
         if (rpt <= 2) hipLaunchKernelGGL((sample_bucket_kernel<T, 1, 2048, 512, true>), grid, b2, 0, st, a);
         else if (rpt <= 4) hipLaunchKernelGGL((sample_bucket_kernel<T, 2, 2048, 512, true>), grid, b2, 0, st, a);
         else if (rpt <= 8) hipLaunchKernelGGL((sample_bucket_kernel<T, 4, 2048, 512, true>), grid, b2, 0, st, a);
-        else hipLaunchKernelGGL((sample_bucket_kernel<T, 8, 2048, 512, true>), grid, b2, 0, st, a);
+        else if (c->AB) {
+            // above 2048 rows the roots go over the whole device first (one
+            // chain at m = 4000: 11 us of solves inside one workgroup)
+            const long long blocks = static_cast<long long>((c->m + 255) / 256) * g.n;
+            hipLaunchKernelGGL((large_roots_kernel<T>), dim3(static_cast<unsigned>(blocks)), b, 0, st, a);
+            hipLaunchKernelGGL((sample_bucket_kernel<T, 8, 2048, 512, true, true>), grid, b2, 0, st, a);
+        } else {
+            hipLaunchKernelGGL((sample_bucket_kernel<T, 8, 2048, 512, true>), grid, b2, 0, st, a);
+        }
         return;
     } else if (rpt <= 1) {
         hipLaunchKernelGGL((sample_bucket_kernel<T, 1, 256>), grid, b, 0, st, a);
@@ -1383,7 +1392,7 @@ ess_status ess_init(const ess_problem* pr, void* stream, ess_ctx** out) {
         (s = dalloc(c, reinterpret_cast<void**>(&c->d_step), sizeof(uint32_t))) != ESS_OK ||
         (s = create_run_streams(c)) != ESS_OK ||
         (s = dalloc(c, reinterpret_cast<void**>(&c->fb_count), sizeof(int) * 2 * kMaxGroups)) != ESS_OK ||
-        (c->m > 4096 &&
+        ((c->m > 4096 || (c->m > 2048 && c->C <= 256)) &&
          (s = dalloc(c, &c->AB, 2 * sizeof(double) * static_cast<size_t>(c->Cp) * c->mp)) != ESS_OK))
         return bail(s);
     {

@@ -703,6 +703,20 @@ __device__ __forceinline__ void block_roots(const ChainRef<T>& r, const T* Pc, i
     }
 }
 
+// alpha, beta of rows row0 + tid + BS j from a root array (beta = 0: no
+// crossing, or past m).
+template <int RPT, int BS>
+__device__ __forceinline__ void block_ab(const double2* ab, int row0, int m, double (&al)[RPT],
+                                         double (&be)[RPT]) {
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int i = row0 + static_cast<int>(threadIdx.x) + BS * j;
+        const double2 v = i < m ? ab[i] : make_double2(0.0, 0.0);
+        al[j] = v.x;
+        be[j] = v.y;
+    }
+}
+
 // G[b] = max beta of the rows in bucket b (G cleared before).
 template <int RPT, int NB>
 __device__ __forceinline__ void bucket_max_pass(BucketLds<NB>& L, const RefineMap& R,
@@ -948,8 +962,10 @@ __device__ __forceinline__ void finish_bucket(const ChainRef<T>& r, BucketLds<NB
 // still exceed SMAX once refinement stops (kRefineLevels levels, a level that
 // did not halve them, or a range that cannot be split): nothing has been
 // moved and the caller hands the chain to the full path.
+// With `ab`, the roots come from large_roots_kernel's output instead.
 template <typename T, int RPT, int NB, int BS = 256, bool REFINE = false>
-__device__ bool bucket_chain(const ChainRef<T>& r, int sel, BucketLds<NB>& L) {
+__device__ bool bucket_chain(const ChainRef<T>& r, int sel, BucketLds<NB>& L,
+                             const double2* ab = nullptr) {
     static_assert(BS == 256 || BS == 512, "one chain per 256 or 512 threads");
     const int tid = threadIdx.x;
     for (int b = tid; b < NB; b += BS) {
@@ -961,7 +977,10 @@ __device__ bool bucket_chain(const ChainRef<T>& r, int sel, BucketLds<NB>& L) {
     // roots of this thread's rows (row i = tid + BS r); beta = 0 marks no crossing
     const T* Pc = r.P0 + static_cast<size_t>(sel) * r.pstride;
     double al[RPT], be[RPT];
-    block_roots<T, RPT, BS>(r, Pc, 0, true, al, be);
+    if (ab)
+        block_ab<RPT, BS>(ab, 0, r.m, al, be);
+    else
+        block_roots<T, RPT, BS>(r, Pc, 0, true, al, be);
     __syncthreads();
     RefineMap R;
     R.n = 0;
@@ -1044,21 +1063,6 @@ __device__ bool bucket_chain(const ChainRef<T>& r, int sel, BucketLds<NB>& L) {
     __syncthreads();
     finish_bucket<T, NB>(r, L, S);
     return true;
-}
-
-// alpha, beta of rows row0 + tid + BS j kept by this thread in the first pass
-// (beta = 0: no crossing, or past m).  Each thread reads back only what it
-// wrote itself.
-template <int RPT, int BS>
-__device__ __forceinline__ void block_ab(const double2* ab, int row0, int m, double (&al)[RPT],
-                                         double (&be)[RPT]) {
-#pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-        const int i = row0 + static_cast<int>(threadIdx.x) + BS * j;
-        const double2 v = i < m ? ab[i] : make_double2(0.0, 0.0);
-        al[j] = v.x;
-        be[j] = v.y;
-    }
 }
 
 // Rows beyond what one pass holds in registers (m > BS RPT): the same bucket
@@ -1175,7 +1179,7 @@ __device__ bool bucket_chain_large(const ChainRef<T>& r, int sel, BucketLds<NB>&
     return true;
 }
 
-template <typename T, int RPT, int NB, int BS = 256, bool REFINE = false>
+template <typename T, int RPT, int NB, int BS = 256, bool REFINE = false, bool PRE = false>
 __global__ __launch_bounds__(BS, (BS == 512 && RPT <= 4 && !REFINE) ? 8 : 1) void sample_bucket_kernel(SampleArgs a) {
     __shared__ BucketLds<NB> lds;
     const int c = a.c0 + blockIdx.x;
@@ -1183,7 +1187,9 @@ __global__ __launch_bounds__(BS, (BS == 512 && RPT <= 4 && !REFINE) ? 8 : 1) voi
     const int sel = a.has_pending ? commit_chain<T>(r) : *r.sel;
     const uint32_t step = r.step;
     if (blockIdx.x == 0 && threadIdx.x == 0) a.fb_count[(step + 1) & 1] = 0;   // next step's list
-    const bool done = !a.force_full && bucket_chain<T, RPT, NB, BS, REFINE>(r, sel, lds);
+    // PRE: large_roots_kernel has solved this step's roots into a.ab
+    const double2* ab = PRE ? static_cast<const double2*>(a.ab) + static_cast<size_t>(c) * a.mp : nullptr;
+    const bool done = !a.force_full && bucket_chain<T, RPT, NB, BS, REFINE>(r, sel, lds, ab);
     if constexpr (REFINE) {
         // the variant for few chains sorts a chain it could not resolve in
         // place, so its launch needs no second kernel
