@@ -43,7 +43,9 @@
 //   may swap, which moves the union by at most their distance.
 //
 // More than 4096 rows (up to 16384) take the same two paths with every pass
-// over the rows made in chunks (sample_large_kernel, fallback_large_kernel).
+// over the rows made in chunks (sample_large_kernel, fallback_large_kernel),
+// after large_roots_kernel has solved the roots over the whole device (which
+// the kernels for few chains also use above 2048 rows).
 // The quadratic comparator of Section 3.1 (likelihood testing at midpoints)
 // sits beside them (sample_midpoint_kernel).
 #pragma once
