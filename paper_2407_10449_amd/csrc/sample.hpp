@@ -119,10 +119,18 @@ __device__ __forceinline__ bool solve_roots(double p, double q, double bi, doubl
             return false;   // also r = 0 (z = +inf) for b > 0
     }
     // float p, q: their squares are exact in float64 and their sum can
-    // neither overflow nor underflow, so the plain root is within an ulp
-    const double r = sizeof(T) == 4 ? sqrt(p * p + q * q) : hypot(p, q);
-    if (!(r > 0.0)) return false;
-    double z = bi / r;
+    // neither overflow nor underflow, so z = b rsqrt(p^2 + q^2) is within a
+    // few ulps (one reciprocal square root instead of a root and a divide)
+    double z;
+    if (sizeof(T) == 4) {
+        const double s2 = p * p + q * q;
+        if (!(s2 > 0.0)) return false;
+        z = bi * rsqrt(s2);
+    } else {
+        const double r = hypot(p, q);
+        if (!(r > 0.0)) return false;
+        z = bi / r;
+    }
     if (!(z < 1.0)) return false;
     z = fmax(z, -1.0);
     double tau, phi;
