@@ -288,8 +288,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "gp_rbf", "d": d, "m": m, "chains": C,
                    "storage": "f32", "projections": "f32 MFMA, f32 accumulate",
-                   "roots": "f32 pretest drops b/r >= 1.01; r and b/r in f64; f32 atan2, acos "
-                            "where |b/r| <= 0.99, f64 near tangency",
+                   "roots": "f32 pretest drops b/r >= 1.01; b/r = b rsqrt(p^2 + q^2) in f64; "
+                            "f32 atan2, acos where |b/r| <= 0.99, f64 near tangency",
                    "interval_ends_and_sampling": "f64", "trim_eps": 1e-6, "seed": 0},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS,
                      "unit": "TFLOP/s",

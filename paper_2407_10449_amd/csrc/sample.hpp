@@ -100,8 +100,8 @@ constexpr int SMAX = 128;   // survivors the bucket path resolves in place
 // T is the storage type of p and q.  With float storage, a float32 estimate
 // of z = b / r (relative error a few 1e-7) first discards rows that certainly
 // miss the ellipse (z >= 1.01), which saves the float64 work for about a third
-// of the rows at the benchmarked shape.  For every other row r and z are
-// float64, and while |z| <= 0.99 the two angles come from float32 atan2 / acos
+// of the rows at the benchmarked shape.  For every other row z is float64,
+// and while |z| <= 0.99 the two angles come from float32 atan2 / acos
 // of the exact floats p, q and of z rounded once: atan2 is off by a few float
 // ulps (< 1e-6 rad) and that rounding moves acos by at most
 // 6e-8 / sqrt(1 - 0.99^2) (< 5e-7 rad), inside the 1e-6 rad trim of the
