@@ -114,9 +114,12 @@ template <typename T>
 __device__ __forceinline__ bool solve_roots(double p, double q, double bi, double& al,
                                             double& be) {
     if (sizeof(T) == 4) {
+        // z >= 1.01 as b > 0 and b^2 >= 1.0201 r^2, without a root or a
+        // divide (also r = 0 for b > 0).  b < 1e18 keeps b^2 finite, so an
+        // overflowing right side only sends the row on to the float64 test.
         const float pf = static_cast<float>(p), qf = static_cast<float>(q);
-        if (static_cast<float>(bi) / sqrtf(pf * pf + qf * qf) >= 1.01f)
-            return false;   // also r = 0 (z = +inf) for b > 0
+        const float bf = static_cast<float>(bi);
+        if (bf > 0.0f && bf < 1e18f && bf * bf >= 1.0201f * (pf * pf + qf * qf)) return false;
     }
     // float p, q: their squares are exact in float64 and their sum can
     // neither overflow nor underflow, so z = b rsqrt(p^2 + q^2) is within a
