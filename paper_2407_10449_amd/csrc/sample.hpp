@@ -97,10 +97,10 @@ constexpr double kKeyScale = 281474976710656.0 / kTwoPi;   // 2^48 / (2 pi)
 constexpr uint64_t kKeyMax = (1ull << 48) - 1;
 constexpr int SMAX = 128;   // survivors the bucket path resolves in place
 
-// T is the storage type of p and q.  With float storage, a float32 estimate
-// of z = b / r (relative error a few 1e-7) first discards rows that certainly
-// miss the ellipse (z >= 1.01), which saves the float64 work for about a third
-// of the rows at the benchmarked shape.  For every other row z is float64,
+// T is the storage type of p and q.  With float storage, a float32 test of
+// z = b / r >= 1.01 (as b^2 >= 1.0201 r^2, relative error a few 1e-7) first
+// discards rows that certainly miss the ellipse, which saves the float64 work
+// for about a third of the rows at the benchmarked shape.  For every other row z is float64,
 // and while |z| <= 0.99 the two angles come from float32 atan2 / acos
 // of the exact floats p, q and of z rounded once: atan2 is off by a few float
 // ulps (< 1e-6 rad) and that rounding moves acos by at most
