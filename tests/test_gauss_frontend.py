@@ -103,3 +103,23 @@ def test_correlated_samples_stay_in_the_original_polytope(E):
     s.close()
     x = g.map(trace).cpu().numpy().reshape(-1, d)
     assert (x @ A.T <= b + 1e-9).all()
+
+
+def test_front_end_argument_errors(E):
+    """The Appendix A entry points refuse bad arguments before touching any
+    device memory (host checks; runs without a GPU)."""
+    lib = E.lib()
+    P = E._P
+    fake = P(0x1000)
+    st = lib.ess_whiten(fake, fake, fake, fake, 10, 3, 16, P(0x2000), fake, None)
+    assert st == E.ESS_ERR_INVALID_ARG and "precision" in E.ess_last_error()
+    st = lib.ess_whiten(fake, fake, fake, fake, 0, 3, 32, P(0x2000), fake, None)
+    assert st == E.ESS_ERR_INVALID_ARG
+    st = lib.ess_whiten(fake, fake, fake, fake, 10, 3, 32, fake, fake, None)
+    assert st == E.ESS_ERR_INVALID_ARG and "alias" in E.ess_last_error()
+    st = lib.ess_whiten(None, fake, fake, fake, 10, 3, 32, P(0x2000), fake, None)
+    assert st == E.ESS_ERR_INVALID_ARG
+    st = lib.ess_unwhiten(fake, 0, 3, fake, fake, 32, P(0x2000), None)
+    assert st == E.ESS_ERR_INVALID_ARG
+    st = lib.ess_unwhiten(fake, 5, 3, fake, fake, 32, fake, None)
+    assert st == E.ESS_ERR_INVALID_ARG and "alias" in E.ess_last_error()
