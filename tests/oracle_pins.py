@@ -129,6 +129,85 @@ def pin_fig2():
     return fails
 
 
+def pin_fig1_trimmed(eps_values=(1e-3, 0.05)):
+    """Section 3.3's trim on Figure 1: every interval [l, u] becomes
+    [l + eps, u - eps], except that an end at 0 or 2 pi is the seam through x_t
+    itself and stays (the reading taken where the paper is silent).  From the
+    figure's active arcs the trimmed set is written down by hand:
+    [0, pi/8 - eps], [7 pi/8 + eps, 9 pi/8 - eps], [7 pi/4 + eps, 2 pi].  The
+    figure's candidate list also holds an empty candidate (the inactive pair
+    (2/5, 4/5) pi), which must stay empty; so must a piece shorter than 2 eps
+    and one of zero length."""
+    fails = []
+    x, nu, cases = fig1_cases()
+    for case in cases:
+        A, b = fig1_problem(x, nu, case["lines"])
+        al, be, _ = ess.roots(A @ x, A @ nu, b)
+        lo, hi = ess.alg3_candidates(al, be)
+        for eps in eps_values:
+            tlo, thi = ess.trim(lo, hi, eps)
+            got = ess.nonempty(tlo, thi)
+            want = [(l + eps if l > 0 else l, h - eps if h < TWO_PI else h)
+                    for l, h in case["active"]]
+            if len(got) != len(want) or any(abs(g[0] - w[0]) > 1e-12 or abs(g[1] - w[1]) > 1e-12
+                                             for g, w in zip(got, want)):
+                fails.append(f"fig1 {case['name']} eps={eps}: trimmed {got} vs {want}")
+            # the empty candidate of the inactive row stays empty
+            n_empty = int((hi - lo < 0).sum())
+            if int((thi - tlo < 0).sum()) < n_empty:
+                fails.append(f"fig1 {case['name']} eps={eps}: trim made an empty candidate non-empty")
+    # short pieces: zero length in the middle, length eps (< 2 eps), and the
+    # seam pieces [0, 0] and [2 pi, 2 pi]
+    eps = 1e-3
+    lo = np.array([0.0, 1.0, 2.0, 3.0, TWO_PI])
+    hi = np.array([0.0, 1.0, 2.0 + eps, 3.5, TWO_PI])
+    tlo, thi = ess.trim(lo, hi, eps)
+    got = ess.nonempty(tlo, thi)
+    if len(got) != 1 or abs(got[0][0] - (3.0 + eps)) > 1e-15 or abs(got[0][1] - (3.5 - eps)) > 1e-15:
+        fails.append(f"short pieces after the trim: {got}")
+    th, total = ess.sample_theta(tlo, thi, 0.999999)
+    if abs(total - (0.5 - 2 * eps)) > 1e-12 or not (3.0 + eps <= th <= 3.5 - eps):
+        fails.append(f"theta {th} / total {total} outside the one trimmed piece")
+    return fails
+
+
+def pin_reject_and_stay():
+    """Section 3.3's second safeguard: a proposal that violates a constraint is
+    rejected and the chain stays at x_t; a proposal on the boundary (a^T x' = b)
+    is accepted (the reading taken where the paper is silent).  To make the
+    branch fire, the transition is handed projections that claim the row
+    never meets the ellipse (q = 0), although the direction nu = (2, 0) does
+    cross x_1 <= b: I_act is then the whole circle, theta = 2 pi u by the
+    inverse CDF of one piece, and x' = (2 sin theta, 0) by hand.
+      chain 0: u = 1/4, b = 1: theta = pi/2, x' = (2, 0) violates: reject, stay at 0
+      chain 1: u = 1/20, b = 1: x'_1 = 2 sin(pi/10) < 1: accept
+      chain 2: u = 1/4, b = 2: x' = (2, 0) lies on the boundary: accept
+    (sin of the float64 nearest pi/2 rounds to 1 exactly, checked below)."""
+    fails = []
+    A = np.array([[1.0, 0.0]])
+    u = np.array([0.25, 0.05, 0.25])
+    theta = TWO_PI * u
+    if float(np.sin(theta)[0]) != 1.0:
+        return ["sin(pi/2) does not round to 1 on this host: the boundary case is not exact"]
+    b = np.array([[1.0], [1.0], [2.0]])
+    x = np.zeros((3, 2))
+    nu = np.tile(np.array([2.0, 0.0]), (3, 1))
+    pq = (np.zeros((3, 1)), np.zeros((3, 1)))
+    out = ess.transition(A, b, x, nu, u, pq=pq)
+    want_rej = [True, False, False]
+    if [bool(v) for v in out["rejected"]] != want_rej:
+        fails.append(f"rejected {list(out['rejected'])} vs {want_rej}")
+    if np.abs(np.asarray(out["theta"]) - theta).max() > 1e-15:
+        fails.append(f"theta {out['theta']} vs 2 pi u {theta}")
+    if not np.array_equal(out["x_new"][0], x[0]):
+        fails.append(f"rejected chain moved to {out['x_new'][0]}")
+    for c in (1, 2):
+        want = np.array([2.0 * math.sin(theta[c]), 0.0])
+        if np.abs(out["x_new"][c] - want).max() > 1e-15:
+            fails.append(f"chain {c}: x_new {out['x_new'][c]} vs {want}")
+    return fails
+
+
 def pin_root_residual(seed=11, n=2000):
     """p cos(theta) + q sin(theta) = b at both roots; the arc between them is
     infeasible and the arc through theta = 0 feasible."""
@@ -467,7 +546,7 @@ def pin_rejection_sampling_reference(seed=19, n_chains=200, n_steps=100, burn=20
     return [f"mean {cm.mean(axis=0)} vs rejection sampling {ref}"] if bad.any() else []
 
 
-FAST_PINS = [pin_fig1, pin_fig2, pin_root_residual, pin_rotation_covariance,
+FAST_PINS = [pin_fig1, pin_fig2, pin_fig1_trimmed, pin_reject_and_stay, pin_root_residual, pin_rotation_covariance,
              pin_alg3_equals_alg2, pin_midpoint_equals_alg2, pin_dense_grid, pin_appendix_d,
              pin_sorting_reduction,
              pin_theta_uniform, pin_philox_kat, pin_box_muller]

@@ -6,7 +6,9 @@ cumulative max, an off-by-one in gamma, a wrong interpolation in the inverse
 CDF, swapped ellipse terms, an inverted safeguard, a wrong Philox constant,
 a likelihood test that reads one row or swaps inside and outside, a gap
 tested at its end instead of its middle, a change of variables with the
-wrong sign of A mu or without the mean.
+wrong sign of A mu or without the mean, a trim that also moves the 0 / 2 pi
+seam, trims by 2 eps or turns an empty candidate into a piece, and a
+transition that never rejects or rejects a proposal on the boundary.
 """
 import numpy as np
 import pytest
@@ -87,6 +89,38 @@ def _transition_inverted_safeguard(A, b, x, nu, u, eps=0.0, pq=None, store=np.fl
     return out
 
 
+def _trim_seam_too(lo, hi, eps):
+    lo = np.asarray(lo, float)
+    hi = np.asarray(hi, float)
+    return lo + eps, hi - eps                                    # the seam moves as well
+
+
+def _trim_twice(lo, hi, eps):
+    return ORIG["trim"](lo, hi, 2.0 * eps)                       # 2 eps per end
+
+
+def _trim_orders_ends(lo, hi, eps):
+    tlo, thi = ORIG["trim"](lo, hi, eps)
+    return np.minimum(tlo, thi), np.maximum(tlo, thi)            # empty candidates become pieces
+
+
+def _transition_always_accept(A, b, x, nu, u, eps=0.0, pq=None, store=np.float64, method="alg3"):
+    out = ORIG["transition"](A, b, x, nu, u, eps, pq, store, method)
+    out["rejected"] = out["total"] <= 0.0                        # the safeguard dropped
+    out["x_new"] = np.where(out["rejected"][:, None], np.asarray(x, float), out["x_prop"])
+    return out
+
+
+def _transition_rejects_boundary(A, b, x, nu, u, eps=0.0, pq=None, store=np.float64, method="alg3"):
+    out = ORIG["transition"](A, b, x, nu, u, eps, pq, store, method)
+    bb = np.asarray(b, float)
+    bb = bb[None, :] if bb.ndim == 1 else bb
+    viol = (out["x_prop"] @ np.asarray(A, float).T >= bb).any(axis=1)   # equality rejected
+    out["rejected"] = viol | (out["total"] <= 0.0)
+    out["x_new"] = np.where(out["rejected"][:, None], np.asarray(x, float), out["x_prop"])
+    return out
+
+
 def _philox_wrong_weyl(c0, c1, c2, c3, k0, k1):
     saved = philox.W1
     philox.W1 = np.uint64(0xBB67AE86)
@@ -129,7 +163,8 @@ def _unwhiten_no_mean(U, L, mu):
 
 
 ORIG = {"roots": ess.roots, "alg3_candidates": ess.alg3_candidates,
-        "transition": ess.transition, "philox4x32_10": philox.philox4x32_10}
+        "transition": ess.transition, "philox4x32_10": philox.philox4x32_10,
+        "trim": ess.trim}
 
 MUTATIONS = [
     (ess, "roots", _roots_sign_flip),
@@ -148,6 +183,11 @@ MUTATIONS = [
     (ess, "midpoint_intervals", _midpoint_tests_lower_end),
     (ess, "whiten", _whiten_shift_sign),
     (ess, "unwhiten", _unwhiten_no_mean),
+    (ess, "trim", _trim_seam_too),
+    (ess, "trim", _trim_twice),
+    (ess, "trim", _trim_orders_ends),
+    (ess, "transition", _transition_always_accept),
+    (ess, "transition", _transition_rejects_boundary),
 ]
 
 
