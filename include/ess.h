@@ -59,6 +59,10 @@ typedef enum {
                                  midpoints between sorted intersection angles
                                  (Section 3.1), O(m^2) per chain; m <= 4096,
                                  single-problem contexts only */
+#define ESS_BRUTE_FORCE 32u   /* comparator, not Algorithm 3: intersect the rows'
+                                 sets one at a time (Algorithm 2), O(m^2) per chain
+                                 at worst (Appendix D); m <= 4096, single-problem
+                                 contexts only */
 
 /* A whitened problem: N(0, I_d) truncated to {x : A x <= b} (Section 1).
  * The polytope must have a non-empty interior; x0 must be strictly inside

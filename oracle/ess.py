@@ -213,7 +213,8 @@ def transition(A, b, x, nu, u, eps=0.0, pq=None, store=np.float64, method="alg3"
     (C, m)) is given, those projections are used instead of A x and A nu.
     The proposal is rounded to `store` before the feasibility check, as the
     code under test stores it.  method="midpoint" builds the active intervals
-    by Section 3.1's likelihood testing instead of Algorithm 3.
+    by Section 3.1's likelihood testing and method="alg2" by Algorithm 2's
+    sequential intersection instead of Algorithm 3.
     Returns a dict with x_new, rejected, theta, intervals (list per chain of
     the non-empty trimmed pieces), alpha, beta, p, q, x_prop.
     """
@@ -233,6 +234,16 @@ def transition(A, b, x, nu, u, eps=0.0, pq=None, store=np.float64, method="alg3"
         lo, hi = alg3_candidates(alpha, beta)
         lo, hi = trim(lo, hi, eps)
         pieces = [(lo[c], hi[c]) for c in range(C)]
+    elif method == "alg2":
+        # Algorithm 2 over the rows the ellipse crosses (a row it does not
+        # cross has I_i = [0, 2 pi], which leaves the intersection as it is)
+        pieces = []
+        for c in range(C):
+            hit = beta[c] > 0.0
+            ivs = alg2_brute_force(alpha[c][hit], beta[c][hit])
+            lo_c = np.array([v[0] for v in ivs] or [0.0])
+            hi_c = np.array([v[1] for v in ivs] or [0.0])
+            pieces.append(trim(lo_c, hi_c, eps))
     else:
         pieces = []
         for c in range(C):

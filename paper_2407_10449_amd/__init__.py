@@ -25,6 +25,7 @@ ESS_ERR_UNSUPPORTED = 5
 ESS_X0_BROADCAST = 1
 ESS_SORT_FULL = 2
 ESS_LIKELIHOOD_MIDPOINT = 16
+ESS_BRUTE_FORCE = 32
 ESS_PER_CHAIN_B = 4
 ESS_EAGER = 8
 
@@ -335,7 +336,8 @@ class Sampler:
     b of shape (n_chains, m) gives every chain its own right-hand side.
     full_sort=True builds every chain's intervals with the full sort (the same
     intervals); method="midpoint" uses Section 3.1's likelihood testing at
-    midpoints instead of Algorithm 3 (the quadratic comparator, m <= 4096);
+    midpoints and method="alg2" Algorithm 2's sequential intersection instead
+    of Algorithm 3 (the quadratic comparators, m <= 4096);
     eager=True launches kernel by kernel instead of replaying a HIP graph."""
 
     def __init__(self, A, b, x0, n_chains, seed=0, precision=32, trim_eps=None,
@@ -361,8 +363,10 @@ class Sampler:
             flags |= ESS_EAGER
         if method == "midpoint":    # Section 3.1's likelihood testing (comparator)
             flags |= ESS_LIKELIHOOD_MIDPOINT
+        elif method == "alg2":      # Algorithm 2's sequential intersection (comparator)
+            flags |= ESS_BRUTE_FORCE
         elif method != "alg3":
-            raise ValueError("method must be 'alg3' or 'midpoint'")
+            raise ValueError("method must be 'alg3', 'alg2' or 'midpoint'")
         if trim_eps is None:
             trim_eps = 1e-6 if precision == 32 else 0.0
         self.trim_eps = float(trim_eps)

@@ -228,8 +228,10 @@ __global__ __launch_bounds__(256) void batched_step_kernel(BatchArgs a) {
     const ChainRef<float> r = batch_ref(a, pd, p, c);
     const int sel = a.has_pending ? commit_chain<float>(r) : *r.sel;
     if (a.do_sample) {
-        const bool ok = bucket_chain<float, RPT, NB>(r, sel, lds.b);
-        if (!ok && tid == 0) a.fb_list[atomicAdd(a.fb_count + par, 1)] = make_int2(p, c);
+        double theta = 0.0;
+        const bool ok = bucket_chain<float, RPT, NB>(r, sel, lds.b, theta);
+        if (ok) move_chain<float>(r, theta);
+        else if (tid == 0) a.fb_list[atomicAdd(a.fb_count + par, 1)] = make_int2(p, c);
     }
 }
 
@@ -244,8 +246,10 @@ __global__ __launch_bounds__(256, RPT <= 8 ? 6 : 1) void batched_chain_kernel(Ba
     const ChainRef<float> r = batch_ref(a, pd, ch.x, ch.y);
     const int sel = a.has_pending ? commit_chain<float>(r) : *r.sel;
     if (a.do_sample) {
-        const bool ok = bucket_chain<float, RPT, NB>(r, sel, lds);
-        if (!ok && threadIdx.x == 0) a.fb_list[atomicAdd(a.fb_count + par, 1)] = ch;
+        double theta = 0.0;
+        const bool ok = bucket_chain<float, RPT, NB>(r, sel, lds, theta);
+        if (ok) move_chain<float>(r, theta);
+        else if (threadIdx.x == 0) a.fb_list[atomicAdd(a.fb_count + par, 1)] = ch;
     }
 }
 
@@ -261,8 +265,10 @@ __global__ __launch_bounds__(256) void batched_fallback_kernel(BatchArgs a) {
         const int2 ch = a.fb_list[idx];
         const ChainRef<float> r = batch_ref(a, a.descs[ch.x], ch.x, ch.y);
         const int sel = *r.sel;
-        if (!bucket_chain<float, NMAX / 256, 2048, 256, true>(r, sel, blds))
-            full_chain<float>(r, sel, full_lds);
+        double theta = 0.0;
+        if (!bucket_chain<float, NMAX / 256, 2048, 256, true>(r, sel, blds, theta))
+            theta = full_chain<float>(r, sel, full_lds);
+        move_chain<float>(r, theta);
         __syncthreads();
     }
 }

@@ -104,7 +104,8 @@ struct ess_ctx {
     long long* rej = nullptr;
     int* fb_list = nullptr;    // chains handed to the full-sort path
     void* AB = nullptr;        // [Cp][mp] double2: alpha, beta of every row (m > 4096, or
-                               // m > 2048 with at most 256 chains)
+                               // m > 2048 with at most 256 chains), and of a chain the
+                               // bucket path hands to the full sort
     int* fb_count = nullptr;   // [2 per group]: list lengths by step parity
     int* accepted = nullptr;   // [Cp]: gated starts taken
     uint32_t* d_step = nullptr;   // device copy of the step counter, read by the kernels
@@ -120,7 +121,6 @@ struct ess_ctx {
     std::vector<GraphEntry> graphs;
     bool use_graphs = true;
     int bm = 128, bn = 128, group_m = 4;
-    int nmax = 512;
     // chain groups: each runs its own sample -> project pipeline on its own
     // stream, so one group's matrix-core work overlaps another's vector work
     int G = 1;
@@ -349,8 +349,12 @@ SampleArgs sample_args(const ess_ctx* c, const Group& g, int gi) {
     return a;
 }
 
-// Bucket path over the group's chains, then the full-sort path over the
-// chains it handed over (usually none: the second launch then exits at once).
+// Dynamic LDS of Algorithm 2's kernel: two lists of m + 2 pieces.
+size_t alg2_lds_bytes(int m) { return 2 * sizeof(double2) * static_cast<size_t>(m + 2); }
+
+// The per-chain kernel of one step over the group's chains (beyond 4096 rows:
+// the root pre-pass, the chunked bucket path and the full sort of the chains
+// it hands over).
 template <typename T>
 void launch_sample_t(const ess_ctx* c, const Group& g, hipStream_t st, const SampleArgs& a) {
     const dim3 grid(g.n), b(256), b2(512);
@@ -359,10 +363,14 @@ void launch_sample_t(const ess_ctx* c, const Group& g, hipStream_t st, const Sam
         hipLaunchKernelGGL((sample_midpoint_kernel<T>), grid, b, 0, st, a);
         return;
     }
-    const dim3 fg(a.force_full ? std::min(g.n, 768) : std::min(g.n, 32));
+    if (c->flags & ESS_BRUTE_FORCE) {
+        hipLaunchKernelGGL((sample_alg2_kernel<T>), grid, dim3(64), alg2_lds_bytes(c->m), st, a);
+        return;
+    }
     if (c->m > 4096) {
         // the roots over the whole device first, then rows in chunks of 4096
         // per pass; the full sort keeps keys only
+        const dim3 fg(a.force_full ? std::min(g.n, 768) : std::min(g.n, 32));
         const long long blocks = static_cast<long long>((c->m + 255) / 256) * g.n;
         hipLaunchKernelGGL((large_roots_kernel<T>), dim3(static_cast<unsigned>(blocks)), b, 0, st, a);
         hipLaunchKernelGGL((sample_large_kernel<T>), grid, b2, 0, st, a);
@@ -373,17 +381,17 @@ void launch_sample_t(const ess_ctx* c, const Group& g, hipStream_t st, const Sam
     // m = 2000: the latency-bound phases have half the rows per thread)
     // With no more chains than compute units, occupancy does not matter and
     // the kernel carries the bucket refinement itself, so a chain with crowded
-    // buckets is resolved in place instead of by the second kernel.
+    // buckets is resolved in place instead of by the full sort.
     // Few chains also take 512 threads at every m: the phases are latency-bound
     // and halving the rows per thread shortens them (one chain at m = 1000:
     // 22 -> 16 us).
-    // These kernels also sort an unresolved chain in place, so no second
-    // launch follows them.
+    // Every variant sorts a chain it cannot resolve in place, so one launch
+    // per step does all of the per-chain work.
     if (g.n <= 256) {
         if (rpt <= 2) hipLaunchKernelGGL((sample_bucket_kernel<T, 1, 2048, 512, true>), grid, b2, 0, st, a);
         else if (rpt <= 4) hipLaunchKernelGGL((sample_bucket_kernel<T, 2, 2048, 512, true>), grid, b2, 0, st, a);
         else if (rpt <= 8) hipLaunchKernelGGL((sample_bucket_kernel<T, 4, 2048, 512, true>), grid, b2, 0, st, a);
-        else if (c->AB) {
+        else if (c->m > 2048) {
             // above 2048 rows the roots go over the whole device first (one
             // chain at m = 4000: 11 us of solves inside one workgroup)
             const long long blocks = static_cast<long long>((c->m + 255) / 256) * g.n;
@@ -392,7 +400,6 @@ void launch_sample_t(const ess_ctx* c, const Group& g, hipStream_t st, const Sam
         } else {
             hipLaunchKernelGGL((sample_bucket_kernel<T, 8, 2048, 512, true>), grid, b2, 0, st, a);
         }
-        return;
     } else if (rpt <= 1) {
         hipLaunchKernelGGL((sample_bucket_kernel<T, 1, 256>), grid, b, 0, st, a);
     } else if (rpt <= 2) {
@@ -403,14 +410,6 @@ void launch_sample_t(const ess_ctx* c, const Group& g, hipStream_t st, const Sam
         hipLaunchKernelGGL((sample_bucket_kernel<T, 4, 2048, 512>), grid, b2, 0, st, a);
     } else {
         hipLaunchKernelGGL((sample_bucket_kernel<T, 8, 2048, 512>), grid, b2, 0, st, a);
-    }
-    // the full-sort pass is usually empty: a small grid keeps its launch cheap,
-    // unless every chain takes it (ESS_SORT_FULL)
-    switch (c->nmax) {
-        case 512: hipLaunchKernelGGL((fallback_kernel<T, 512>), fg, b, 0, st, a); break;
-        case 1024: hipLaunchKernelGGL((fallback_kernel<T, 1024>), fg, b, 0, st, a); break;
-        case 2048: hipLaunchKernelGGL((fallback_kernel<T, 2048>), fg, b, 0, st, a); break;
-        default: hipLaunchKernelGGL((fallback_kernel<T, 4096>), fg, b, 0, st, a); break;
     }
 }
 
@@ -466,11 +465,14 @@ ess_status copy_rows_out(const ess_ctx* c, void* dst, const void* src) {
     return ESS_OK;
 }
 
-// Replace the state by the rows already in c->X: A x into the committed
-// projection buffers and a strict feasibility check (a_i^T x < b_i).
-ess_status set_state_from_X(ess_ctx* c, const char* what) {
+// Strict feasibility check (a_i^T x < b_i) of the rows in c->X (staged = 0:
+// their projections go to the committed buffers, for ess_init) or of rows
+// staged in c->Xprop (staged = 1: projections into the proposal buffers; on
+// success every chain adopts its staged row as an accepted proposal, so a
+// failed call leaves the state as it was).
+ess_status check_rows(ess_ctx* c, const char* what, int staged) {
     HIP_TRY(hipMemsetAsync(c->flag, 0, sizeof(int) * c->Cp, c->st));
-    ESS_TRY(launch_proj(c, c->whole(), c->st, c->X, COLS_X, 1, 1));
+    ESS_TRY(launch_proj(c, c->whole(), c->st, staged ? c->Xprop : c->X, COLS_X, !staged, 1));
     std::vector<int> fl(c->C);
     HIP_TRY(hipMemcpyAsync(fl.data(), c->flag, sizeof(int) * c->C, hipMemcpyDeviceToHost, c->st));
     HIP_TRY(hipStreamSynchronize(c->st));
@@ -478,6 +480,7 @@ ess_status set_state_from_X(ess_ctx* c, const char* what) {
         if (!fl[ch]) continue;
         int sel = 0;
         HIP_TRY(hipMemcpy(&sel, c->sel + ch, sizeof(int), hipMemcpyDeviceToHost));
+        if (staged) sel ^= 1;
         std::vector<double> bh(c->m), ph(c->m);
         HIP_TRY(hipMemcpy(bh.data(), c->b + static_cast<size_t>(ch) * c->bstride,
                           sizeof(double) * c->m, hipMemcpyDeviceToHost));
@@ -499,7 +502,15 @@ ess_status set_state_from_X(ess_ctx* c, const char* what) {
                     "%s: chain %d is not strictly feasible: row %d has a^T x = %.9g >= b = %.9g",
                     what, ch, row, row >= 0 ? ph[row] : 0.0, row >= 0 ? bh[row] : 0.0);
     }
+    if (staged) ESS_TRY(launch_commit(c, c->whole(), c->st, sample_args(c, c->whole(), 0)));
     return ESS_OK;
+}
+
+// nu of the current step (the device counter) into N and A nu into Q, which
+// every run expects to find there.
+ess_status prime_direction(ess_ctx* c) {
+    ESS_TRY(launch_draw(c, 0, c->C, c->st, 0, c->d_step, c->N, c->dp, nullptr));
+    return launch_proj(c, c->whole(), c->st, c->Xprop, COLS_NU, 0, 0);
 }
 
 ess_status check_ctx(const ess_ctx* c) {
@@ -541,24 +552,22 @@ ess_status issue_run(ess_ctx* c, int64_t n_steps, int64_t thin, void* trace, hip
         HIP_TRY(hipEventRecord(c->fork, base));
         for (int g = 0; g < c->G; ++g) HIP_TRY(hipStreamWaitEvent(sts[g], c->fork, 0));
     }
+    // N and Q already hold nu of the current step and A nu (prime_direction
+    // after every change of state or counter, and each run's last step draws
+    // and projects the next run's first direction), so every step of the run
+    // is the same pair of launches
     SampleArgs a[kMaxGroups];
     for (int g = 0; g < c->G; ++g) {
         if (gr[g].n == 0) continue;
-        ESS_TRY(clear_fallback_lists(c, sts[g], g));
-        ESS_TRY(timed(c, ESS_KERNEL_OTHER, sts[g], [&] {
-            return launch_draw(c, gr[g].c0, gr[g].n, sts[g], 0, c->d_step, c->N, c->dp, nullptr);
-        }));
-        ESS_TRY(timed(c, ESS_KERNEL_OTHER, sts[g],
-                      [&] { return launch_proj(c, gr[g], sts[g], c->Xprop, COLS_NU, 0, 0); }));
+        if (c->m > 4096) ESS_TRY(clear_fallback_lists(c, sts[g], g));
         a[g] = sample_args(c, gr[g], g);
     }
     for (int64_t s = 0; s < n_steps; ++s) {
-        const bool both = s + 1 < n_steps;
         for (int g = 0; g < c->G; ++g) {
             if (gr[g].n == 0) continue;
             a[g].step = static_cast<uint32_t>(s);
             a[g].has_pending = s > 0;
-            a[g].gen_next = both;
+            a[g].gen_next = 1;
             a[g].trace = (trace && s > 0 && s % thin == 0)
                              ? static_cast<char*>(trace) + (s / thin - 1) * trace_row
                              : nullptr;
@@ -569,8 +578,8 @@ ess_status issue_run(ess_ctx* c, int64_t n_steps, int64_t thin, void* trace, hip
             ESS_TRY(timed(c, ESS_KERNEL_SAMPLE, sts[g],
                           [&] { return launch_sample(c, gr[g], sts[g], a[g]); }));
             if (split && g + 1 < c->G) HIP_TRY(hipEventRecord(c->stagger[g], sts[g]));
-            ESS_TRY(timed(c, both ? ESS_KERNEL_PROJECT : ESS_KERNEL_OTHER, sts[g], [&] {
-                return launch_proj(c, gr[g], sts[g], c->Xprop, both ? COLS_BOTH : COLS_X, 0, 0);
+            ESS_TRY(timed(c, ESS_KERNEL_PROJECT, sts[g], [&] {
+                return launch_proj(c, gr[g], sts[g], c->Xprop, COLS_BOTH, 0, 0);
             }));
         }
     }
@@ -919,6 +928,9 @@ ess_status run_dispatch(ess_ctx* c, int64_t n_steps, int64_t thin, void* trace) 
             (void)hipGraphDestroy(graph);
             HIP_TRY(ei);
             if (c->graphs.size() >= 8) {
+                // the oldest graph may still be queued or running on the
+                // capture stream: wait for it before destroying it
+                HIP_TRY(hipStreamSynchronize(c->cs));
                 (void)hipGraphExecDestroy(c->graphs.front().exec);
                 c->graphs.erase(c->graphs.begin());
             }
@@ -1279,6 +1291,28 @@ ess_status mlp_backward(ess_mlp* n, const float* target, int B, double* loss) {
 
 // Start states for every chain: the candidate row where it is strictly
 // feasible, the fallback row elsewhere.
+// Projection tile shape of a single-problem context.
+void choose_tiles(ess_ctx* c) {
+    if (c->prec == 32) {
+        // 128 x 128 tiles when they fill the 256 CUs (one tile each), else
+        // 64 x 64: measured fastest at d=1000, m=2000, 1024 chains (256
+        // tiles) and at d=256, m=768 with 2048 chains (192 large tiles: 64 x 64
+        // took 64.7 us per step against 73.8 to 76.0 for the larger shapes)
+        const long long big = static_cast<long long>(c->mp / 128) * (2 * c->Cp / 128);
+        c->bm = c->bn = big >= 256 ? 128 : 64;
+    } else {
+        c->bm = c->bn = 64;
+    }
+    if (const char* e = std::getenv("ESS_PROJ_TILE")) {   // "BMxBN", e.g. 64x128
+        int bm = 0, bn = 0;
+        if (std::sscanf(e, "%dx%d", &bm, &bn) == 2 && (bm == 64 || bm == 128) &&
+            (bn == 64 || bn == 128) && c->prec == 32) {
+            c->bm = bm;
+            c->bn = bn;
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void gate_rows_kernel(const int* __restrict__ flag,
                                                         const void* fallback, void* X, int d, int dp,
                                                         int esz, int* accepted) {
@@ -1318,9 +1352,20 @@ ess_status ess_init(const ess_problem* pr, void* stream, ess_ctx** out) {
     if (pr->m > kMaxRowsLarge)
         return fail(ESS_ERR_UNSUPPORTED, "m = %d exceeds the %d rows one workgroup sorts", pr->m,
                     kMaxRowsLarge);
-    if ((pr->flags & ESS_LIKELIHOOD_MIDPOINT) && pr->m > kMidpointMaxRows)
-        return fail(ESS_ERR_UNSUPPORTED, "likelihood testing takes m <= %d (got %d)",
+    if ((pr->flags & (ESS_LIKELIHOOD_MIDPOINT | ESS_BRUTE_FORCE)) && pr->m > kMidpointMaxRows)
+        return fail(ESS_ERR_UNSUPPORTED, "the quadratic comparators take m <= %d (got %d)",
                     kMidpointMaxRows, pr->m);
+    if ((pr->flags & ESS_LIKELIHOOD_MIDPOINT) && (pr->flags & ESS_BRUTE_FORCE))
+        return fail(ESS_ERR_INVALID_ARG, "choose one of ESS_LIKELIHOOD_MIDPOINT and ESS_BRUTE_FORCE");
+    if (pr->flags & ESS_BRUTE_FORCE) {
+        // Algorithm 2's lists take more LDS than the default limit above 2046 rows
+        hipError_t e = hipFuncSetAttribute(
+            reinterpret_cast<const void*>(pr->precision == 32 ? &sample_alg2_kernel<float>
+                                                              : &sample_alg2_kernel<double>),
+            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(alg2_lds_bytes(pr->m)));
+        if (e != hipSuccess)
+            return fail(ESS_ERR_HIP, "hipFuncSetAttribute: %s", hipGetErrorString(e));
+    }
     if (pr->d > (1 << 20) || pr->n_chains > (1 << 24))
         return fail(ESS_ERR_UNSUPPORTED, "d or n_chains too large");
 
@@ -1348,27 +1393,7 @@ ess_status ess_init(const ess_problem* pr, void* stream, ess_ctx** out) {
     c->Cp = round_up(c->C, 128);
     c->G = std::min(c->G, c->Cp / 128);
     c->dp = round_up(c->d, 32);
-    if (c->prec == 32) {
-        // 128 x 128 tiles when they fill the 256 CUs (one tile each), else
-        // 64 x 64: measured fastest at d=1000, m=2000, 1024 chains (256
-        // tiles) and at d=256, m=768 with 2048 chains (192 large tiles: 64 x 64
-        // took 64.7 us per step against 73.8 to 76.0 for the larger shapes)
-        const long long big = static_cast<long long>(c->mp / 128) * (2 * c->Cp / 128);
-        c->bm = c->bn = big >= 256 ? 128 : 64;
-    } else {
-        c->bm = c->bn = 64;
-    }
-    if (const char* e = std::getenv("ESS_PROJ_TILE")) {   // "BMxBN", e.g. 64x128
-        int bm = 0, bn = 0;
-        if (std::sscanf(e, "%dx%d", &bm, &bn) == 2 && (bm == 64 || bm == 128) &&
-            (bn == 64 || bn == 128) && c->prec == 32) {
-            c->bm = bm;
-            c->bn = bn;
-        }
-    }
-    c->nmax = 512;
-    while (c->nmax < c->m) c->nmax <<= 1;
-
+    choose_tiles(c);
     auto bail = [&](ess_status s) {
         std::string keep = g_err;
         ess_destroy(c);
@@ -1392,8 +1417,7 @@ ess_status ess_init(const ess_problem* pr, void* stream, ess_ctx** out) {
         (s = dalloc(c, reinterpret_cast<void**>(&c->d_step), sizeof(uint32_t))) != ESS_OK ||
         (s = create_run_streams(c)) != ESS_OK ||
         (s = dalloc(c, reinterpret_cast<void**>(&c->fb_count), sizeof(int) * 2 * kMaxGroups)) != ESS_OK ||
-        ((c->m > 4096 || (c->m > 2048 && c->C <= 256)) &&
-         (s = dalloc(c, &c->AB, 2 * sizeof(double) * static_cast<size_t>(c->Cp) * c->mp)) != ESS_OK))
+        (s = dalloc(c, &c->AB, 2 * sizeof(double) * static_cast<size_t>(c->Cp) * c->mp)) != ESS_OK)
         return bail(s);
     {
         // every group stream and event exists from the start: the autotuner and
@@ -1436,7 +1460,8 @@ ess_status ess_init(const ess_problem* pr, void* stream, ess_ctx** out) {
         fail(ESS_ERR_HIP, "copying the problem: %s", hipGetErrorString(e));
         return bail(ESS_ERR_HIP);
     }
-    if ((s = set_state_from_X(c, "ess_init")) != ESS_OK) return bail(s);
+    if ((s = check_rows(c, "ess_init", 0)) != ESS_OK || (s = prime_direction(c)) != ESS_OK)
+        return bail(s);
     *out = c;
     return ESS_OK;
 }
@@ -1534,11 +1559,13 @@ ess_status ess_set_state(ess_ctx* c, const void* x_in, uint64_t step) {
     if (c->batch) {
         ESS_TRY(batched_copy_state(c, static_cast<const float*>(x_in), c->batch->X, 1));
         ESS_TRY(batched_set_state_from_X(c, "ess_set_state"));
+        ESS_TRY(launch_step_counter(c, c->st, step, 0));
     } else {
-        ESS_TRY(copy_rows_in(c, c->X, x_in));
-        ESS_TRY(set_state_from_X(c, "ess_set_state"));
+        ESS_TRY(copy_rows_in(c, c->Xprop, x_in));
+        ESS_TRY(check_rows(c, "ess_set_state", 1));
+        ESS_TRY(launch_step_counter(c, c->st, step, 0));
+        ESS_TRY(prime_direction(c));
     }
-    ESS_TRY(launch_step_counter(c, c->st, step, 0));
     c->step = step;
     return ESS_OK;
 }
@@ -1581,9 +1608,9 @@ ess_status ess_init_batched(const ess_problem* pr, int32_t n_problems, void* str
             return fail(ESS_ERR_INVALID_ARG, "problem %d: trim_eps must lie in [0, 1]", p);
         if (q.m > 4096) return fail(ESS_ERR_UNSUPPORTED, "problem %d: m = %d exceeds 4096", p, q.m);
         if (q.d > (1 << 20)) return fail(ESS_ERR_UNSUPPORTED, "problem %d: d too large", p);
-        if (q.flags & (ESS_SORT_FULL | ESS_LIKELIHOOD_MIDPOINT))
+        if (q.flags & (ESS_SORT_FULL | ESS_LIKELIHOOD_MIDPOINT | ESS_BRUTE_FORCE))
             return fail(ESS_ERR_UNSUPPORTED,
-                        "problem %d: ESS_SORT_FULL and ESS_LIKELIHOOD_MIDPOINT are not offered for batches", p);
+                        "problem %d: ESS_SORT_FULL and the comparators are not offered for batches", p);
         total_chains += q.n_chains;
     }
     if (total_chains > (1 << 24)) return fail(ESS_ERR_UNSUPPORTED, "too many chains in the batch");
@@ -1611,11 +1638,11 @@ ess_status ess_transition_explicit(ess_ctx* c, const void* x, const void* nu, co
     ESS_TRY(check_ctx(c));
     if (c->batch) return fail(ESS_ERR_UNSUPPORTED, "explicit transitions take single-problem contexts");
     if (!x || !nu || !u || !x_new) return fail(ESS_ERR_INVALID_ARG, "null x, nu, u or x_new");
-    ESS_TRY(copy_rows_in(c, c->X, x));
-    ESS_TRY(set_state_from_X(c, "ess_transition_explicit"));
+    ESS_TRY(copy_rows_in(c, c->Xprop, x));
+    ESS_TRY(check_rows(c, "ess_transition_explicit", 1));
     ESS_TRY(copy_rows_in(c, c->N, nu));
     const Group w = c->whole();
-    ESS_TRY(clear_fallback_lists(c, c->st, 0));
+    if (c->m > 4096) ESS_TRY(clear_fallback_lists(c, c->st, 0));
     ESS_TRY(launch_proj(c, w, c->st, c->Xprop, COLS_NU, 0, 0));
     SampleArgs a = sample_args(c, w, 0);
     a.step = 0;   // the device counter holds the current step
@@ -1630,7 +1657,8 @@ ess_status ess_transition_explicit(ess_ctx* c, const void* x, const void* nu, co
     f.rejected_out = rejected;
     ESS_TRY(launch_commit(c, w, c->st, f));
     ESS_TRY(copy_rows_out(c, x_new, c->X));
-    return ESS_OK;
+    // N and Q back to the current step's direction for later runs
+    return prime_direction(c);
 }
 
 ess_status ess_draw(ess_ctx* c, uint64_t step, void* nu, double* u) {
@@ -1649,18 +1677,22 @@ ess_status ess_set_state_gated(ess_ctx* c, const void* x_candidate, const void* 
     if (c->batch) return fail(ESS_ERR_UNSUPPORTED, "gated starts take single-problem contexts");
     if (!x_candidate || !x_fallback) return fail(ESS_ERR_INVALID_ARG, "null candidate or fallback");
     if (step >= (1ull << 32)) return fail(ESS_ERR_UNSUPPORTED, "the step counter is limited to 2^32");
-    ESS_TRY(copy_rows_in(c, c->X, x_candidate));
+    // candidates staged in Xprop, checked strictly (projections into the
+    // proposal buffers), rejected rows replaced by their fallback; the state
+    // changes only once every staged row has passed the check
+    ESS_TRY(copy_rows_in(c, c->Xprop, x_candidate));
     HIP_TRY(hipMemsetAsync(c->flag, 0, sizeof(int) * c->Cp, c->st));
-    ESS_TRY(launch_proj(c, c->whole(), c->st, c->X, COLS_X, 1, 1));   // strict check
-    hipLaunchKernelGGL(gate_rows_kernel, dim3(c->C), dim3(256), 0, c->st, c->flag, x_fallback, c->X,
-                       c->d, c->dp, c->esz, c->accepted);
+    ESS_TRY(launch_proj(c, c->whole(), c->st, c->Xprop, COLS_X, 0, 1));   // strict check
+    hipLaunchKernelGGL(gate_rows_kernel, dim3(c->C), dim3(256), 0, c->st, c->flag, x_fallback,
+                       c->Xprop, c->d, c->dp, c->esz, c->accepted);
     HIP_TRY(hipGetLastError());
     std::vector<int> acc(c->C);
     HIP_TRY(hipMemcpyAsync(acc.data(), c->accepted, sizeof(int) * c->C, hipMemcpyDeviceToHost, c->st));
-    ESS_TRY(set_state_from_X(c, "ess_set_state_gated (fallback rows)"));
+    ESS_TRY(check_rows(c, "ess_set_state_gated (fallback rows)", 1));
     if (accepted)
         for (int i = 0; i < c->C; ++i) accepted[i] = acc[i];
     ESS_TRY(launch_step_counter(c, c->st, step, 0));
+    ESS_TRY(prime_direction(c));
     c->step = step;
     return ESS_OK;
 }
@@ -1852,19 +1884,34 @@ ess_status ess_autotune(ess_ctx* c, int32_t steps_per_trial, char* report, int32
                     "ess_autotune is switched off for single-problem contexts: its trial loop "
                     "ended the process with a host segmentation fault whose cause is not yet known");
     ess_ctx::Batch& B = *c->batch;
+    // the saved state and the two timing events, released on every return
+    struct Scratch {
+        hipStream_t st = nullptr;
+        float* saved = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        ~Scratch() {
+            if (saved) {
+                (void)hipStreamSynchronize(st);   // no copy still reads or writes it
+                (void)hipFree(saved);
+            }
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+        }
+    } scr;
+    scr.st = c->st;
     // keep the chains where they are: save the state, restore it afterwards
-    float* saved = nullptr;
     const size_t bytes = sizeof(float) * (B.h.back().x_off +
                                           static_cast<size_t>(B.h.back().Cp) * B.h.back().dp);
-    HIP_TRY(hipMalloc(&saved, bytes));
+    HIP_TRY(hipMalloc(&scr.saved, bytes));
+    float* const saved = scr.saved;
     HIP_TRY(hipMemcpyAsync(saved, B.X, bytes, hipMemcpyDeviceToDevice, c->st));
     const uint64_t step0 = c->step;
     bool present[kTileBuckets] = {};
     for (const auto& d : B.h) present[tile_bucket(d)] = true;
 
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventCreate(&scr.e0));
+    HIP_TRY(hipEventCreate(&scr.e1));
+    hipEvent_t e0 = scr.e0, e1 = scr.e1;
     std::ostringstream rep;
     ess_status st = ESS_OK;
     // time the current choice: capture and warm, then time a replay
@@ -1910,13 +1957,10 @@ ess_status ess_autotune(ess_ctx* c, int32_t steps_per_trial, char* report, int32
         st = trial(t);
         if (st == ESS_OK && t.us < best.us) best = t;
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     ess_status fin = apply_choice(c, st == ESS_OK ? best : before);
     if (fin == ESS_OK) fin = drop_graphs(c);
     HIP_TRY(hipMemcpyAsync(B.X, saved, bytes, hipMemcpyDeviceToDevice, c->st));
     HIP_TRY(hipStreamSynchronize(c->st));
-    (void)hipFree(saved);
     ESS_TRY(fin);
     ESS_TRY(batched_set_state_from_X(c, "ess_autotune"));
     ESS_TRY(launch_step_counter(c, c->st, step0, 0));

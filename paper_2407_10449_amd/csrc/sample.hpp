@@ -32,22 +32,23 @@
 //   their own bucket, found by comparing against the bucket's rows in float64.
 //   The survivors' candidates are then ranked by (alpha, row) and summed in
 //   ascending order.  Crowded buckets are split again (refinement, below)
-//   in the kernels for few chains and in the second attempt on a chain.
-// * full path (fallback_kernel): a bitonic sort of all crossing rows in LDS,
-//   for chains whose survivors still exceed SMAX (adversarial inputs such as
-//   many disjoint arcs spread over the circle) or when the full sort is
-//   requested.  Keys are
+//   in the kernels for few chains and beyond 4096 rows.
+// * full path (full_chain): a bitonic sort of all crossing rows in LDS, for
+//   chains whose survivors still exceed SMAX (adversarial inputs such as many
+//   disjoint arcs spread over the circle) or when the full sort is requested,
+//   done in place by the same workgroup up to 4096 rows.  Keys are
 //   alpha mapped monotonically to a 48-bit fixed-point turn fraction
-//   floor(alpha * 2^48 / 2 pi) above a 16-bit slot index, so one 64-bit
-//   compare orders them; two alphas closer than 2 pi * 2^-48 (2.2e-14 rad)
-//   may swap, which moves the union by at most their distance.
+//   floor(alpha * 2^48 / 2 pi) above a 16-bit slot (or row) index, so one
+//   64-bit compare orders them; two alphas closer than 2 pi * 2^-48
+//   (2.2e-14 rad) may swap, which moves the union by at most their distance.
 //
 // More than 4096 rows (up to 16384) take the same two paths with every pass
 // over the rows made in chunks (sample_large_kernel, fallback_large_kernel),
 // after large_roots_kernel has solved the roots over the whole device (which
 // the kernels for few chains also use above 2048 rows).
-// The quadratic comparator of Section 3.1 (likelihood testing at midpoints)
-// sits beside them (sample_midpoint_kernel).
+// The quadratic comparators sit beside them: likelihood testing at midpoints
+// (Section 3.1, sample_midpoint_kernel) and Algorithm 2's sequential
+// intersection (sample_alg2_kernel).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -416,11 +417,22 @@ struct FullLds {
     double* theta;    // [1]
 };
 
-// LARGE: only the keys live in LDS (room for 16384 rows).  They carry the row
-// index instead of a slot, and every sweep solves the row's roots again.
+// Where the sweep finds alpha and beta of the k-th key in order.
+enum FullKeys {
+    KEYS_SLOT = 0,   // alpha and beta of every crossing row in LDS, keys carry the slot
+    KEYS_ROW = 1,    // only the keys live in LDS (room for 16384 rows); they carry
+                     // the row index and every sweep solves the row's roots again
+    KEYS_ROW_AB = 2  // keys as KEYS_ROW; alpha and beta of each row come from `abg`
+                     // (one double2 per row, beta = 0 where the ellipse does not
+                     // cross), which the caller has filled
+};
+
 // BS threads (256 or 512) take part.
-template <typename T, bool LARGE = false, int BS = 256>
-__device__ void full_chain(const ChainRef<T>& r, int sel, const FullLds& L) {
+// Returns theta (the same in every thread); the caller moves the chain.
+template <typename T, int KEYS = KEYS_SLOT, int BS = 256>
+__device__ double full_chain(const ChainRef<T>& r, int sel, const FullLds& L,
+                             const double2* abg = nullptr) {
+    constexpr bool LARGE = KEYS != KEYS_SLOT;
     constexpr int NW = BS / 64;
     const int tid = threadIdx.x;
     const T* Pc = r.P0 + static_cast<size_t>(sel) * r.pstride;
@@ -430,11 +442,18 @@ __device__ void full_chain(const ChainRef<T>& r, int sel, const FullLds& L) {
         double al = 0.0, be = 0.0;
         bool hit = false;
         if (i < r.m) {
-            const T p = Pc[i], q = r.q[i];
-            hit = solve_roots<T>(static_cast<double>(p), static_cast<double>(q), r.b[i], al, be);
-            if (r.p_out) {
-                r.p_out[i] = p;
-                r.q_out[i] = q;
+            if constexpr (KEYS == KEYS_ROW_AB) {
+                const double2 v = abg[i];
+                al = v.x;
+                be = v.y;
+                hit = be > 0.0;
+            } else {
+                const T p = Pc[i], q = r.q[i];
+                hit = solve_roots<T>(static_cast<double>(p), static_cast<double>(q), r.b[i], al, be);
+                if (r.p_out) {
+                    r.p_out[i] = p;
+                    r.q_out[i] = q;
+                }
             }
         }
         int tot;
@@ -465,7 +484,11 @@ __device__ void full_chain(const ChainRef<T>& r, int sel, const FullLds& L) {
     // alpha and beta of the k-th key in order
     auto ab = [&](int k, double& a, double& bt) {
         const int s = static_cast<int>(L.key[k] & 0xFFFF);
-        if constexpr (LARGE) {
+        if constexpr (KEYS == KEYS_ROW_AB) {
+            const double2 v = abg[s];
+            a = v.x;
+            bt = v.y;
+        } else if constexpr (KEYS == KEYS_ROW) {
             solve_roots<T>(static_cast<double>(Pc[s]), static_cast<double>(r.q[s]), r.b[s], a, bt);
         } else {
             a = L.alpha[s];
@@ -597,7 +620,7 @@ __device__ void full_chain(const ChainRef<T>& r, int sel, const FullLds& L) {
         }
     }
     __syncthreads();
-    move_chain<T>(r, L.theta[0]);
+    return L.theta[0];
 }
 
 #define ESS_FULL_LDS(NMAX)                                  \
@@ -730,6 +753,17 @@ __device__ __forceinline__ void block_ab(const double2* ab, int row0, int m, dou
     }
 }
 
+// The inverse of block_ab: alpha, beta of rows row0 + tid + BS j into ab.
+template <int RPT, int BS>
+__device__ __forceinline__ void store_ab(double2* ab, int row0, int m, const double (&al)[RPT],
+                                         const double (&be)[RPT]) {
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int i = row0 + static_cast<int>(threadIdx.x) + BS * j;
+        if (i < m) ab[i] = make_double2(al[j], be[j]);
+    }
+}
+
 // G[b] = max beta of the rows in bucket b (G cleared before).
 template <int RPT, int NB>
 __device__ __forceinline__ void bucket_max_pass(BucketLds<NB>& L, const RefineMap& R,
@@ -840,9 +874,10 @@ __device__ __forceinline__ void pred_max_pass(BucketLds<NB>& L, const RefineMap&
 }
 
 // The survivors' candidates in ascending (alpha, row) order, theta by inverse
-// CDF, the optional interval output, and the move.
+// CDF and the optional interval output.  Returns theta (the same in every
+// thread); the caller moves the chain.
 template <typename T, int NB>
-__device__ __forceinline__ void finish_bucket(const ChainRef<T>& r, BucketLds<NB>& L, int S) {
+__device__ __forceinline__ double finish_bucket(const ChainRef<T>& r, BucketLds<NB>& L, int S) {
     const int tid = threadIdx.x;
     // the survivors' candidates, placed in ascending (alpha, row) order
     const double eps = r.eps;
@@ -961,7 +996,7 @@ __device__ __forceinline__ void finish_bucket(const ChainRef<T>& r, BucketLds<NB
         if (r.n_intervals) *r.n_intervals = w;
     }
     __syncthreads();
-    move_chain<T>(r, L.theta);
+    return L.theta;
 }
 
 // When more than SMAX rows survive, the survivors' buckets [blo, bhi] are
@@ -973,12 +1008,14 @@ __device__ __forceinline__ void finish_bucket(const ChainRef<T>& r, BucketLds<NB
 // state sits close to many constraints, where alpha piles up just above 0)
 // then spread over all NB buckets again.  Returns false when the survivors
 // still exceed SMAX once refinement stops (kRefineLevels levels, a level that
-// did not halve them, or a range that cannot be split): nothing has been
-// moved and the caller hands the chain to the full path.
-// With `ab`, the roots come from large_roots_kernel's output instead.
+// did not halve them, or a range that cannot be split): the caller hands the
+// chain to the full path.  On success theta holds the drawn angle and the
+// caller moves the chain.
+// With `ab`, the roots come from large_roots_kernel's output instead; with
+// `spill`, a chain handed over leaves every row's alpha and beta there.
 template <typename T, int RPT, int NB, int BS = 256, bool REFINE = false>
-__device__ bool bucket_chain(const ChainRef<T>& r, int sel, BucketLds<NB>& L,
-                             const double2* ab = nullptr) {
+__device__ bool bucket_chain(const ChainRef<T>& r, int sel, BucketLds<NB>& L, double& theta,
+                             const double2* ab = nullptr, double2* spill = nullptr) {
     static_assert(BS == 256 || BS == 512, "one chain per 256 or 512 threads");
     const int tid = threadIdx.x;
     for (int b = tid; b < NB; b += BS) {
@@ -1006,7 +1043,11 @@ __device__ bool bucket_chain(const ChainRef<T>& r, int sel, BucketLds<NB>& L,
     // Beyond overflow it also pays when survivors crowd a few buckets: every
     // row then meets all survivors of its bucket in the predecessor pass.
     // Below overflow it stops once a level no longer halves the survivors.
-    if (!REFINE && S > SMAX) return false;
+    if (!REFINE && S > SMAX) {
+        // the full sort takes over: every row's alpha and beta for it
+        if (spill) store_ab<RPT, BS>(spill, 0, r.m, al, be);
+        return false;
+    }
     int s_prev = 1 << 30;
     while (REFINE && S > kRefineTarget) {
         if (R.n == kRefineLevels || (S <= SMAX && 2 * S > s_prev)) {
@@ -1074,7 +1115,7 @@ __device__ bool bucket_chain(const ChainRef<T>& r, int sel, BucketLds<NB>& L,
     link_survivors<T, NB>(r, L, S);
     pred_max_pass<RPT, NB, BS>(L, R, al, be, 0);
     __syncthreads();
-    finish_bucket<T, NB>(r, L, S);
+    theta = finish_bucket<T, NB>(r, L, S);
     return true;
 }
 
@@ -1082,10 +1123,11 @@ __device__ bool bucket_chain(const ChainRef<T>& r, int sel, BucketLds<NB>& L,
 // path with refinement, each pass over the rows in chunks of BS RPT, reading
 // alpha and beta of every row from `ab` (16 bytes per row), which
 // large_roots_kernel filled before this launch (three passes, plus three per
-// refinement level).  Returns false, with nothing moved, as bucket_chain
+// refinement level).  Returns false, or true with theta, as bucket_chain
 // does.
 template <typename T, int RPT, int NB, int BS>
-__device__ bool bucket_chain_large(const ChainRef<T>& r, int sel, BucketLds<NB>& L, double2* ab) {
+__device__ bool bucket_chain_large(const ChainRef<T>& r, int sel, BucketLds<NB>& L, double& theta,
+                                   double2* ab) {
     const int tid = threadIdx.x;
     constexpr int CH = BS * RPT;
     for (int b = tid; b < NB; b += BS) {
@@ -1188,30 +1230,71 @@ __device__ bool bucket_chain_large(const ChainRef<T>& r, int sel, BucketLds<NB>&
         pred_max_pass<RPT, NB, BS>(L, R, al, be, c0);
     }
     __syncthreads();
-    finish_bucket<T, NB>(r, L, S);
+    theta = finish_bucket<T, NB>(r, L, S);
     return true;
 }
 
+// LDS of the bucket kernels for many chains: the bucket path's arrays or, for
+// a chain the bucket path hands back, the keys of the full sort done in
+// place.  The keys carry the row index and every sweep solves the row's
+// roots again (as beyond 4096 rows), so the union is no larger than the
+// bucket arrays up to 2048 rows and occupancy is unchanged.
+template <int NB, int NK>
+struct BucketOrKeys {
+    union {
+        BucketLds<NB> bucket;
+        uint64_t key[NK];
+    };
+    double red[8];
+    int cnt[8];
+    double bcast[2];
+    int kstar;
+    double theta[2];
+};
+
 template <typename T, int RPT, int NB, int BS = 256, bool REFINE = false, bool PRE = false>
 __global__ __launch_bounds__(BS, (BS == 512 && RPT <= 4 && !REFINE) ? 8 : 1) void sample_bucket_kernel(SampleArgs a) {
-    __shared__ BucketLds<NB> lds;
     const int c = a.c0 + blockIdx.x;
     const ChainRef<T> r = make_ref<T>(a, c);
     const int sel = a.has_pending ? commit_chain<T>(r) : *r.sel;
-    const uint32_t step = r.step;
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.fb_count[(step + 1) & 1] = 0;   // next step's list
-    // PRE: large_roots_kernel has solved this step's roots into a.ab
-    const double2* ab = PRE ? static_cast<const double2*>(a.ab) + static_cast<size_t>(c) * a.mp : nullptr;
-    const bool done = !a.force_full && bucket_chain<T, RPT, NB, BS, REFINE>(r, sel, lds, ab);
     if constexpr (REFINE) {
-        // the variant for few chains sorts a chain it could not resolve in
-        // place, so its launch needs no second kernel
+        // the variants for few chains refine crowded buckets and keep alpha
+        // and beta of a chain they sort in LDS (occupancy does not matter
+        // with no more chains than compute units)
+        __shared__ BucketLds<NB> lds;
+        // PRE: large_roots_kernel has solved this step's roots into a.ab
+        const double2* ab = PRE ? static_cast<const double2*>(a.ab) + static_cast<size_t>(c) * a.mp : nullptr;
+        double theta = 0.0;
+        const bool done = !a.force_full && bucket_chain<T, RPT, NB, BS, true>(r, sel, lds, theta, ab);
         if (!done) {
             ESS_FULL_LDS(RPT * BS)
-            full_chain<T, false, BS>(r, sel, full_lds);
+            theta = full_chain<T, KEYS_SLOT, BS>(r, sel, full_lds);
         }
+        move_chain<T>(r, theta);
     } else {
-        if (!done && threadIdx.x == 0) a.fb_list[atomicAdd(a.fb_count + (step & 1), 1)] = c;
+        // a chain whose survivors overflow (or every chain, with the full
+        // sort requested) is sorted in place by the same workgroup, so no
+        // second launch follows.  Its roots go to the chain's row of a.ab
+        // first, so the full sort reads them instead of solving them again
+        // (which would hold the kernel's registers above the bucket path's).
+        constexpr int NK = RPT * BS > 512 ? RPT * BS : 512;
+        __shared__ BucketOrKeys<NB, NK> lds;
+        double2* abg = static_cast<double2*>(a.ab) + static_cast<size_t>(c) * a.mp;
+        bool done = false;
+        double theta = 0.0;
+        if (!a.force_full) {
+            done = bucket_chain<T, RPT, NB, BS, false>(r, sel, lds.bucket, theta, nullptr, abg);
+        } else {
+            double al[RPT], be[RPT];
+            block_roots<T, RPT, BS>(r, r.P0 + static_cast<size_t>(sel) * r.pstride, 0, true, al, be);
+            store_ab<RPT, BS>(abg, 0, r.m, al, be);
+        }
+        if (!done) {
+            __syncthreads();   // every row's alpha and beta is in a.ab
+            const FullLds L{nullptr, nullptr, lds.key, lds.red, lds.cnt, lds.bcast, &lds.kstar, lds.theta};
+            theta = full_chain<T, KEYS_ROW_AB, BS>(r, sel, L, abg);
+        }
+        move_chain<T>(r, theta);
     }
 }
 
@@ -1404,6 +1487,142 @@ __global__ __launch_bounds__(256) void sample_midpoint_kernel(SampleArgs a) {
     midpoint_chain<T>(r, sel, lds);
 }
 
+// ---------------------------------------------------------------------------
+// Comparator: Algorithm 2, the active set by its definition.  Starting from
+// [0, 2 pi], the set is intersected with I_i = [0, alpha_i] U [beta_i, 2 pi]
+// one row at a time, in row order: every piece [l, h] leaves
+// [l, min(h, alpha_i)] and [max(l, beta_i), h].  Pieces of zero length are
+// dropped where they appear (they carry no length, and no later
+// intersection can lengthen them), and a row the ellipse does not cross
+// (I_i the whole circle) leaves the set as it is.  The arc (alpha_i, beta_i)
+// splits at most one piece, so the list holds at most m + 1 pieces; the work
+// per row is linear in their number, O(m^2) at worst (Appendix D's input).
+// The pieces come out in ascending order, the same non-empty intervals as
+// Algorithm 3's candidates, and theta is drawn from them in the same way.
+// One wave per chain; the list lives in LDS as two buffers of m + 2 pieces
+// (dynamic shared memory).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(64) void sample_alg2_kernel(SampleArgs a) {
+    extern __shared__ double2 alg2_lists[];
+    __shared__ double s_theta;
+    const int lane = threadIdx.x;
+    const int c = a.c0 + blockIdx.x;
+    const ChainRef<T> r = make_ref<T>(a, c);
+    const int sel = a.has_pending ? commit_chain<T>(r) : *r.sel;
+    const T* Pc = r.P0 + static_cast<size_t>(sel) * r.pstride;
+    double2* cur = alg2_lists;
+    double2* nxt = alg2_lists + (r.m + 2);
+    if (lane == 0) cur[0] = make_double2(0.0, kTwoPi);
+    int n = 1;   // pieces in cur (the same in every lane)
+    __syncthreads();
+    for (int i0 = 0; i0 < r.m; i0 += 64) {
+        // the roots of 64 rows at once, then the rows one after another
+        const int i = i0 + lane;
+        double al = 0.0, be = 0.0;
+        if (i < r.m) {
+            const T p = Pc[i], q = r.q[i];
+            double x0, x1;
+            if (solve_roots<T>(static_cast<double>(p), static_cast<double>(q), r.b[i], x0, x1)) {
+                al = x0;
+                be = x1;
+            }
+            if (r.p_out) {
+                r.p_out[i] = p;
+                r.q_out[i] = q;
+            }
+        }
+        const int rows = min(64, r.m - i0);
+        for (int j = 0; j < rows; ++j) {
+            const double aj = __shfl(al, j, 64), bj = __shfl(be, j, 64);
+            if (!(bj > 0.0)) continue;   // no crossing: I_j is the whole circle
+            int total = 0;
+            for (int k0 = 0; k0 < n; k0 += 64) {
+                const int k = k0 + lane;
+                const double2 v = k < n ? cur[k] : make_double2(0.0, 0.0);
+                const double h1 = fmin(v.y, aj), l2 = fmax(v.x, bj);
+                const bool p1 = k < n && h1 > v.x;
+                const bool p2 = k < n && v.y > l2;
+                const int cnt = static_cast<int>(p1) + static_cast<int>(p2);
+                int incl = cnt;   // inclusive prefix sum of the counts over the wave
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int y = __shfl_up(incl, o, 64);
+                    if (lane >= o) incl += y;
+                }
+                const int pos = total + incl - cnt;
+                if (p1) nxt[pos] = make_double2(v.x, h1);
+                if (p2) nxt[pos + (p1 ? 1 : 0)] = make_double2(l2, v.y);
+                total += __shfl(incl, 63, 64);
+            }
+            n = total;
+            double2* t = cur;
+            cur = nxt;
+            nxt = t;
+            __syncthreads();
+        }
+    }
+    // trim real ends by eps, theta by inverse CDF over the pieces in order
+    if (lane == 0) {
+        const double eps = r.eps;
+        auto piece = [&](int k, double& lo, double& hi) {
+            lo = cur[k].x;
+            hi = cur[k].y;
+            if (lo > 0.0) lo += eps;
+            if (hi < kTwoPi) hi -= eps;
+        };
+        double total = 0.0;
+        for (int k = 0; k < n; ++k) {
+            double lo, hi;
+            piece(k, lo, hi);
+            total += fmax(hi - lo, 0.0);
+        }
+        double theta = 0.0;
+        if (total > 0.0) {
+            const double sv = theta_uniform(r) * total;
+            double run = 0.0;
+            int last = -1;
+            bool found = false;
+            for (int k = 0; k < n; ++k) {
+                double lo, hi;
+                piece(k, lo, hi);
+                const double len = fmax(hi - lo, 0.0);
+                if (len > 0.0) {
+                    last = k;
+                    if (!found && run + len > sv) {
+                        theta = fmax(lo, fmin(lo + (sv - run), hi));
+                        found = true;
+                    }
+                }
+                run += len;
+            }
+            if (!found) {   // rounding put s at the total
+                double lo, hi;
+                piece(last, lo, hi);
+                theta = hi;
+            }
+        } else {
+            *r.flag = 1;   // empty active set: stay, counted as a rejection
+        }
+        if (r.intervals) {
+            int w = 0;
+            for (int k = 0; k < n; ++k) {
+                double lo, hi;
+                piece(k, lo, hi);
+                if (hi - lo > 0.0) {
+                    r.intervals[2 * w] = lo;
+                    r.intervals[2 * w + 1] = hi;
+                    ++w;
+                }
+            }
+            if (r.n_intervals) *r.n_intervals = w;
+        }
+        s_theta = theta;
+    }
+    __syncthreads();
+    move_chain<T>(r, s_theta);
+}
+
 // Rows beyond 4096: 512 threads per chain, the chunked bucket path with
 // refinement; chains it cannot resolve go to the full sort of keys only.
 constexpr int kMaxRowsLarge = 16384;
@@ -1446,8 +1665,10 @@ __global__ __launch_bounds__(512) void sample_large_kernel(SampleArgs a) {
     const uint32_t step = r.step;
     if (blockIdx.x == 0 && threadIdx.x == 0) a.fb_count[(step + 1) & 1] = 0;   // next step's list
     double2* ab = static_cast<double2*>(a.ab) + static_cast<size_t>(c) * a.mp;
-    const bool done = !a.force_full && bucket_chain_large<T, 8, 2048, 512>(r, sel, lds, ab);
-    if (!done && threadIdx.x == 0) a.fb_list[atomicAdd(a.fb_count + (step & 1), 1)] = c;
+    double theta = 0.0;
+    const bool done = !a.force_full && bucket_chain_large<T, 8, 2048, 512>(r, sel, lds, theta, ab);
+    if (done) move_chain<T>(r, theta);
+    else if (threadIdx.x == 0) a.fb_list[atomicAdd(a.fb_count + (step & 1), 1)] = c;
 }
 
 template <typename T>
@@ -1462,26 +1683,7 @@ __global__ __launch_bounds__(256) void fallback_large_kernel(SampleArgs a) {
     const int count = a.fb_count[abs_step(a) & 1];
     for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
         const ChainRef<T> r = make_ref<T>(a, a.fb_list[idx]);
-        full_chain<T, true>(r, *r.sel, L);
-        __syncthreads();
-    }
-}
-
-// Chains the bucket kernel handed over (a.fb_list[0 .. fb_count[step & 1])),
-// processed by a grid-stride loop: first the bucket path with refinement of
-// crowded buckets, then, if that still leaves too many survivors (or the full
-// path is requested), the full sort.  The bucket kernel of the next step
-// clears this count; the host clears both counts when a call starts.
-template <typename T, int NMAX>
-__global__ __launch_bounds__(256) void fallback_kernel(SampleArgs a) {
-    ESS_FULL_LDS(NMAX)
-    __shared__ BucketLds<2048> blds;
-    const int count = a.fb_count[abs_step(a) & 1];
-    for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
-        const ChainRef<T> r = make_ref<T>(a, a.fb_list[idx]);
-        const int sel = *r.sel;
-        if (a.force_full || !bucket_chain<T, NMAX / 256, 2048, 256, true>(r, sel, blds))
-            full_chain<T>(r, sel, full_lds);
+        move_chain<T>(r, full_chain<T, KEYS_ROW>(r, *r.sel, L));
         __syncthreads();
     }
 }
