@@ -157,17 +157,25 @@ def random_small(rng, d, m, n_chains=4):
 
 
 def random_states(rng, A, b, n, scale=1.0, margin=1e-3):
-    """n points strictly inside {A x <= b} (rejection from N(0, scale^2 I)).
+    """n points strictly inside {A x <= b} (needs b > margin, so that 0 is inside).
 
-    Falls back to shrinking toward 0 (feasible when b > 0)."""
+    Each point is a draw x ~ N(0, scale^2 I), kept as it is when it clears
+    every constraint by `margin`, else pulled toward 0 along its own
+    direction to a uniform fraction in [0.2, 0.9] of the distance at which it
+    would reach the first constraint (less margin): a generic interior point
+    in a random direction, never 0 itself."""
+    A = np.asarray(A, np.float64)
+    b = np.asarray(b, np.float64)
+    assert (b > margin).all(), "0 must clear every constraint by the margin"
     d = A.shape[1]
     out = np.empty((n, d))
     for i in range(n):
-        for _ in range(1000):
-            x = scale * rng.standard_normal(d)
-            if (A @ x <= b - margin).all():
-                break
-        else:
-            x = np.zeros(d)
-        out[i] = x
+        x = scale * rng.standard_normal(d)
+        ax = A @ x
+        if (ax <= b - margin).all():
+            out[i] = x
+            continue
+        pos = ax > 0
+        t_max = np.min((b[pos] - margin) / ax[pos])
+        out[i] = rng.uniform(0.2, 0.9) * t_max * x
     return out

@@ -38,30 +38,78 @@ def fp32_dot_bound(A, x):
     return 2 * d * 2.0 ** -24 * (np.abs(A) @ np.abs(x).T).T   # (C, m)
 
 
+def _state_check(A, b, c, x_gpu, rejected_gpu, ref, tol_x):
+    """Chain c's accept/reject decision and new state against the oracle's
+    transition `ref`: returns ("fail" message | None, excused)."""
+    rg, rr = bool(rejected_gpu), bool(ref["rejected"][c])
+    if rg != rr:
+        xp = ref["x_prop"][c]
+        slack = (b[c] if np.ndim(b) == 2 else b) - A @ xp
+        # float32 dot-product rounding plus the state tolerance below
+        bound = fp32_dot_bound(A, xp[None, :])[0] + tol_x * (np.abs(A) @ np.maximum(np.abs(xp), 1.0))
+        if np.any(np.abs(slack) <= bound):
+            return None, True
+        return f"chain {c}: rejected gpu={rg} ref={rr}, min slack {slack.min():.3e}", False
+    xr = ref["x_new"][c]
+    err = np.max(np.abs(x_gpu - xr))
+    if err > tol_x * max(1.0, np.max(np.abs(xr))):
+        return f"chain {c}: |dx| = {err:.3e}", False
+    return None, False
+
+
 def compare_transition(A, b, x, nu, u, gpu, ref, tol_ang=TOL_ANG, tol_x=TOL_X):
     """Returns (failures, n_excused) for one explicit transition."""
     fails = []
     excused = 0
-    C = x.shape[0]
     n_int = gpu["n_intervals"]
-    for c in range(C):
+    for c in range(x.shape[0]):
         gi = pieces(gpu["intervals"][c], n_int[c], 0.0)
         if not intervals_match(gi, ref["intervals"][c], tol_ang):
             fails.append(f"chain {c}: intervals {gi[:4]} vs {ref['intervals'][c][:4]}")
             continue
-        rg, rr = bool(gpu["rejected"][c]), bool(ref["rejected"][c])
-        if rg != rr:
-            xp = ref["x_prop"][c]
-            slack = (b[c] if np.ndim(b) == 2 else b) - A @ xp
-            # float32 dot-product rounding plus the state tolerance below
-            bound = fp32_dot_bound(A, xp[None, :])[0] + tol_x * (np.abs(A) @ np.maximum(np.abs(xp), 1.0))
-            if np.any(np.abs(slack) <= bound):
-                excused += 1
-                continue
-            fails.append(f"chain {c}: rejected gpu={rg} ref={rr}, min slack {slack.min():.3e}")
-            continue
-        xr = ref["x_new"][c]
-        err = np.max(np.abs(gpu["x_new"][c] - xr))
-        if err > tol_x * max(1.0, np.max(np.abs(xr))):
-            fails.append(f"chain {c}: |dx| = {err:.3e}")
+        msg, exc = _state_check(A, b, c, gpu["x_new"][c], gpu["rejected"][c], ref, tol_x)
+        excused += exc
+        if msg:
+            fails.append(msg)
     return fails, excused
+
+
+def compare_states(A, b, x_new, rejected, ref, tol_x=TOL_X):
+    """The state part of a transition (the accept/reject decision and the new
+    x) for every chain.  Returns (failures, n_excused)."""
+    fails = []
+    excused = 0
+    for c in range(x_new.shape[0]):
+        msg, exc = _state_check(A, b, c, x_new[c], rejected[c], ref, tol_x)
+        excused += exc
+        if msg:
+            fails.append(msg)
+    return fails, excused
+
+
+def chain_states(A, b, n, store, x0=None, seed=20240714, pool=32, burn=3, span=8):
+    """n strictly interior states of {A x <= b} taken from float64 oracle
+    chains (Algorithm 1 run from x0, default 0, for burn + span steps; the
+    states after the burn-in).  Rows of A and the states are rounded to
+    `store`, as the code under test holds them, and every kept state clears
+    each constraint by four times the float32 rounding bound of its dot
+    product, so a float32 check cannot call it infeasible.  States are
+    shuffled and repeated to fill n rows."""
+    from oracle import ess as ref_ess
+
+    A_s = np.asarray(A, np.float64).astype(store).astype(np.float64)
+    b = np.asarray(b, np.float64)
+    d = A_s.shape[1]
+    x0 = np.zeros(d) if x0 is None else np.asarray(x0, np.float64)
+    eps = 1e-6 if store == np.float32 else 0.0
+    tr, _, _ = ref_ess.run(A_s, b, x0, pool, burn + span, seed, eps=eps, store=store)
+    cand = tr[burn:].reshape(-1, d)
+    slack = b[None, :] - cand @ A_s.T
+    ok = (slack > 4.0 * fp32_dot_bound(A_s, cand) + 1e-12).all(axis=1)
+    ok &= np.abs(cand).max(axis=1) > 0.0
+    cand = cand[ok]
+    assert len(cand) >= min(n, pool), f"only {len(cand)} usable chain states"
+    rng = np.random.default_rng(seed)
+    cand = cand[rng.permutation(len(cand))]
+    reps = -(-n // len(cand))
+    return np.tile(cand, (reps, 1))[:n].astype(store)

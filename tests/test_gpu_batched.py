@@ -6,6 +6,8 @@ import pytest
 
 import synth
 from oracle import ess as ref_ess
+from oracle import philox as ref_philox
+from parity import compare_states
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -30,21 +32,37 @@ def problems(n, chains, seed=4):
             for i, p in enumerate(probs)]
 
 
-def test_batched_matches_oracle_first_steps(E):
-    """Each problem's chains follow the oracle's Philox stream (problem word p)."""
+def test_batched_matches_oracle_per_step(E):
+    """Every chain of every problem, one step at a time: from the state the
+    batch reached, the oracle's transition with the step's Philox draws
+    (problem word p) gives the decision and the new state to 1e-5.  Four
+    steps, so the states are generic mid-chain states after the first."""
     probs = problems(10, 16)
     say("[batched] shapes", [(p["A"].shape, p["n_chains"]) for p in probs])
     s = E.BatchedSampler(probs)
-    T = 3
-    tr, _ = s.run(T)
-    per = s.split(tr.cpu().numpy())
-    s.close()
-    for p, (pr, g) in enumerate(zip(probs, per)):
-        rtr, _, _ = ref_ess.run(pr["A"].astype(np.float32).astype(np.float64), pr["b"], pr["x0"],
-                                pr["n_chains"], T, seed=pr["seed"], eps=1e-6, store=np.float32,
-                                problem=p)
-        err = np.abs(g - rtr).max(axis=(0, 2))
-        assert (err < 1e-4).mean() >= 0.9, (p, np.sort(err)[-4:])
+    x_prev = [x.astype(np.float64) for x in s.split(s.state()[0].cpu().numpy())]
+    rej_prev = s.rejections()
+    starts = np.cumsum([0] + [p["n_chains"] for p in probs])
+    excused = 0
+    for t in range(4):
+        _, step = s.state()
+        s.run(1, keep_trace=False)
+        x_next = [x.astype(np.float64) for x in s.split(s.state()[0].cpu().numpy())]
+        rej = s.rejections()
+        for p, pr in enumerate(probs):
+            C, d = pr["n_chains"], pr["A"].shape[1]
+            A32 = pr["A"].astype(np.float32).astype(np.float64)
+            ch = np.arange(C)
+            nu = ref_philox.normals(pr["seed"], step, ch, d, problem=p).astype(np.float32)
+            u = ref_philox.uniforms(pr["seed"], step, ch, problem=p)
+            ref = ref_ess.transition(A32, pr["b"], x_prev[p], nu.astype(np.float64), u,
+                                     eps=pr["trim_eps"], store=np.float32)
+            rj = (rej - rej_prev)[starts[p]:starts[p + 1]]
+            fails, exc = compare_states(A32, pr["b"], x_next[p], rj, ref)
+            assert not fails, (t, p, fails[:5])
+            excused += exc
+        x_prev, rej_prev = x_next, rej
+    assert excused <= 2
 
 
 def test_batched_checkpoint_and_determinism(E):

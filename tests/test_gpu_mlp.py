@@ -43,12 +43,15 @@ def test_forward_and_gradients_match_reference(E, widths, B):
     scale = np.abs(r_out).max()
     assert np.abs(out - r_out).max() <= 1e-2 * scale
     assert abs(loss - ref.mse(r_out, y)) <= 1e-2 * ref.mse(r_out, y)
-    flat_ref = np.concatenate([np.concatenate([gW.ravel(), gc]) for gW, gc in r_grads])
+    # every gradient element: within 1e-2 of its layer's largest gradient
+    # (weights and biases separately); bfloat16 operands are identical on
+    # both sides, so only float32 against float64 accumulation and the
+    # rounding of recomputed activations to bfloat16 differ
     for (W, c), (gW, gc), off in zip(params, r_grads, np.cumsum([0] + [W.size + c.size for W, c in params])[:-1]):
         gw = g[off:off + W.size]
-        assert np.linalg.norm(gw - gW.ravel()) <= 1e-2 * np.linalg.norm(gW), off
+        assert np.abs(gw - gW.ravel()).max() <= 1e-2 * np.abs(gW).max(), off
         gb = g[off + W.size: off + W.size + c.size]
-        assert np.linalg.norm(gb - gc) <= 1e-2 * np.linalg.norm(gc) + 1e-7
+        assert np.abs(gb - gc).max() <= 1e-2 * np.abs(gc).max() + 1e-7, off
     net.close()
 
 

@@ -8,7 +8,8 @@ import pytest
 import synth
 from oracle import ess as ref_ess
 from oracle import philox as ref_philox
-from parity import TOL_ANG, compare_transition, pieces, intervals_match
+from parity import (TOL_ANG, chain_states, compare_states, compare_transition, pieces,
+                    intervals_match)
 
 pytestmark = pytest.mark.gpu
 
@@ -28,11 +29,13 @@ def say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def explicit_case(E, A, b, C, precision, seed, eps, n_ref=None, rng_seed=0):
+def explicit_case(E, A, b, C, precision, seed, eps, n_ref=None, rng_seed=0, x0=None):
     """One explicit transition on the GPU and in the oracle on identical inputs."""
     rng = np.random.default_rng(rng_seed)
     npdt = np.float32 if precision == 32 else np.float64
-    x = synth.random_states(rng, A, b, C, scale=0.7, margin=1e-3).astype(npdt)
+    # generic mid-chain states (x = 0 would make every p = a_i^T x zero)
+    x = chain_states(A, b, C, npdt, x0=x0, seed=rng_seed)
+    assert (np.abs(x).max(axis=1) == 0).mean() <= 0.05
     nu = rng.standard_normal(x.shape).astype(npdt)
     u = rng.uniform(size=C)
     s = E.Sampler(A, b, x, C, seed=seed, precision=precision, trim_eps=eps)
@@ -78,14 +81,15 @@ LARGE = [c for c in CASES if c[0].startswith("large_m")]
 def test_explicit_transition_matches_oracle(E, name, d, m, C, precision, eps):
     say(f"[explicit] {name} d={d} m={m} C={C} prec={precision}")
     rng = np.random.default_rng(d * 7 + m)
+    x0 = None
     if name.startswith("univariate"):
         pr = synth.univariate(-1.0, 3.0)
-        A, b = pr.A, pr.b
+        A, b, x0 = pr.A, pr.b, pr.x0
     else:
         A = rng.standard_normal((m, d)) / math.sqrt(d)
         b = rng.uniform(0.5, 1.5, m)
     Ab, x, nu, u, g, ref, ref2 = explicit_case(E, A, b, C, precision, seed=5, eps=eps,
-                                               n_ref=min(C, 96), rng_seed=m)
+                                               n_ref=min(C, 96), rng_seed=m, x0=x0)
     fails, excused = compare_transition(Ab, b, x, nu, u, g, ref)
     assert not fails, "\n".join(fails[:10])
     assert excused <= max(1, len(u) // 20)
@@ -133,16 +137,20 @@ def test_near_tangent_rows_cross_both_root_branches(E):
 
 
 def test_explicit_full_size_gp_rbf(E):
-    """d=1000, m=2000, 1024 chains (the benchmarked shape): sampled chains."""
+    """d=1000, m=2000, 1024 chains (the benchmarked shape and kernel), from
+    mid-chain states: 128 sampled chains, tier 1 and tier 2."""
     say("[explicit] gp_rbf full size")
     pr = synth.gp_rbf()
     Ab, x, nu, u, g, ref, ref2 = explicit_case(E, pr.A, pr.b, pr.n_chains, 32, seed=0, eps=1e-6,
-                                               n_ref=24, rng_seed=3)
+                                               n_ref=128, rng_seed=3)
+    assert len(np.unique(x, axis=0)) >= 100
     fails, excused = compare_transition(Ab, pr.b, x, nu, u, g, ref)
     assert not fails, "\n".join(fails[:10])
+    assert excused <= 3
     for c in range(len(u)):
         gi = pieces(g["intervals"][c], g["n_intervals"][c], 0.0)
-        assert intervals_match(gi, ref2["intervals"][c], 1e-5)
+        assert intervals_match(gi, ref2["intervals"][c], 1e-5), (c, gi, ref2["intervals"][c])
+        assert abs(g["theta"][c] - ref2["theta"][c]) <= 1e-5 * max(1.0, len(gi)), c
 
 
 def test_no_constraint_crosses_the_ellipse(E):
@@ -261,16 +269,45 @@ def test_run_matches_oracle_fp64(E):
     s.close()
 
 
-def test_run_matches_oracle_fp32_first_steps(E):
-    pr = synth.box_halfspace(n_chains=256)
-    T = 4
-    s = E.Sampler(pr.A, pr.b, pr.x0, pr.n_chains, seed=0, precision=32, trim_eps=1e-6)
-    tr, _ = s.run(T)
-    tr = tr.cpu().numpy()
-    rtr, _, _ = ref_ess.run(pr.A, pr.b, pr.x0, pr.n_chains, T, seed=0, eps=1e-6, store=np.float32)
-    err = np.abs(tr - rtr).max(axis=(0, 2))
-    ok = err < 1e-4
-    assert ok.mean() > 0.98, np.sort(err)[-10:]
+def run_step_by_step(E, s, A, b, seed, T, idx, eps, store=np.float32):
+    """T single-step runs of sampler s; after each, the sampled chains idx are
+    compared with one oracle transition from the GPU's previous state with
+    the step's Philox draws (so errors cannot accumulate): the decision and
+    the new state to 1e-5.  Returns the number of excused decisions."""
+    C, d = s.n_chains, s.d
+    A_s = np.asarray(A, np.float64).astype(store).astype(np.float64)
+    x_prev = s.state()[0].cpu().numpy().astype(np.float64)
+    rej_prev = s.rejections()
+    excused = 0
+    moved = 0
+    for t in range(T):
+        _, step = s.state()
+        s.run(1, keep_trace=False)
+        x_next = s.state()[0].cpu().numpy().astype(np.float64)
+        rej = s.rejections()
+        nu = ref_philox.normals(seed, step, idx, d).astype(store).astype(np.float64)
+        u = ref_philox.uniforms(seed, step, idx)
+        ref = ref_ess.transition(A_s, b, x_prev[idx], nu, u, eps=eps, store=store)
+        fails, exc = compare_states(A_s, b, x_next[idx], (rej - rej_prev)[idx], ref)
+        assert not fails, (t, fails[:10])
+        excused += exc
+        moved += int((x_next[idx] != x_prev[idx]).any(axis=1).sum())
+        x_prev, rej_prev = x_next, rej
+    assert moved >= 0.9 * T * len(idx)
+    return excused
+
+
+@pytest.mark.parametrize("workload,C", [("box_halfspace", 300), ("gp_rbf", 1024)])
+def test_run_matches_oracle_fp32_per_step(E, workload, C):
+    """The production run path (graph replay, more than 256 chains, so the
+    kernels tuned for occupancy; gp_rbf is the benchmarked shape and kernel),
+    checked one step at a time from the states it reached."""
+    say(f"[run] per-step {workload} C={C}")
+    pr = getattr(synth, workload)(n_chains=C)
+    s = E.Sampler(pr.A, pr.b, pr.x0, C, seed=0, precision=32, trim_eps=1e-6)
+    idx = np.linspace(0, C - 1, 96).astype(int)
+    excused = run_step_by_step(E, s, pr.A, pr.b, 0, 4, idx, 1e-6)
+    assert excused <= 2
     s.close()
 
 
@@ -487,40 +524,51 @@ def test_section_4_2_at_d_8000(E):
 
 
 MID_CASES = [
-    # name, d, m, C, precision, eps
-    ("mid_ragged_f32", 37, 150, 40, 32, 1e-6),
-    ("mid_f64", 20, 300, 16, 64, 0.0),
-    ("mid_m2000_f32", 40, 2000, 8, 32, 1e-6),
-    ("mid_max_m_f32", 30, 4096, 3, 32, 1e-6),
+    # method, name, d, m, C, precision, eps
+    ("midpoint", "mid_ragged_f32", 37, 150, 40, 32, 1e-6),
+    ("midpoint", "mid_f64", 20, 300, 16, 64, 0.0),
+    ("midpoint", "mid_m2000_f32", 40, 2000, 8, 32, 1e-6),
+    ("midpoint", "mid_max_m_f32", 30, 4096, 3, 32, 1e-6),
+    ("alg2", "alg2_ragged_f32", 37, 150, 40, 32, 1e-6),
+    ("alg2", "alg2_f64", 20, 300, 16, 64, 0.0),
+    ("alg2", "alg2_many_m1000_f32", 40, 1000, 300, 32, 1e-6),
+    ("alg2", "alg2_m2000_f32", 40, 2000, 8, 32, 1e-6),
+    ("alg2", "alg2_max_m_f64", 30, 4096, 3, 64, 0.0),
 ]
 
 
-@pytest.mark.parametrize("name,d,m,C,precision,eps", MID_CASES, ids=[c[0] for c in MID_CASES])
-def test_midpoint_comparator_matches_oracle_and_alg3(E, name, d, m, C, precision, eps):
-    """Section 3.1's likelihood testing at midpoints (the quadratic
-    comparator) finds the same pieces as Algorithm 3 from the same
-    projections, and agrees with the oracle's midpoint method."""
-    say(f"[midpoint] {name} d={d} m={m} C={C} prec={precision}")
+@pytest.mark.parametrize("method,name,d,m,C,precision,eps", MID_CASES, ids=[c[1] for c in MID_CASES])
+def test_quadratic_comparators_match_oracle_and_alg3(E, method, name, d, m, C, precision, eps):
+    """The quadratic comparators, Section 3.1's likelihood testing at
+    midpoints and Algorithm 2's sequential intersection, find the same
+    pieces as Algorithm 3 from the same projections, and agree with the
+    oracle's version of the same method."""
+    say(f"[{method}] {name} d={d} m={m} C={C} prec={precision}")
     rng = np.random.default_rng(d * 5 + m)
     A = rng.standard_normal((m, d)) / math.sqrt(d)
     b = rng.uniform(0.5, 1.5, m)
     npdt = np.float32 if precision == 32 else np.float64
-    x = synth.random_states(rng, A, b, C, scale=0.7, margin=1e-3).astype(npdt)
+    x = chain_states(A, b, C, npdt, seed=m)
     nu = rng.standard_normal(x.shape).astype(npdt)
     u = rng.uniform(size=C)
     outs = {}
-    for method in ("alg3", "midpoint"):
-        s = E.Sampler(A, b, x, C, seed=5, precision=precision, trim_eps=eps, method=method)
-        outs[method] = {k: v.cpu().numpy() for k, v in s.transition_explicit(x, nu, u).items()}
+    for meth in ("alg3", method):
+        s = E.Sampler(A, b, x, C, seed=5, precision=precision, trim_eps=eps, method=meth)
+        outs[meth] = {k: v.cpu().numpy() for k, v in s.transition_explicit(x, nu, u).items()}
         s.close()
-    a, g = outs["alg3"], outs["midpoint"]
+    a, g = outs["alg3"], outs[method]
     assert np.array_equal(a["n_intervals"], g["n_intervals"])
-    assert np.abs(a["intervals"] - g["intervals"]).max() <= 1e-13
-    assert np.abs(a["theta"] - g["theta"]).max() <= 1e-12
+    # float64: the same roots bit for bit.  float32: each kernel inlines its
+    # own copy of the float32 atan2 / acos away from tangency, and the compiler
+    # may contract them differently, so an angle can differ by a float ulp
+    # (up to 2.4e-7 rad below pi)
+    tol_same = 1e-13 if precision == 64 else 1e-6
+    assert np.abs(a["intervals"] - g["intervals"]).max() <= tol_same
+    assert np.abs(a["theta"] - g["theta"]).max() <= 10 * tol_same
     assert np.array_equal(a["rejected"], g["rejected"])
     Ab = A.astype(npdt).astype(np.float64)
     ref = ref_ess.transition(Ab, b, x.astype(np.float64), nu.astype(np.float64), u, eps=eps,
-                             store=npdt, pq=(g["pq"][0], g["pq"][1]), method="midpoint")
+                             store=npdt, pq=(g["pq"][0], g["pq"][1]), method=method)
     # the root solve's rounding bounds the rest, as in the Algorithm 3 parity
     # cases: float64 trig in float64 mode, float32 trig away from tangency
     tol2 = 1e-9 if precision == 64 else 1e-5
@@ -530,13 +578,28 @@ def test_midpoint_comparator_matches_oracle_and_alg3(E, name, d, m, C, precision
         assert abs(g["theta"][c] - ref["theta"][c]) <= tol2 * max(1.0, len(gi)), c
 
 
+@pytest.mark.parametrize("method", ["midpoint", "alg2"])
 @pytest.mark.parametrize("precision", [32, 64])
-def test_midpoint_comparator_on_the_sorting_reduction(E, precision):
-    """Section 3.1's reduction (100 disjoint arcs) through the comparator."""
+def test_comparators_on_the_sorting_reduction(E, precision, method):
+    """Section 3.1's reduction (100 disjoint arcs) through the comparators."""
     rng = np.random.default_rng(23)
     c = 0.1 + 5.9 * (np.arange(100) + rng.uniform(0.2, 0.4, 100)) / 100
-    Ab, b, x, nu, u, g, ref = run_arcs(E, c, c + 0.005, precision, method="midpoint")
+    Ab, b, x, nu, u, g, ref = run_arcs(E, c, c + 0.005, precision, method=method)
     assert (g["n_intervals"] == 101).all(), g["n_intervals"]
+    fails, _ = compare_transition(Ab, b, x, nu, u, g, ref)
+    assert not fails, fails[:5]
+
+
+@pytest.mark.parametrize("precision,m", [(32, 7), (64, 14)])
+def test_alg2_on_appendix_d_worst_case(E, precision, m):
+    """Appendix D's input, I_i = [0, 3^-i] U [2 3^-i, 1] scaled by 2 pi and
+    placed at pi / 2: Algorithm 2's list grows by one piece per row and ends
+    with all m + 1 intervals, as Algorithm 3 finds them."""
+    i = np.arange(1, m + 1)
+    al = 2 * np.pi * 3.0 ** -i
+    Ab, b, x, nu, u, g, ref = run_arcs(E, 0.5 * np.pi + al, 0.5 * np.pi + 2 * al, precision,
+                                       method="alg2")
+    assert (g["n_intervals"] == m + 1).all(), g["n_intervals"]
     fails, _ = compare_transition(Ab, b, x, nu, u, g, ref)
     assert not fails, fails[:5]
 
@@ -583,7 +646,7 @@ def test_full_sort_path_matches_bucket_path(E, name, d, m, C, precision, eps):
     A = rng.standard_normal((m, d)) / math.sqrt(d)
     b = rng.uniform(0.5, 1.5, m)
     npdt = np.float32 if precision == 32 else np.float64
-    x = synth.random_states(rng, A, b, C, scale=0.7, margin=1e-3).astype(npdt)
+    x = chain_states(A, b, C, npdt, seed=m)
     nu = rng.standard_normal(x.shape).astype(npdt)
     u = rng.uniform(size=C)
     outs = []
