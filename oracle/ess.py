@@ -10,7 +10,8 @@ Implementation for Linearly Truncated Multivariate Normal Distributions"
   x(theta) = x cos(theta) + nu sin(theta) (Section 2, eq. "ellipse"), build
   the active intervals I_act, draw theta uniformly on I_act, move;
 * per-constraint roots of p cos(theta) + q sin(theta) = b (Section 2, eq.
-  "trigonometry-equation"; Appendix B, eq. "roots");
+  "trigonometry-equation"; Appendix B, eq. "roots"), and Appendix B's two
+  alternative forms, for the ablation of the root formula;
 * the active intervals by brute force (Algorithm 2), by sort + cumulative
   max (Algorithm 3 / Proposition 1), with the no-root padding of Section 3.2,
   and by likelihood testing at midpoints (Section 3.1, the quadratic method
@@ -73,6 +74,55 @@ def roots(p, q, b):
     alpha = np.where(hit, alpha, 0.0)
     beta = np.where(hit, beta, 0.0)
     return alpha, beta, hit
+
+
+# --------------------------------------------------------------------------
+# Appendix B's two alternative root forms (for the ablation only)
+# --------------------------------------------------------------------------
+def roots_gessner(p, q, b, dtype=np.float64):
+    """The form of Gessner et al. quoted in Appendix B:
+    theta = +-acos(b / r) + 2 atan(q / (r + p)).  The half angle 2 atan(q /
+    (r + p)) equals tau (tan(tau / 2) = sin tau / (1 + cos tau)), so the
+    infeasible arc is again (2 atan(q / (r + p)) - phi, ... + phi) and the
+    same wrap gives (alpha, beta, hit) as `roots` does.  Evaluated in `dtype`
+    as written: nothing handles r + p = 0 (q = 0 with p < 0), where the
+    quotient is 0 / 0."""
+    p, q, b = (np.asarray(v, dtype=np.float64).astype(dtype) for v in (p, q, b))
+    with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
+        r = np.sqrt(p * p + q * q)
+        z = b / r
+        hit = (r > 0) & (z < 1)
+        phi = np.arccos(np.clip(np.where(hit, z, 0), -1, 1)).astype(np.float64)
+        tau = (2 * np.arctan(q / (r + p))).astype(np.float64)
+    alpha = wrap_2pi(tau - phi)
+    beta = np.minimum(alpha + 2.0 * phi, TWO_PI)
+    return np.where(hit, alpha, 0.0), np.where(hit, beta, 0.0), hit
+
+
+def roots_benavoli(p, q, b, dtype=np.float64):
+    """The form of Benavoli et al. quoted in Appendix B:
+    tan(theta / 2) = (q +- sqrt(r^2 - b^2)) / (b + p).  With t = tan(theta / 2)
+    the constraint p cos + q sin <= b becomes g(t) = (b + p) t^2 - 2 q t +
+    (b - p) >= 0, so for b + p > 0 the infeasible arc lies between the two
+    roots and for b + p < 0 it runs through theta = pi; theta = 0 (x_t) is
+    feasible either way.  Returns (alpha, beta, hit) as `roots` does,
+    evaluated in `dtype` as written: nothing handles b + p = 0, where one
+    root is at theta = pi and the quotient divides by zero."""
+    p, q, b = (np.asarray(v, dtype=np.float64).astype(dtype) for v in (p, q, b))
+    with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
+        r2 = p * p + q * q
+        hit = (r2 > 0) & (b * b < r2) | ((r2 > 0) & (b < 0))
+        s = np.sqrt(np.maximum(r2 - b * b, 0))
+        den = b + p
+        t1 = 2 * np.arctan((q - s) / den)
+        t2 = 2 * np.arctan((q + s) / den)
+        lo = np.minimum(t1, t2).astype(np.float64)
+        hi = np.maximum(t1, t2).astype(np.float64)
+    inside = np.asarray(den, np.float64) > 0          # infeasible arc is (lo, hi)
+    alpha = np.where(inside, wrap_2pi(lo), wrap_2pi(hi))
+    width = np.where(inside, hi - lo, lo + TWO_PI - hi)
+    beta = np.minimum(alpha + width, TWO_PI)
+    return np.where(hit, alpha, 0.0), np.where(hit, beta, 0.0), hit
 
 
 # --------------------------------------------------------------------------

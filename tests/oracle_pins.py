@@ -244,6 +244,39 @@ def pin_root_residual(seed=11, n=2000):
     return fails
 
 
+def pin_alternative_root_forms(seed=23, n=20000):
+    """Appendix B's two other forms (Gessner et al., Benavoli et al.) solve the
+    same equation: away from their edge cases (r + p and b + p both above
+    1e-3 r) each root has residual p cos(theta) + q sin(theta) - b within
+    1e-11 (b + r), the arc between alpha and beta is infeasible at its
+    midpoint, and alpha, beta equal the tau +- acos form's to 1e-9."""
+    fails = []
+    rng = np.random.default_rng(seed)
+    p = rng.standard_normal(n) * 2
+    q = rng.standard_normal(n) * 2
+    r = np.hypot(p, q)
+    b = np.maximum(p, 0) + rng.uniform(0, 1.5, n) * r
+    ok = (r + p > 1e-3 * r) & (np.abs(b + p) > 1e-3 * r)
+    p, q, b, r = p[ok], q[ok], b[ok], r[ok]
+    a0, b0, h0 = ess.roots(p, q, b)
+    for f in (ess.roots_gessner, ess.roots_benavoli):
+        al, be, hit = f(p, q, b)
+        if not np.array_equal(hit, h0):
+            fails.append(f"{f.__name__}: {np.sum(hit != h0)} rows differ in crossing or not")
+            continue
+        for t in (al, be):
+            res = np.abs(p * np.cos(t) + q * np.sin(t) - b)[hit]
+            if res.size and res.max() > 1e-11 * (np.abs(b) + r)[hit].max():
+                fails.append(f"{f.__name__}: residual {res.max():.3e}")
+        mid = 0.5 * (al + be)
+        if np.any((p * np.cos(mid) + q * np.sin(mid) <= b)[hit]):
+            fails.append(f"{f.__name__}: an arc midpoint is feasible")
+        d = np.abs(np.mod(np.concatenate([al - a0, be - b0])[np.tile(hit, 2)] + PI, TWO_PI) - PI)
+        if d.size and d.max() > 1e-9:
+            fails.append(f"{f.__name__}: differs from tau +- acos by {d.max():.3e}")
+    return fails
+
+
 def pin_rotation_covariance(seed=12, n=500):
     """Replacing (x, nu) by (x cos s + nu sin s, -x sin s + nu cos s) rotates
     every angle by -s (mod 2 pi)."""
@@ -546,7 +579,8 @@ def pin_rejection_sampling_reference(seed=19, n_chains=200, n_steps=100, burn=20
     return [f"mean {cm.mean(axis=0)} vs rejection sampling {ref}"] if bad.any() else []
 
 
-FAST_PINS = [pin_fig1, pin_fig2, pin_fig1_trimmed, pin_reject_and_stay, pin_root_residual, pin_rotation_covariance,
+FAST_PINS = [pin_fig1, pin_fig2, pin_fig1_trimmed, pin_reject_and_stay, pin_root_residual,
+             pin_alternative_root_forms, pin_rotation_covariance,
              pin_alg3_equals_alg2, pin_midpoint_equals_alg2, pin_dense_grid, pin_appendix_d,
              pin_sorting_reduction,
              pin_theta_uniform, pin_philox_kat, pin_box_muller]
