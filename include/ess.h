@@ -157,6 +157,34 @@ ess_status ess_transition_explicit(ess_ctx* ctx, const void* x, const void* nu,
                                    int32_t* n_intervals, double* theta,
                                    int32_t* rejected, void* pq);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * transition of ess_transition_explicit without a context.  It calls no
+ * hipMalloc or hipFree; every buffer a context would own lives in one static
+ * array of 64 MiB per device, which the library holds until the process ends.
+ * A (m x d, T), b (m, double) and x, nu, u are read as by ess_init and
+ * ess_transition_explicit (precision 32: float T; 64: double); x must be
+ * strictly feasible (ESS_ERR_INFEASIBLE_START names the first chain that is
+ * not; this check synchronises `stream`).  Outputs as for
+ * ess_transition_explicit, with the same values: x_new (n_chains x d, T),
+ * intervals (nullable, n_chains x (m + 1) x 2 double), n_intervals
+ * (nullable, n_chains int32), theta (nullable, n_chains double), rejected
+ * (nullable, n_chains int32).  The remaining work is queued on `stream` (a
+ * hipStream_t as void*, NULL = the null stream).  ESS_ERR_UNSUPPORTED when the
+ * shape needs more than the static array: about
+ *   4 (mp dp + 3 Cp dp + 3 Cp mp) + 16 Cp mp bytes in precision 32 (8 in
+ *   place of 4 in precision 64), mp = m and Cp = n_chains rounded up to 128,
+ *   dp = d rounded up to 32.
+ * Every call on a device shares that device's array and keeps the last
+ * call's contents there (the call clears what it needs): calls that overlap
+ * on one device, from several streams or threads, race. */
+ess_status ess_transition_explicit_static(int32_t d, int32_t m, int32_t n_chains,
+                                          int32_t precision, const void* A, const double* b,
+                                          double trim_eps, const void* x, const void* nu,
+                                          const double* u, void* x_new, double* intervals,
+                                          int32_t* n_intervals, double* theta, int32_t* rejected,
+                                          void* stream);
+
 /* The random numbers step `step` uses: nu (n_chains x d, T, nullable) and the
  * theta uniforms u (n_chains double, nullable).  Does not change the context. */
 ess_status ess_draw(ess_ctx* ctx, uint64_t step, void* nu, double* u);

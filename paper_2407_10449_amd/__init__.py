@@ -59,6 +59,8 @@ _SIGS = {
     "ess_set_state": ([_P, _P, ctypes.c_uint64], ctypes.c_int),
     "ess_rejections": ([_P, _P], ctypes.c_int),
     "ess_transition_explicit": ([_P] * 10, ctypes.c_int),
+    "ess_transition_explicit_static": ([ctypes.c_int32] * 4 + [_P, _P, ctypes.c_double] + [_P] * 9,
+                                       ctypes.c_int),
     "ess_draw": ([_P, ctypes.c_uint64, _P, _P], ctypes.c_int),
     "ess_profile": ([_P, ctypes.c_int], ctypes.c_int),
     "ess_profile_read": ([_P, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
@@ -213,6 +215,17 @@ def ess_transition_explicit(ctx, x, nu, u, x_new, intervals=None, n_intervals=No
     _check(lib().ess_transition_explicit(ctx, _ptr(x), _ptr(nu), _ptr(u), _ptr(x_new),
                                          _ptr(intervals), _ptr(n_intervals), _ptr(theta),
                                          _ptr(rejected), _ptr(pq)))
+
+
+def ess_transition_explicit_static(d, m, n_chains, precision, A, b, trim_eps, x, nu, u, x_new,
+                                   intervals=None, n_intervals=None, theta=None, rejected=None,
+                                   stream=None):
+    """The context-free transition that allocates no device memory (its
+    buffers live in the library's static array)."""
+    _check(lib().ess_transition_explicit_static(
+        int(d), int(m), int(n_chains), int(precision), _ptr(A), _ptr(b), float(trim_eps), _ptr(x),
+        _ptr(nu), _ptr(u), _ptr(x_new), _ptr(intervals), _ptr(n_intervals), _ptr(theta),
+        _ptr(rejected), _stream_handle(stream)))
 
 
 def ess_draw(ctx, step, nu=None, u=None):

@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <memory>
+#include <mutex>
 #include <numeric>
 #include <cstdarg>
 #include <cstdio>
@@ -1313,6 +1314,77 @@ void choose_tiles(ess_ctx* c) {
     }
 }
 
+// ---------------------------------------------------------------- no allocation
+// ess_transition_explicit_static keeps every buffer a context would own in
+// one file-scope array per device.  Host code never passes `scratch` itself
+// to a kernel or copy: its address on the current device comes from
+// hipGetSymbolAddress, once per device.
+constexpr size_t kStaticScratchBytes = static_cast<size_t>(64) << 20;
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+ess_status scratch_address(void** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(ESS_ERR_UNSUPPORTED, "device %d: the static buffer serves devices 0 .. %d", dev,
+                    kMaxDevices - 1);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(ESS_ERR_HIP, "hipGetSymbolAddress gave a null address");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return ESS_OK;
+}
+
+// rows x cols (dense, row-major) into rows_p x ld, zero everywhere else.
+template <typename T>
+__global__ __launch_bounds__(256) void pad_copy_kernel(const T* __restrict__ src, int rows, int cols,
+                                                       T* __restrict__ dst, int rows_p, int ld) {
+    const size_t n = static_cast<size_t>(rows_p) * ld;
+    for (size_t e = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x; e < n;
+         e += static_cast<size_t>(gridDim.x) * 256) {
+        const int r = static_cast<int>(e / ld), k = static_cast<int>(e % ld);
+        dst[e] = (r < rows && k < cols) ? src[static_cast<size_t>(r) * cols + k] : T(0);
+    }
+}
+
+__global__ __launch_bounds__(256) void fill_ints_kernel(int* __restrict__ p, int n, int v) {
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) p[i] = v;
+}
+
+// The lowest chain whose strict feasibility check flagged a row (first
+// starts at C).
+__global__ __launch_bounds__(256) void first_flag_kernel(const int* __restrict__ flag, int C,
+                                                         int* __restrict__ first) {
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c < C && flag[c]) atomicMin(first, c);
+}
+
+template <typename T>
+ess_status pad_copy(const void* src, int rows, int cols, void* dst, int rows_p, int ld,
+                    hipStream_t st) {
+    const size_t n = static_cast<size_t>(rows_p) * ld;
+    const unsigned grid = static_cast<unsigned>(std::min<size_t>((n + 255) / 256, 4096));
+    hipLaunchKernelGGL((pad_copy_kernel<T>), dim3(grid), dim3(256), 0, st,
+                       static_cast<const T*>(src), rows, cols, static_cast<T*>(dst), rows_p, ld);
+    HIP_TRY(hipGetLastError());
+    return ESS_OK;
+}
+
+ess_status fill_ints(int* p, int n, int v, hipStream_t st) {
+    const unsigned grid = static_cast<unsigned>(std::min((n + 255) / 256, 1024));
+    hipLaunchKernelGGL(fill_ints_kernel, dim3(grid), dim3(256), 0, st, p, n, v);
+    HIP_TRY(hipGetLastError());
+    return ESS_OK;
+}
+
 __global__ __launch_bounds__(256) void gate_rows_kernel(const int* __restrict__ flag,
                                                         const void* fallback, void* X, int d, int dp,
                                                         int esz, int* accepted) {
@@ -1659,6 +1731,121 @@ ess_status ess_transition_explicit(ess_ctx* c, const void* x, const void* nu, co
     ESS_TRY(copy_rows_out(c, x_new, c->X));
     // N and Q back to the current step's direction for later runs
     return prime_direction(c);
+}
+
+ess_status ess_transition_explicit_static(int32_t d, int32_t m, int32_t n_chains,
+                                          int32_t precision, const void* A, const double* b,
+                                          double trim_eps, const void* x, const void* nu,
+                                          const double* u, void* x_new, double* intervals,
+                                          int32_t* n_intervals, double* theta, int32_t* rejected,
+                                          void* stream) {
+    g_err.clear();
+    if (!A || !b || !x || !nu || !u || !x_new)
+        return fail(ESS_ERR_INVALID_ARG, "null A, b, x, nu, u or x_new");
+    if (d < 1 || m < 1 || n_chains < 1)
+        return fail(ESS_ERR_INVALID_ARG, "d, m and n_chains must be >= 1 (got %d, %d, %d)", d, m,
+                    n_chains);
+    if (precision != 32 && precision != 64)
+        return fail(ESS_ERR_INVALID_ARG, "precision must be 32 or 64 (got %d)", precision);
+    if (!(trim_eps >= 0.0) || trim_eps > 1.0)
+        return fail(ESS_ERR_INVALID_ARG, "trim_eps must lie in [0, 1] (got %g)", trim_eps);
+    if (m > kMaxRowsLarge || d > (1 << 20) || n_chains > (1 << 24))
+        return fail(ESS_ERR_UNSUPPORTED, "d, m or n_chains too large");
+    void* base = nullptr;
+    ESS_TRY(scratch_address(&base));
+
+    // the buffers of a context, carved from the static array (256-byte aligned)
+    ess_ctx c;
+    c.d = d;
+    c.m = m;
+    c.C = n_chains;
+    c.prec = precision;
+    c.esz = precision == 32 ? 4 : 8;
+    c.eps = trim_eps;
+    c.st = static_cast<hipStream_t>(stream);
+    c.mp = round_up(m, 128);
+    c.Cp = round_up(n_chains, 128);
+    c.dp = round_up(d, 32);
+    c.use_graphs = false;
+    choose_tiles(&c);
+    const size_t rows = static_cast<size_t>(c.Cp) * c.dp * c.esz;
+    const size_t proj = static_cast<size_t>(c.Cp) * c.mp * c.esz;
+    const int n_ints = 3 * c.Cp + 2 * kMaxGroups + 2;   // sel, flag, fb_list, fb_count, step, first
+    size_t off = 0;
+    auto carve = [&](size_t bytes) {
+        const size_t o = off;
+        off += (bytes + 255) / 256 * 256;
+        return o;
+    };
+    const size_t oA = carve(static_cast<size_t>(c.mp) * c.dp * c.esz);
+    const size_t oX = carve(rows), oXp = carve(rows), oN = carve(rows);
+    const size_t oP = carve(2 * proj), oQ = carve(proj);
+    const size_t oAB = carve(2 * sizeof(double) * static_cast<size_t>(c.Cp) * c.mp);
+    const size_t oRej = carve(sizeof(long long) * c.Cp);
+    const size_t oInts = carve(sizeof(int) * n_ints);
+    if (off > kStaticScratchBytes)
+        return fail(ESS_ERR_UNSUPPORTED,
+                    "this shape needs %zu bytes of device memory; the static buffer holds %zu", off,
+                    kStaticScratchBytes);
+    unsigned char* mem = static_cast<unsigned char*>(base);
+    c.A = mem + oA;
+    c.b = const_cast<double*>(b);   // read only
+    c.X = mem + oX;
+    c.Xprop = mem + oXp;
+    c.N = mem + oN;
+    c.P = mem + oP;
+    c.Q = mem + oQ;
+    c.AB = mem + oAB;
+    c.rej = reinterpret_cast<long long*>(mem + oRej);
+    int* ints = reinterpret_cast<int*>(mem + oInts);
+    c.sel = ints;
+    c.flag = ints + c.Cp;
+    c.fb_list = ints + 2 * c.Cp;
+    c.fb_count = ints + 3 * c.Cp;
+    c.d_step = reinterpret_cast<uint32_t*>(ints + 3 * c.Cp + 2 * kMaxGroups);
+    int* first = ints + 3 * c.Cp + 2 * kMaxGroups + 1;
+
+    // the array keeps the previous call's contents: clear what starts at zero
+    // (fill kernels, so the call can be captured), pad A, x and nu with zeros
+    ESS_TRY(fill_ints(ints, n_ints - 1, 0, c.st));
+    ESS_TRY(fill_ints(first, 1, n_chains, c.st));
+    ESS_TRY(fill_ints(reinterpret_cast<int*>(c.rej), 2 * c.Cp, 0, c.st));
+    const Group w = c.whole();
+    if (precision == 32) {
+        ESS_TRY(pad_copy<float>(A, m, d, c.A, c.mp, c.dp, c.st));
+        ESS_TRY(pad_copy<float>(x, n_chains, d, c.X, c.Cp, c.dp, c.st));
+        ESS_TRY(pad_copy<float>(nu, n_chains, d, c.N, c.Cp, c.dp, c.st));
+    } else {
+        ESS_TRY(pad_copy<double>(A, m, d, c.A, c.mp, c.dp, c.st));
+        ESS_TRY(pad_copy<double>(x, n_chains, d, c.X, c.Cp, c.dp, c.st));
+        ESS_TRY(pad_copy<double>(nu, n_chains, d, c.N, c.Cp, c.dp, c.st));
+    }
+    // strict feasibility of x (a_i^T x < b_i): A x into the committed buffers
+    ESS_TRY(launch_proj(&c, w, c.st, c.X, COLS_X, 1, 1));
+    hipLaunchKernelGGL(first_flag_kernel, dim3((n_chains + 255) / 256), dim3(256), 0, c.st, c.flag,
+                       n_chains, first);
+    HIP_TRY(hipGetLastError());
+    int bad = n_chains;
+    HIP_TRY(hipMemcpyAsync(&bad, first, sizeof(int), hipMemcpyDeviceToHost, c.st));
+    HIP_TRY(hipStreamSynchronize(c.st));
+    if (bad < n_chains)
+        return fail(ESS_ERR_INFEASIBLE_START,
+                    "ess_transition_explicit_static: chain %d is not strictly feasible", bad);
+    // the transition, as ess_transition_explicit runs it
+    ESS_TRY(fill_ints(c.flag, c.Cp, 0, c.st));
+    ESS_TRY(launch_proj(&c, w, c.st, c.Xprop, COLS_NU, 0, 0));
+    SampleArgs a = sample_args(&c, w, 0);
+    a.step = 0;
+    a.u_explicit = u;
+    a.intervals = intervals;
+    a.n_intervals = n_intervals;
+    a.theta_out = theta;
+    ESS_TRY(launch_sample(&c, w, c.st, a));
+    ESS_TRY(launch_proj(&c, w, c.st, c.Xprop, COLS_X, 0, 0));
+    SampleArgs f = sample_args(&c, w, 0);
+    f.rejected_out = rejected;
+    ESS_TRY(launch_commit(&c, w, c.st, f));
+    return copy_rows_out(&c, x_new, c.X);
 }
 
 ess_status ess_draw(ess_ctx* c, uint64_t step, void* nu, double* u) {
