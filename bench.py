@@ -23,6 +23,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -57,18 +59,30 @@ def measured_traffic():
         return None
 
 
-def cpu_baseline(pr, seconds, n_chains=64):
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or None."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(pr, seconds, n_chains=64, store=None, eps=1e-6):
     """The oracle (float64 numpy, BLAS threads as configured) on n_chains of the
     same problem, stepping until `seconds` of CPU work have passed."""
     import numpy as np
     from threadpoolctl import threadpool_info
 
     from oracle import ess as ref
+    store = np.float32 if store is None else store
     x = np.broadcast_to(pr.x0, (n_chains, pr.d)).copy()
     t0 = time.perf_counter()
     steps = 0
     while True:
-        _, x, _ = ref.run(pr.A, pr.b, x, n_chains, 1, seed=0, eps=1e-6, store=np.float32,
+        _, x, _ = ref.run(pr.A, pr.b, x, n_chains, 1, seed=0, eps=eps, store=store,
                           start_step=steps)
         steps += 1
         if time.perf_counter() - t0 >= seconds:
@@ -76,9 +90,58 @@ def cpu_baseline(pr, seconds, n_chains=64):
     dt = time.perf_counter() - t0
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     return {"value": n_chains * steps / dt, "unit": "chain-steps/s", "cores": int(threads),
-            "kind": "oracle",
-            "sample": f"gp_rbf d={pr.d} m={pr.m}: {n_chains} chains x {steps} steps "
+            "kind": "oracle", "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+            "sample": f"{pr.name} d={pr.d} m={pr.m}: {n_chains} chains x {steps} steps "
                       f"({dt:.1f} s, float64 numpy oracle)"}
+
+
+def bench_config(E, torch, pr, precision, steps, cpu_seconds, cpu_chains):
+    """One of the smaller workloads at its own chain count and step count:
+    chain-steps/s of a graph replay, the per-kernel durations of the same steps
+    launched one by one, and the oracle on the host."""
+    C = pr.n_chains
+    eps = 1e-6 if precision == 32 else 0.0
+    s = E.Sampler(pr.A, pr.b, pr.x0, C, seed=0, precision=precision, trim_eps=eps)
+    E.ess_run(s.ctx, steps, 1, None, False)          # capture and warm up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    E.ess_run(s.ctx, steps, 1, None, False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    E.ess_profile(s.ctx, True)
+    E.ess_run(s.ctx, steps, 1, None, False)
+    kinds = {"project": E.ESS_KERNEL_PROJECT, "sample": E.ESS_KERNEL_SAMPLE,
+             "other": E.ESS_KERNEL_OTHER}
+    ker = {}
+    for k, v in kinds.items():
+        ms, n = E.ess_profile_read(s.ctx, v)
+        ker[k] = ms / steps
+    E.ess_profile(s.ctx, False)
+    rej = int(s.rejections().sum())
+    s.close()
+    esz = 4 if precision == 32 else 8
+    # algorithmic work per step: 4 m d flop per chain in the projections;
+    # the per-chain kernel reads p, q of every row and b (shared, from cache)
+    # and reads x, x', nu and writes x', nu (20 d bytes with float storage)
+    proj_flops = 4.0 * pr.m * pr.d * C
+    chain_bytes = C * (2 * pr.m * esz + 5 * pr.d * esz)
+    peak_tflops = 157.3 if precision == 32 else 78.6
+    dominant = max(("project", "sample"), key=lambda k: ker[k])
+    out = {"workload": pr.name, "d": pr.d, "m": pr.m, "chains": C, "steps": steps,
+           "precision": precision, "chain_steps_per_s": C * steps / dt,
+           "ms_per_step": dt * 1e3 / steps, "rejections": rej,
+           "kernels_ms_per_step": ker, "dominant_kernel": dominant,
+           "projection": {"tflops": proj_flops / (ker["project"] * 1e-3) / 1e12,
+                          "peak_tflops": peak_tflops,
+                          "unit": "fp32 MFMA" if precision == 32 else "fp64 vector"},
+           "per_chain_kernel": {"hbm_gbs": chain_bytes / (ker["sample"] * 1e-3) / 1e9,
+                                "hbm_peak_gbs": 8000.0}}
+    out["projection"]["frac"] = out["projection"]["tflops"] / peak_tflops
+    out["per_chain_kernel"]["frac"] = out["per_chain_kernel"]["hbm_gbs"] / 8000.0
+    out["cpu_baseline"] = cpu_baseline(pr, cpu_seconds, n_chains=cpu_chains,
+                                       store=np.float32 if precision == 32 else np.float64,
+                                       eps=eps)
+    return out
 
 
 def bench_batched(E, torch, steps=50, plain_steps=10):
@@ -129,7 +192,7 @@ def bench_batched(E, torch, steps=50, plain_steps=10):
             "autotune": report.strip().splitlines()[-1]}
 
 
-def bench_warm_start(E, torch, log, steps=48000):
+def bench_warm_start(E, torch, log, steps=216000):
     """ESS/s at equal accuracy: batched + learned warm start against plain
     per-problem contexts (and against the batched context started plain)."""
     import numpy as np
@@ -162,9 +225,11 @@ def bench_paper_timing(E, torch, dims=(100, 250, 500, 1000, 2000, 4000)):
     for d in dims:
         row = {"d": d, "m": d}
         pr = synth.paper_highdim(d=d)
-        # Algorithm 3, and up to 4096 rows the quadratic comparator (Section
-        # 3.1's likelihood testing at midpoints) on the same instance
-        methods = (("alg3", ""), ("midpoint", "_midpoint")) if d <= 4096 else (("alg3", ""),)
+        # Algorithm 3, and up to 4096 rows the quadratic comparators (Section
+        # 3.1's likelihood testing at midpoints, Algorithm 2's sequential
+        # intersection) on the same instance
+        methods = ((("alg3", ""), ("midpoint", "_midpoint"), ("alg2", "_alg2")) if d <= 4096
+                   else (("alg3", ""),))
         for method, tag in methods:
             for chains, steps in ((1, 1000), (10, 100)):
                 s = E.Sampler(pr.A, pr.b, pr.x0, chains, seed=0, precision=32, method=method)
@@ -180,10 +245,12 @@ def bench_paper_timing(E, torch, dims=(100, 250, 500, 1000, 2000, 4000)):
                 row[f"{chains}x{steps}{tag}_rejections"] = int(nrej)
         if "1x1000_midpoint_ms" in row:
             row["midpoint_over_alg3_1x1000"] = row["1x1000_midpoint_ms"] / row["1x1000_ms"]
+            row["alg2_over_alg3_1x1000"] = row["1x1000_alg2_ms"] / row["1x1000_ms"]
         print(f"# paper timing d={d}: {row}", file=sys.stderr, flush=True)
         out.append(row)
     return {"workload": "Section 4.2 instances, float32, 1000 samples per run; *_midpoint: "
-                        "likelihood testing at midpoints (O(m^2)) on the same instances",
+                        "likelihood testing at midpoints (O(m^2)) on the same instances; "
+                        "*_alg2: Algorithm 2's sequential intersection",
             "rows": out}
 
 
@@ -200,7 +267,7 @@ def main():
                     help="run only the batched measurement and print its JSON (for profiling)")
     ap.add_argument("--warm-only", action="store_true",
                     help="run only the warm-start comparison and print its JSON")
-    ap.add_argument("--warm-steps", type=int, default=48000,
+    ap.add_argument("--warm-steps", type=int, default=216000,
                     help="steps per arm of the warm-start comparison")
     ap.add_argument("--paper-timing-only", action="store_true",
                     help="run only Section 4.2's timing protocol and print its JSON")
@@ -298,13 +365,20 @@ def main():
                      "kernel": "proj_gemm_f32 (A x' and A nu, 4 m d C flop per launch)"},
         "kernels_ms_per_step": {"project": proj_ms / max(proj_n, 1),
                                 "sample": samp_ms / max(samp_n, 1),
-                                "other_total": other_ms},
+                                "other": other_ms / args.steps,
+                                "other_launches_per_run": other_n},
         "timing": "value: one K-step graph replay; kernel durations: the same K steps "
                   "launched one by one with HIP events around each launch",
         "rejections": rej,
     }
     if not args.no_extras:
         log = lambda msg: print(msg, file=sys.stderr, flush=True)
+        cpu_s = 0.0 if args.no_cpu_baseline else 5.0
+        out["configs"] = [
+            bench_config(E, torch, synth.small_fp64(), 64, 2000, cpu_s, 16),
+            bench_config(E, torch, synth.box_halfspace(), 32, 1000, cpu_s, 64),
+        ]
+        log(f"configs: {out['configs']}")
         out["batched"] = bench_batched(E, torch)
         out["warm_start"] = bench_warm_start(E, torch, log, args.warm_steps)
         out["paper_timing"] = bench_paper_timing(E, torch, paper_dims)
