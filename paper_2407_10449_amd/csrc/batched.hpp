@@ -78,8 +78,10 @@ struct BatchArgs {
     long long* rej;
     int* tickets;          // [2][n_probs]
     int* done;             // [2][n_probs]: released tiles
-    int2* fb_list;         // [NC]: (problem, chain) handed to the full sort
+    int2* fb_list;         // unused since chains are sorted in place (kept for the layout)
     int* fb_count;         // [2]
+    double2* ab;           // alpha, beta of a chain sorted in full: problem p's chain c
+                           // owns ab[q_off + c mp ..) (the Q pack's layout)
     int* error;            // [1]: set when a wait exceeds its spin limit
     uint32_t step;         // relative to *step_base
     const uint32_t* step_base;   // nullable device counter
@@ -177,22 +179,48 @@ __device__ __forceinline__ void batch_tile(const BatchArgs& a, const ProbDesc& p
     }
 }
 
-template <int NB>
-union BatchLds {
-    BatchGemmLds g;
-    BucketLds<NB> b;
+template <int NB, int NK>
+struct BatchLds {
+    union {
+        BatchGemmLds g;
+        BucketLds<NB> bucket;
+        uint64_t key[NK];   // the full sort of a chain the bucket path hands back
+    };
+    double red[8];
+    int cnt[8];
+    double bcast[2];
+    int kstar;
+    double theta[2];
 };
+
+// The per-chain part of a batched step after the commit: the bucket path, and
+// for a chain whose survivors overflow the full sort in place from its roots,
+// which the bucket path leaves in a.ab (keys in the bucket arrays' LDS).
+template <int RPT, int NB, typename Lds>
+__device__ __forceinline__ void batch_sample(const BatchArgs& a, const ProbDesc& pd, int c,
+                                             const ChainRef<float>& r, int sel, Lds& lds) {
+    double2* abg = a.ab + pd.q_off + static_cast<size_t>(c) * pd.mp;
+    double theta = 0.0;
+    if (!bucket_chain<float, RPT, NB>(r, sel, lds.bucket, theta, nullptr, abg)) {
+        __syncthreads();   // every row's alpha and beta is in a.ab
+        const FullLds L{nullptr, nullptr, lds.key, lds.red, lds.cnt, lds.bcast, &lds.kstar, lds.theta};
+        theta = full_chain<float, KEYS_ROW_AB, 256>(r, sel, L, abg);
+    }
+    move_chain<float>(r, theta);
+}
+
+template <int RPT>
+constexpr int batch_keys() { return RPT * 256 > 512 ? RPT * 256 : 512; }
 
 template <int RPT, int NB>
 __global__ __launch_bounds__(256) void batched_step_kernel(BatchArgs a) {
-    __shared__ __attribute__((aligned(16))) BatchLds<NB> lds;
+    __shared__ __attribute__((aligned(16))) BatchLds<NB, batch_keys<RPT>()> lds;
     __shared__ int s_item;
     const int tid = threadIdx.x;
     const int par = static_cast<int>(abs_step(a) & 1u);
     const int p = a.wg_prob[blockIdx.x];
     const ProbDesc& pd = a.descs[p];
     if (tid == 0) s_item = atomicAdd(a.tickets + par * a.n_probs + p, 1);
-    if (blockIdx.x == 0 && tid == 0) a.fb_count[par ^ 1] = 0;   // the next launch's list
     __syncthreads();
     const int item = __builtin_amdgcn_readfirstlane(s_item);
     if (item == 0 && tid == 0) {                                 // the next launch's counters
@@ -227,50 +255,18 @@ __global__ __launch_bounds__(256) void batched_step_kernel(BatchArgs a) {
     __syncthreads();
     const ChainRef<float> r = batch_ref(a, pd, p, c);
     const int sel = a.has_pending ? commit_chain<float>(r) : *r.sel;
-    if (a.do_sample) {
-        double theta = 0.0;
-        const bool ok = bucket_chain<float, RPT, NB>(r, sel, lds.b, theta);
-        if (ok) move_chain<float>(r, theta);
-        else if (tid == 0) a.fb_list[atomicAdd(a.fb_count + par, 1)] = make_int2(p, c);
-    }
+    if (a.do_sample) batch_sample<RPT, NB>(a, pd, c, r, sel, lds);
 }
 
 // Split form, second launch: one workgroup per chain (the caller's order).
 template <int RPT, int NB>
 __global__ __launch_bounds__(256, RPT <= 8 ? 6 : 1) void batched_chain_kernel(BatchArgs a) {
-    __shared__ __attribute__((aligned(16))) BucketLds<NB> lds;
-    const int par = static_cast<int>(abs_step(a) & 1u);
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.fb_count[par ^ 1] = 0;   // the next step's list
+    __shared__ __attribute__((aligned(16))) BucketOrKeys<NB, batch_keys<RPT>()> lds;
     const int2 ch = a.chains[blockIdx.x];
     const ProbDesc& pd = a.descs[ch.x];
     const ChainRef<float> r = batch_ref(a, pd, ch.x, ch.y);
     const int sel = a.has_pending ? commit_chain<float>(r) : *r.sel;
-    if (a.do_sample) {
-        double theta = 0.0;
-        const bool ok = bucket_chain<float, RPT, NB>(r, sel, lds, theta);
-        if (ok) move_chain<float>(r, theta);
-        else if (threadIdx.x == 0) a.fb_list[atomicAdd(a.fb_count + par, 1)] = ch;
-    }
-}
-
-// Chains the batched step handed over: the bucket path with refinement of
-// crowded buckets, else the full sort.
-template <int NMAX>
-__global__ __launch_bounds__(256) void batched_fallback_kernel(BatchArgs a) {
-    ESS_FULL_LDS(NMAX)
-    __shared__ BucketLds<2048> blds;
-    const int par = static_cast<int>(abs_step(a) & 1u);
-    const int count = a.fb_count[par];
-    for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
-        const int2 ch = a.fb_list[idx];
-        const ChainRef<float> r = batch_ref(a, a.descs[ch.x], ch.x, ch.y);
-        const int sel = *r.sel;
-        double theta = 0.0;
-        if (!bucket_chain<float, NMAX / 256, 2048, 256, true>(r, sel, blds, theta))
-            theta = full_chain<float>(r, sel, full_lds);
-        move_chain<float>(r, theta);
-        __syncthreads();
-    }
+    if (a.do_sample) batch_sample<RPT, NB>(a, pd, ch.y, r, sel, lds);
 }
 
 // Projection tiles, one block per entry of the tile table (split form, and

@@ -137,7 +137,7 @@ struct ess_ctx {
     long long prof_n[4] = {0, 0, 0, 0};
     // many problems advanced together (ess_init_batched)
     struct Batch {
-        int n = 0, NT = 0, NTL = 0, NC = 0, rpt = 1, nb = 256, nmax = 512;
+        int n = 0, NT = 0, NTL = 0, NC = 0, rpt = 1, nb = 256;
         bool fused = false;          // one launch per step instead of tiles, then chains
         long long state_elems = 0;   // sum of C d (caller layout)
         int chains_padded = 0;
@@ -159,6 +159,7 @@ struct ess_ctx {
         double* b = nullptr;
         int* counters = nullptr;   // fb_count[2], error[1], tickets[2 n], done[2 n]
         int2* fb_list = nullptr;
+        double2* ab = nullptr;       // alpha, beta of chains sorted in full (the Q pack's layout)
     };
     std::unique_ptr<Batch> batch;
 
@@ -629,6 +630,7 @@ BatchArgs batch_args(const ess_ctx* c) {
     a.tickets = B.counters + 3;
     a.done = B.counters + 3 + 2 * B.n;
     a.fb_list = B.fb_list;
+    a.ab = B.ab;
     a.step_base = c->d_step;
     return a;
 }
@@ -661,18 +663,6 @@ ess_status launch_batched_step(ess_ctx* c, const BatchArgs& a, hipStream_t st) {
     if (B.rpt <= 4) return launch_step_t<4, 2048>(c, a, st);
     if (B.rpt <= 8) return launch_step_t<8, 2048>(c, a, st);
     return launch_step_t<16, 2048>(c, a, st);
-}
-
-ess_status launch_batched_fallback(const ess_ctx* c, const BatchArgs& a, hipStream_t st) {
-    const dim3 g(std::min(c->batch->NC, 64)), b(256);
-    switch (c->batch->nmax) {
-        case 512: hipLaunchKernelGGL((batched_fallback_kernel<512>), g, b, 0, st, a); break;
-        case 1024: hipLaunchKernelGGL((batched_fallback_kernel<1024>), g, b, 0, st, a); break;
-        case 2048: hipLaunchKernelGGL((batched_fallback_kernel<2048>), g, b, 0, st, a); break;
-        default: hipLaunchKernelGGL((batched_fallback_kernel<4096>), g, b, 0, st, a); break;
-    }
-    HIP_TRY(hipGetLastError());
-    return ESS_OK;
 }
 
 // A x for the rows in X (p_direct) with the strict start check, then the flags.
@@ -726,8 +716,6 @@ ess_status batched_issue(ess_ctx* c, int64_t n_steps, int64_t thin, void* trace,
                       ? static_cast<float*>(trace) + (s / thin - 1) * row
                       : nullptr;
         ESS_TRY(launch_batched_step(c, a, st));
-        if (a.do_sample)
-            ESS_TRY(timed(c, ESS_KERNEL_OTHER, st, [&] { return launch_batched_fallback(c, a, st); }));
     }
     return launch_step_counter(c, st, static_cast<uint64_t>(n_steps), 1);
 }
@@ -839,8 +827,6 @@ ess_status batched_init(ess_ctx* c, const ess_problem* pr, int n) {
     B.max_table = static_cast<int>(max_tiles + 8ll * (max_panel + 1));
     B.rpt = (max_m + 255) / 256;
     B.nb = max_m <= 256 ? 256 : 2048;
-    B.nmax = 512;
-    while (B.nmax < max_m) B.nmax <<= 1;
     // problems with the most projection work first, so their tiles start early
     B.order.resize(n);
     std::iota(B.order.begin(), B.order.end(), 0);
@@ -866,6 +852,7 @@ ess_status batched_init(ess_ctx* c, const ess_problem* pr, int n) {
     ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.Q), sizeof(float) * q_off));
     ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.counters), sizeof(int) * (3 + 4 * n)));
     ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.fb_list), sizeof(int2) * B.NC));
+    ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.ab), sizeof(double2) * q_off));
     ESS_TRY(dalloc(c, reinterpret_cast<void**>(&c->sel), sizeof(int) * chain_off));
     ESS_TRY(dalloc(c, reinterpret_cast<void**>(&c->flag), sizeof(int) * chain_off));
     ESS_TRY(dalloc(c, reinterpret_cast<void**>(&c->rej), sizeof(long long) * chain_off));
