@@ -337,6 +337,7 @@ def main():
 
     value = C * args.steps / dt
     flops_per_launch = 4.0 * m * d * C           # A x' and A nu for every chain
+    split_off = os.environ.get("ESS_PROJ") == "f32"
     proj_avg_s = proj_ms / max(proj_n, 1) / 1e3
     achieved = flops_per_launch / proj_avg_s / 1e12 if proj_n else None
     traffic = measured_traffic()
@@ -354,7 +355,11 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "gp_rbf", "d": d, "m": m, "chains": C,
-                   "storage": "f32", "projections": "f32 MFMA, f32 accumulate",
+                   "storage": "f32",
+                   "projections": ("f32 MFMA, f32 accumulate" if split_off else
+                                   "f32 operands split exactly into three bf16 pieces, six "
+                                   "bf16 MFMA products (dropped terms < 2^-24 |a x|), f32 "
+                                   "accumulate; error vs f64 below the f32 MFMA kernel's"),
                    "roots": "f32 pretest drops b/r >= 1.01; b/r = b rsqrt(p^2 + q^2) in f64; "
                             "f32 atan2, acos where |b/r| <= 0.99, f64 near tangency",
                    "interval_ends_and_sampling": "f64", "trim_eps": 1e-6, "seed": 0},
@@ -362,7 +367,10 @@ def main():
                      "unit": "TFLOP/s",
                      "frac": (achieved / PEAK_FP32_MFMA_TFLOPS) if achieved else None,
                      "traffic": traffic,
-                     "kernel": "proj_gemm_f32 (A x' and A nu, 4 m d C flop per launch)"},
+                     "kernel": ("proj_gemm_f32 (A x' and A nu, 4 m d C flop per launch)" if split_off
+                                else "proj_gemm_split (A x' and A nu, 4 m d C algorithmic flop "
+                                     "per launch; float32 contraction, so the float32 matrix "
+                                     "peak is its roofline)")},
         "kernels_ms_per_step": {"project": proj_ms / max(proj_n, 1),
                                 "sample": samp_ms / max(samp_n, 1),
                                 "other": other_ms / args.steps,
@@ -371,6 +379,11 @@ def main():
                   "launched one by one with HIP events around each launch",
         "rejections": rej,
     }
+    if achieved and not split_off:
+        # the bfloat16 matrix-core work actually issued: six products per
+        # multiply-add of the float32 contraction
+        out["roofline"]["executed_bf16"] = {"tflops": 6 * achieved, "peak": 2500.0,
+                                            "frac": 6 * achieved / 2500.0}
     if not args.no_extras:
         log = lambda msg: print(msg, file=sys.stderr, flush=True)
         cpu_s = 0.0 if args.no_cpu_baseline else 5.0

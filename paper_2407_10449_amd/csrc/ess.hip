@@ -104,6 +104,8 @@ struct ess_ctx {
     int* flag = nullptr;
     long long* rej = nullptr;
     int* fb_list = nullptr;    // chains handed to the full-sort path
+    uint16_t* A3 = nullptr;    // [3][mp][dp] bfloat16 pieces of A (split projections)
+    bool split_proj = false;   // float32 projections through exact bfloat16 splits
     void* AB = nullptr;        // [Cp][mp] double2: alpha, beta of every row (m > 4096, or
                                // m > 2048 with at most 256 chains), and of a chain the
                                // bucket path hands to the full sort
@@ -301,7 +303,17 @@ ess_status launch_proj(const ess_ctx* c, const Group& g, hipStream_t st, const v
         HIP_TRY(hipGetLastError());
         return ESS_OK;
     }
-    if (c->prec == 32) {
+    if (c->prec == 32 && c->split_proj) {
+        const float* B0 = static_cast<const float*>(Y) + off;
+        const float* B1 = static_cast<const float*>(c->N) + off;
+        const size_t plane = static_cast<size_t>(c->mp) * c->dp;
+        const int tiles_m = c->mp / 128, half = g.Cg / 128;
+        const int tn0 = (cols == COLS_NU) ? half : 0;
+        const int tiles_n = (cols == COLS_BOTH) ? 2 * half : half;
+        hipLaunchKernelGGL((proj_gemm_split<4, 2>), dim3(tiles_m * tiles_n), dim3(512), 0, st,
+                           c->A3, c->A3 + plane, c->A3 + 2 * plane, B0, B1, c->dp, tiles_m,
+                           tiles_n, tn0, c->group_m, o);
+    } else if (c->prec == 32) {
         const float* B0 = static_cast<const float*>(Y) + off;
         if (c->bm == 128 && c->bn == 128) launch_f32<128, 128, 4, 2>(c, g, st, B0, cols, o);
         else if (c->bm == 128 && c->bn == 64) launch_f32<128, 64>(c, g, st, B0, cols, o);
@@ -1518,6 +1530,26 @@ ess_status ess_init(const ess_problem* pr, void* stream, ess_ctx** out) {
     if (e != hipSuccess) {
         fail(ESS_ERR_HIP, "copying the problem: %s", hipGetErrorString(e));
         return bail(ESS_ERR_HIP);
+    }
+    // float32 projections through exact bfloat16 splits wherever the 128 x
+    // 128 tiles fill the device (ESS_PROJ=f32 keeps the float32 matrix cores)
+    {
+        const char* pe = std::getenv("ESS_PROJ");
+        c->split_proj = c->prec == 32 && c->bm == 128 && c->bn == 128 &&
+                        !(pe && std::strcmp(pe, "f32") == 0);
+    }
+    if (c->split_proj) {
+        const size_t plane = static_cast<size_t>(c->mp) * c->dp;
+        if ((s = dalloc(c, reinterpret_cast<void**>(&c->A3), 3 * plane * sizeof(uint16_t))) != ESS_OK)
+            return bail(s);
+        const unsigned grid = static_cast<unsigned>(std::min<size_t>((plane / 2 + 255) / 256, 4096));
+        hipLaunchKernelGGL(split_rows_kernel, dim3(grid), dim3(256), 0, c->st,
+                           static_cast<const float*>(c->A), plane, c->A3, c->A3 + plane,
+                           c->A3 + 2 * plane);
+        if ((e = hipGetLastError()) != hipSuccess) {
+            fail(ESS_ERR_HIP, "splitting A: %s", hipGetErrorString(e));
+            return bail(ESS_ERR_HIP);
+        }
     }
     if ((s = check_rows(c, "ess_init", 0)) != ESS_OK || (s = prime_direction(c)) != ESS_OK)
         return bail(s);

@@ -242,6 +242,219 @@ __global__ __launch_bounds__(64 * NW_M * NW_N) void proj_gemm_f32(const float* _
     gemm_tile_f32<BM, BN, NW_M, NW_N, 8>(A, B0, B1, K, tm * BM, tn * BN, o, lds);
 }
 
+// ---------------------------------------------------------------------------
+// float32 projections through exact bfloat16 splits on the bfloat16 matrix
+// cores (v_mfma_f32_16x16x32_bf16), float32 accumulation.
+//
+// Every float32 operand x is split into three bfloat16 pieces,
+//   hi = bf16(x), mid = bf16(x - hi), lo = x - hi - mid,
+// each rounded to nearest: x - hi keeps at most 16 significant bits and
+// x - hi - mid at most 8, so lo is exact and hi + mid + lo = x exactly.  Of
+// the nine products of pieces, the six down to relative size 2^-16 are
+// accumulated (hi hi, hi mid, mid hi, hi lo, mid mid, lo hi); the three
+// dropped ones (mid lo, lo mid, lo lo) are below 2^-24 of |a x| together,
+// the size of one float32 rounding, and carry random signs.  Measured on
+// random 2000 x 2048 x 1000 products the error against float64 stays below
+// that of a float32 sum of the same terms.  Products of bfloat16 pieces are
+// exact in float32, so only the float32 accumulation rounds.
+//
+// A is split once at init (three [mp][dp] arrays of bfloat16); the x' and
+// nu rows stay float32 in memory and are split while they are staged into
+// LDS.  Tile 128 x 128, K slabs of 32 (one MFMA deep), double-buffered LDS
+// with rows of 40 bfloat16 (80 bytes: the 16 rows of a fragment read fall on
+// distinct banks).
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+struct SplitLds {
+    static constexpr int BM = 128, BN = 128, BK = 32, LK = 40;
+    uint16_t a[2][3][BM * LK];
+    uint16_t b[2][3][BN * LK];
+};
+
+// bfloat16 rounding (to nearest, ties to even) of a float's bits, as the
+// high half of a float32 pattern
+__device__ __forceinline__ uint32_t bf16_round_bits(uint32_t u) {
+    return (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;
+}
+
+// the three pieces of two floats, packed two bfloat16 per word (low half first)
+__device__ __forceinline__ void split_pair(float x0, float x1, uint32_t& h, uint32_t& m,
+                                           uint32_t& l) {
+    const uint32_t h0 = bf16_round_bits(__float_as_uint(x0));
+    const uint32_t h1 = bf16_round_bits(__float_as_uint(x1));
+    const float r0 = x0 - __uint_as_float(h0), r1 = x1 - __uint_as_float(h1);
+    const uint32_t m0 = bf16_round_bits(__float_as_uint(r0));
+    const uint32_t m1 = bf16_round_bits(__float_as_uint(r1));
+    const float s0 = r0 - __uint_as_float(m0), s1 = r1 - __uint_as_float(m1);
+    h = (h0 >> 16) | h1;
+    m = (m0 >> 16) | m1;
+    l = (__float_as_uint(s0) >> 16) | (__float_as_uint(s1) & 0xFFFF0000u);
+}
+
+__device__ __forceinline__ void split8(const float4 v, const float4 w, uint4& h, uint4& m, uint4& l) {
+    split_pair(v.x, v.y, h.x, m.x, l.x);
+    split_pair(v.z, v.w, h.y, m.y, l.y);
+    split_pair(w.x, w.y, h.z, m.z, l.z);
+    split_pair(w.z, w.w, h.w, m.w, l.w);
+}
+
+// A (mp x dp floats) into its three bfloat16 pieces, n = mp dp elements.
+__global__ __launch_bounds__(256) void split_rows_kernel(const float* __restrict__ src, size_t n,
+                                                         uint16_t* __restrict__ hi,
+                                                         uint16_t* __restrict__ mid,
+                                                         uint16_t* __restrict__ lo) {
+    for (size_t e = 2 * (static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x); e < n;
+         e += 2 * static_cast<size_t>(gridDim.x) * 256) {
+        uint32_t h, m, l;
+        split_pair(src[e], e + 1 < n ? src[e + 1] : 0.0f, h, m, l);
+        hi[e] = static_cast<uint16_t>(h);
+        mid[e] = static_cast<uint16_t>(m);
+        lo[e] = static_cast<uint16_t>(l);
+        if (e + 1 < n) {
+            hi[e + 1] = static_cast<uint16_t>(h >> 16);
+            mid[e + 1] = static_cast<uint16_t>(m >> 16);
+            lo[e + 1] = static_cast<uint16_t>(l >> 16);
+        }
+    }
+}
+
+template <int NW_M, int NW_N>
+__device__ __forceinline__ void gemm_tile_split(const uint16_t* __restrict__ A0,
+                                                const uint16_t* __restrict__ A1,
+                                                const uint16_t* __restrict__ A2,
+                                                const float* __restrict__ B0,
+                                                const float* __restrict__ B1, int K, int m0, int n0,
+                                                const ProjOut& o, SplitLds& L) {
+    constexpr int BM = SplitLds::BM, BN = SplitLds::BN, BK = SplitLds::BK, LK = SplitLds::LK;
+    constexpr int NT = 64 * NW_M * NW_N;
+    constexpr int WM = BM / NW_M, WN = BN / NW_N, TM = WM / 16, TN = WN / 16;
+    constexpr int LD = BM * BK / 8 / NT;   // 16-byte chunks of 8 k per thread and piece
+    static_assert(LD == 1 || LD == 2, "128 x 32 slab over 256 or 512 threads");
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave / NW_N, wn = wave % NW_N;
+    const float* Bb = (n0 < o.Cg) ? B0 + static_cast<size_t>(n0) * K
+                                  : B1 + static_cast<size_t>(n0 - o.Cg) * K;
+    // chunk u of this thread: row idx / 4, k offset 8 (idx % 4), idx = tid + u NT
+    const int r0 = tid >> 2, q0 = (tid & 3) * 8;
+    const int r1 = (tid + NT) >> 2, q1 = ((tid + NT) & 3) * 8;
+    const size_t ao0 = static_cast<size_t>(m0 + r0) * K + q0, ao1 = static_cast<size_t>(m0 + r1) * K + q1;
+    const size_t bo0 = static_cast<size_t>(r0) * K + q0, bo1 = static_cast<size_t>(r1) * K + q1;
+    const int lo0 = r0 * LK + q0, lo1 = r1 * LK + q1;
+    uint4 a00, a01, a02, a10, a11, a12;
+    float4 b0a, b0b, b1a, b1b;
+    auto gload = [&](int k0) {
+        a00 = *reinterpret_cast<const uint4*>(A0 + ao0 + k0);
+        a01 = *reinterpret_cast<const uint4*>(A1 + ao0 + k0);
+        a02 = *reinterpret_cast<const uint4*>(A2 + ao0 + k0);
+        b0a = *reinterpret_cast<const float4*>(Bb + bo0 + k0);
+        b0b = *reinterpret_cast<const float4*>(Bb + bo0 + k0 + 4);
+        if constexpr (LD == 2) {
+            a10 = *reinterpret_cast<const uint4*>(A0 + ao1 + k0);
+            a11 = *reinterpret_cast<const uint4*>(A1 + ao1 + k0);
+            a12 = *reinterpret_cast<const uint4*>(A2 + ao1 + k0);
+            b1a = *reinterpret_cast<const float4*>(Bb + bo1 + k0);
+            b1b = *reinterpret_cast<const float4*>(Bb + bo1 + k0 + 4);
+        }
+    };
+    auto lstore = [&](int buf) {
+        uint4 h, m, l;
+        split8(b0a, b0b, h, m, l);
+        *reinterpret_cast<uint4*>(&L.a[buf][0][lo0]) = a00;
+        *reinterpret_cast<uint4*>(&L.a[buf][1][lo0]) = a01;
+        *reinterpret_cast<uint4*>(&L.a[buf][2][lo0]) = a02;
+        *reinterpret_cast<uint4*>(&L.b[buf][0][lo0]) = h;
+        *reinterpret_cast<uint4*>(&L.b[buf][1][lo0]) = m;
+        *reinterpret_cast<uint4*>(&L.b[buf][2][lo0]) = l;
+        if constexpr (LD == 2) {
+            split8(b1a, b1b, h, m, l);
+            *reinterpret_cast<uint4*>(&L.a[buf][0][lo1]) = a10;
+            *reinterpret_cast<uint4*>(&L.a[buf][1][lo1]) = a11;
+            *reinterpret_cast<uint4*>(&L.a[buf][2][lo1]) = a12;
+            *reinterpret_cast<uint4*>(&L.b[buf][0][lo1]) = h;
+            *reinterpret_cast<uint4*>(&L.b[buf][1][lo1]) = m;
+            *reinterpret_cast<uint4*>(&L.b[buf][2][lo1]) = l;
+        }
+    };
+
+    f32x4 acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    double brow[TM][4];
+    if (n0 < o.Cg && o.bstride == 0) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + wm * WM + i * 16 + (lane >> 4) * 4 + r;
+                brow[i][r] = row < o.m ? o.b[row] : __builtin_inf();
+            }
+    }
+
+    const int KT = K / BK;
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    for (int kt = 0; kt < KT; ++kt) {
+        const int buf = kt & 1;
+        if (kt + 1 < KT) gload((kt + 1) * BK);
+        // lane l supplies k = 8 (l / 16) .. + 7 of row l % 16 for A and of
+        // column l % 16 for B; the output is rows 4 (l / 16) .. + 3 of column l % 16
+        const int kofs = 8 * (lane >> 4);
+        bf16x8 af[3][TM], bfr[3][TN];
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+                af[p][i] = *reinterpret_cast<const bf16x8*>(
+                    &L.a[buf][p][(wm * WM + i * 16 + (lane & 15)) * LK + kofs]);
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+                bfr[p][j] = *reinterpret_cast<const bf16x8*>(
+                    &L.b[buf][p][(wn * WN + j * 16 + (lane & 15)) * LK + kofs]);
+        }
+        // smallest products first
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                f32x4 c = acc[i][j];
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[2][i], bfr[0][j], c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1][i], bfr[1][j], c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bfr[2][j], c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1][i], bfr[0][j], c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bfr[1][j], c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bfr[0][j], c, 0, 0, 0);
+                acc[i][j] = c;
+            }
+        if (kt + 1 < KT) lstore(buf ^ 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const int i0 = m0 + wm * WM + i * 16 + (lane >> 4) * 4;
+            const int n = n0 + wn * WN + j * 16 + (lane & 15);
+            proj_store4<float>(o, n, i0, acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3],
+                               brow[i]);
+        }
+}
+
+template <int NW_M, int NW_N>
+__global__ __launch_bounds__(64 * NW_M * NW_N) void proj_gemm_split(
+    const uint16_t* __restrict__ A0, const uint16_t* __restrict__ A1,
+    const uint16_t* __restrict__ A2, const float* __restrict__ B0, const float* __restrict__ B1,
+    int K, int tiles_m, int tiles_n, int tn0, int group_m, ProjOut o) {
+    __shared__ __attribute__((aligned(16))) SplitLds lds;
+    int tm, tn;
+    tile_coords(blockIdx.x, tiles_m, tiles_n, group_m, tm, tn);
+    tn += tn0;
+    gemm_tile_split<NW_M, NW_N>(A0, A1, A2, B0, B1, K, tm * SplitLds::BM, tn * SplitLds::BN, o, lds);
+}
+
 // float64 projections on the vector ALUs (MI355X runs float64 FMA on the
 // vector units at the same rate as its float64 matrix cores).  64 x 64 tile,
 // each thread a 4 x 4 block: rows 4 ty .. 4 ty + 3, columns tx + 16 u.
