@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ESS chain-steps/s at d=1000,m=2000; batched+warm-start vs plain ESS/s, 1 GPU"
 PEAK_FP32_MFMA_TFLOPS = 157.3
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "proj_gemm_f32_gp_rbf_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "proj_gemm_split_gp_rbf_traffic.txt")
 
 
 def kernel_source_digest():

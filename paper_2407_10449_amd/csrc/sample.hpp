@@ -403,6 +403,104 @@ __device__ __forceinline__ void move_chain(const ChainRef<T>& r, double theta) {
     }
 }
 
+// The bookkeeping half of a commit (Section 3.3): the decision on the pending
+// proposal, the rejection count and the projection buffer the roots read.
+// The rows are copied later, by move_pairs, in the same pass as the move.
+// Returns the committed projection buffer; `from_prop` tells whether the
+// proposal became the state.
+template <typename T>
+__device__ __forceinline__ int commit_flags(const ChainRef<T>& r, bool& from_prop) {
+    const int fl = *r.flag;
+    const int s = *r.sel;
+    __syncthreads();   // every read of flag / sel precedes the writes below
+    const int snew = fl ? s : (s ^ 1);
+    if (threadIdx.x == 0) {
+        if (fl) *r.rej += 1;
+        *r.sel = snew;
+        *r.flag = 0;
+        if (r.rejected_out) *r.rejected_out = fl;
+    }
+    from_prop = !fl;
+    return snew;
+}
+
+// Element pairs (2 j, 2 j + 1), j = t, t + BS, ... belong to thread t in
+// move_pairs, so a thread reads nu exactly where it writes the next nu.  The
+// first pair is loaded ahead, while the roots' loads are in flight, and held
+// in registers until the move.
+template <typename T>
+struct PairAhead {
+    T v0, v1, n0, n1;   // the state's and nu's elements
+};
+
+template <typename T>
+__device__ __forceinline__ PairAhead<T> pair_ahead(const ChainRef<T>& r, bool from_prop) {
+    PairAhead<T> q{};
+    const int k = 2 * static_cast<int>(threadIdx.x);
+    if (k < r.d) {
+        const T* src = from_prop ? r.xp : r.x;
+        const bool two = k + 1 < r.d;
+        q.v0 = src[k];
+        q.n0 = r.nu[k];
+        q.v1 = two ? src[k + 1] : T(0);
+        q.n1 = two ? r.nu[k + 1] : T(0);
+    }
+    return q;
+}
+
+// The move of every element, x' = v cos(theta) + nu sin(theta), where v is
+// the state (the proposal when it was accepted, else x), with the commit's
+// copies on the way: the accepted proposal into x, the state into the trace;
+// then nu replaced by the next step's draw.  Element pairs as in pair_ahead,
+// the first taken from `q`.
+template <typename T, int BS>
+__device__ __forceinline__ void move_pairs(const ChainRef<T>& r, double theta, bool from_prop,
+                                           bool copy_state, const PairAhead<T>& q) {
+    if (threadIdx.x == 0 && r.theta_out) *r.theta_out = theta;
+    double sd, cd;
+    sincos(theta, &sd, &cd);
+    const T ct = static_cast<T>(cd), st = static_cast<T>(sd);
+    const T* src = from_prop ? r.xp : r.x;
+    for (int j = threadIdx.x; 2 * j < r.d; j += BS) {
+        const int k = 2 * j;
+        const bool two = k + 1 < r.d;
+        T v0, v1, n0, n1;
+        if (j < BS) {
+            v0 = q.v0;
+            v1 = q.v1;
+            n0 = q.n0;
+            n1 = q.n1;
+        } else {
+            v0 = src[k];
+            n0 = r.nu[k];
+            v1 = two ? src[k + 1] : T(0);
+            n1 = two ? r.nu[k + 1] : T(0);
+        }
+        if (copy_state) {
+            r.x[k] = v0;
+            if (two) r.x[k + 1] = v1;
+        }
+        if (r.trace) {
+            r.trace[k] = v0;
+            if (two) r.trace[k + 1] = v1;
+        }
+        // one explicit contraction, as in move_chain
+        r.xp[k] = fma(v0, ct, n0 * st);
+        if (two) r.xp[k + 1] = fma(v1, ct, n1 * st);
+    }
+    // the next nu over the same pairs: each thread overwrites only the nu
+    // elements it has read itself, so no barrier is needed
+    if (r.gen_next) {
+        const Rng rng(r.seed);
+        for (int j = threadIdx.x; 2 * j < r.d; j += BS) {
+            double z0, z1;
+            rng.normal_pair(j, r.chain, r.step + 1, r.problem, z0, z1);
+            r.nu[2 * j] = static_cast<T>(z0);
+            if (2 * j + 1 < r.d) r.nu[2 * j + 1] = static_cast<T>(z1);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Full path: bitonic sort of every crossing row, then the sweep.
 // ---------------------------------------------------------------------------
@@ -1256,8 +1354,8 @@ template <typename T, int RPT, int NB, int BS = 256, bool REFINE = false, bool P
 __global__ __launch_bounds__(BS, (BS == 512 && RPT <= 4 && !REFINE) ? 8 : 1) void sample_bucket_kernel(SampleArgs a) {
     const int c = a.c0 + blockIdx.x;
     const ChainRef<T> r = make_ref<T>(a, c);
-    const int sel = a.has_pending ? commit_chain<T>(r) : *r.sel;
     if constexpr (REFINE) {
+        const int sel = a.has_pending ? commit_chain<T>(r) : *r.sel;
         // the variants for few chains refine crowded buckets and keep alpha
         // and beta of a chain they sort in LDS (occupancy does not matter
         // with no more chains than compute units)
@@ -1281,6 +1379,10 @@ __global__ __launch_bounds__(BS, (BS == 512 && RPT <= 4 && !REFINE) ? 8 : 1) voi
         __shared__ BucketOrKeys<NB, NK> lds;
         double2* abg = static_cast<double2*>(a.ab) + static_cast<size_t>(c) * a.mp;
         bool done = false;
+        // the commit's bookkeeping now, its row copies with the move
+        bool from_prop = false;
+        const int sel = a.has_pending ? commit_flags<T>(r, from_prop) : *r.sel;
+        const PairAhead<T> ahead = pair_ahead<T>(r, from_prop);
         double theta = 0.0;
         if (!a.force_full) {
             done = bucket_chain<T, RPT, NB, BS, false>(r, sel, lds.bucket, theta, nullptr, abg);
@@ -1294,7 +1396,7 @@ __global__ __launch_bounds__(BS, (BS == 512 && RPT <= 4 && !REFINE) ? 8 : 1) voi
             const FullLds L{nullptr, nullptr, lds.key, lds.red, lds.cnt, lds.bcast, &lds.kstar, lds.theta};
             theta = full_chain<T, KEYS_ROW_AB, BS>(r, sel, L, abg);
         }
-        move_chain<T>(r, theta);
+        move_pairs<T, BS>(r, theta, from_prop, from_prop && a.has_pending, ahead);
     }
 }
 
