@@ -70,10 +70,11 @@ typedef enum {
  * zero-length single-root case of Figure 2(d). */
 typedef struct {
     int32_t d;            /* dimension, >= 1                                  */
-    int32_t m;            /* number of constraints, 1 .. 16384 (1 .. 4096 in a
+    int32_t m;            /* number of constraints, 1 .. 65536 (1 .. 4096 in a
                              batched context); above 4096 every pass over the
                              rows is made in chunks of 4096 and the full sort
-                             keeps keys only                                  */
+                             keeps keys only, in LDS up to 16384 rows and in
+                             device memory (8 bytes per row and chain) beyond */
     int32_t n_chains;     /* independent chains, >= 1                         */
     int32_t precision;    /* 32: float storage and projections, float64 roots,
                              interval ends and sampling; 64: float64 throughout */
@@ -174,7 +175,9 @@ ess_status ess_transition_explicit(ess_ctx* ctx, const void* x, const void* nu,
  * shape needs more than the static array: about
  *   4 (mp dp + 3 Cp dp + 3 Cp mp) + 16 Cp mp bytes in precision 32 (8 in
  *   place of 4 in precision 64), mp = m and Cp = n_chains rounded up to 128,
- *   dp = d rounded up to 32.
+ *   dp = d rounded up to 32; plus 6 mp dp bytes where precision 32 takes the
+ *   split projections (as ess_init would: both 128 x 128 tiles), and 8 Cp m2
+ *   bytes above 16384 rows (m2 = m rounded up to a power of two).
  * Every call on a device shares that device's array and keeps the last
  * call's contents there (the call clears what it needs): calls that overlap
  * on one device, from several streams or threads, race. */

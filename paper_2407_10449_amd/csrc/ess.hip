@@ -104,6 +104,8 @@ struct ess_ctx {
     int* flag = nullptr;
     long long* rej = nullptr;
     int* fb_list = nullptr;    // chains handed to the full-sort path
+    uint64_t* keys = nullptr;  // more than 16384 rows: [Cp][kstride] full-sort keys
+    int kstride = 0;
     uint16_t* A3 = nullptr;    // [3][mp][dp] bfloat16 pieces of A (split projections)
     bool split_proj = false;   // float32 projections through exact bfloat16 splits
     void* AB = nullptr;        // [Cp][mp] double2: alpha, beta of every row (m > 4096, or
@@ -360,6 +362,8 @@ SampleArgs sample_args(const ess_ctx* c, const Group& g, int gi) {
     a.step_base = c->d_step;
     a.force_full = (c->flags & ESS_SORT_FULL) ? 1 : 0;
     a.ab = c->AB;
+    a.keys = c->keys;
+    a.kstride = c->kstride;
     return a;
 }
 
@@ -388,7 +392,10 @@ void launch_sample_t(const ess_ctx* c, const Group& g, hipStream_t st, const Sam
         const long long blocks = static_cast<long long>((c->m + 255) / 256) * g.n;
         hipLaunchKernelGGL((large_roots_kernel<T>), dim3(static_cast<unsigned>(blocks)), b, 0, st, a);
         hipLaunchKernelGGL((sample_large_kernel<T>), grid, b2, 0, st, a);
-        hipLaunchKernelGGL((fallback_large_kernel<T>), fg, b, 0, st, a);
+        if (c->m > kMaxRowsLds)
+            hipLaunchKernelGGL((fallback_large_kernel<T, true>), fg, b, 0, st, a);
+        else
+            hipLaunchKernelGGL((fallback_large_kernel<T>), fg, b, 0, st, a);
         return;
     }
     // more than 1024 rows: 512 threads per chain (measured 12 % faster at
@@ -1490,6 +1497,13 @@ ess_status ess_init(const ess_problem* pr, void* stream, ess_ctx** out) {
         (s = dalloc(c, reinterpret_cast<void**>(&c->fb_count), sizeof(int) * 2 * kMaxGroups)) != ESS_OK ||
         (s = dalloc(c, &c->AB, 2 * sizeof(double) * static_cast<size_t>(c->Cp) * c->mp)) != ESS_OK)
         return bail(s);
+    if (c->m > kMaxRowsLds) {
+        c->kstride = 512;
+        while (c->kstride < c->m) c->kstride <<= 1;
+        if ((s = dalloc(c, reinterpret_cast<void**>(&c->keys),
+                        sizeof(uint64_t) * static_cast<size_t>(c->Cp) * c->kstride)) != ESS_OK)
+            return bail(s);
+    }
     {
         // every group stream and event exists from the start: the autotuner and
         // cached choices may raise the group count up to kMaxGroups later
@@ -1787,6 +1801,17 @@ ess_status ess_transition_explicit_static(int32_t d, int32_t m, int32_t n_chains
     c.dp = round_up(d, 32);
     c.use_graphs = false;
     choose_tiles(&c);
+    {
+        // the projections ess_init would choose, so the values agree
+        const char* pe = std::getenv("ESS_PROJ");
+        c.split_proj = precision == 32 && c.bm == 128 && c.bn == 128 &&
+                       !(pe && std::strcmp(pe, "f32") == 0);
+    }
+    if (m > kMaxRowsLds) {
+        c.kstride = 512;
+        while (c.kstride < m) c.kstride <<= 1;
+    }
+    const size_t plane = static_cast<size_t>(c.mp) * c.dp;
     const size_t rows = static_cast<size_t>(c.Cp) * c.dp * c.esz;
     const size_t proj = static_cast<size_t>(c.Cp) * c.mp * c.esz;
     const int n_ints = 3 * c.Cp + 2 * kMaxGroups + 2;   // sel, flag, fb_list, fb_count, step, first
@@ -1802,6 +1827,8 @@ ess_status ess_transition_explicit_static(int32_t d, int32_t m, int32_t n_chains
     const size_t oAB = carve(2 * sizeof(double) * static_cast<size_t>(c.Cp) * c.mp);
     const size_t oRej = carve(sizeof(long long) * c.Cp);
     const size_t oInts = carve(sizeof(int) * n_ints);
+    const size_t oKeys = carve(sizeof(uint64_t) * static_cast<size_t>(c.Cp) * c.kstride);
+    const size_t oA3 = carve(c.split_proj ? 3 * plane * sizeof(uint16_t) : 0);
     if (off > kStaticScratchBytes)
         return fail(ESS_ERR_UNSUPPORTED,
                     "this shape needs %zu bytes of device memory; the static buffer holds %zu", off,
@@ -1816,6 +1843,8 @@ ess_status ess_transition_explicit_static(int32_t d, int32_t m, int32_t n_chains
     c.Q = mem + oQ;
     c.AB = mem + oAB;
     c.rej = reinterpret_cast<long long*>(mem + oRej);
+    c.keys = c.kstride ? reinterpret_cast<uint64_t*>(mem + oKeys) : nullptr;
+    c.A3 = c.split_proj ? reinterpret_cast<uint16_t*>(mem + oA3) : nullptr;
     int* ints = reinterpret_cast<int*>(mem + oInts);
     c.sel = ints;
     c.flag = ints + c.Cp;
@@ -1834,6 +1863,13 @@ ess_status ess_transition_explicit_static(int32_t d, int32_t m, int32_t n_chains
         ESS_TRY(pad_copy<float>(A, m, d, c.A, c.mp, c.dp, c.st));
         ESS_TRY(pad_copy<float>(x, n_chains, d, c.X, c.Cp, c.dp, c.st));
         ESS_TRY(pad_copy<float>(nu, n_chains, d, c.N, c.Cp, c.dp, c.st));
+        if (c.split_proj) {
+            const unsigned grid = static_cast<unsigned>(std::min<size_t>((plane / 2 + 255) / 256, 4096));
+            hipLaunchKernelGGL(split_rows_kernel, dim3(grid), dim3(256), 0, c.st,
+                               static_cast<const float*>(c.A), plane, c.A3, c.A3 + plane,
+                               c.A3 + 2 * plane);
+            HIP_TRY(hipGetLastError());
+        }
     } else {
         ESS_TRY(pad_copy<double>(A, m, d, c.A, c.mp, c.dp, c.st));
         ESS_TRY(pad_copy<double>(x, n_chains, d, c.X, c.Cp, c.dp, c.st));

@@ -88,6 +88,8 @@ struct SampleArgs {
     int* fb_count;        // [2]: list length, indexed by step parity
     int force_full;       // 1: every chain takes the full path
     void* ab;             // more than 4096 rows: [Cp][mp] double2, alpha and beta per row
+    uint64_t* keys;       // more than 16384 rows: [Cp][kstride] sort keys of the full sort
+    int kstride;          // a power of two >= m
 };
 
 __device__ __forceinline__ uint32_t abs_step(const SampleArgs& a) {
@@ -1726,8 +1728,11 @@ __global__ __launch_bounds__(64) void sample_alg2_kernel(SampleArgs a) {
 }
 
 // Rows beyond 4096: 512 threads per chain, the chunked bucket path with
-// refinement; chains it cannot resolve go to the full sort of keys only.
-constexpr int kMaxRowsLarge = 16384;
+// refinement; chains it cannot resolve go to the full sort of keys only, in
+// LDS up to kMaxRowsLds rows and in global memory beyond (the keys carry the
+// row in 16 bits).
+constexpr int kMaxRowsLds = 16384;
+constexpr int kMaxRowsLarge = 65536;
 
 // Roots of every row of every chain ahead of sample_large_kernel: one thread
 // per row and many workgroups per chain, so the float64 solves spread over
@@ -1773,19 +1778,27 @@ __global__ __launch_bounds__(512) void sample_large_kernel(SampleArgs a) {
     else if (threadIdx.x == 0) a.fb_list[atomicAdd(a.fb_count + (step & 1), 1)] = c;
 }
 
-template <typename T>
+// The chains sample_large_kernel handed over: the full sort of their keys,
+// with alpha and beta of every row read back from a.ab (large_roots_kernel
+// solved them this step).  GLOBAL: the keys live in the chain's row of a.keys
+// instead of LDS, for more than kMaxRowsLds rows (a bitonic network over
+// global memory, slow but only for chains whose survivors overflow).
+template <typename T, bool GLOBAL = false>
 __global__ __launch_bounds__(256) void fallback_large_kernel(SampleArgs a) {
-    __shared__ uint64_t s_key[kMaxRowsLarge];
+    __shared__ uint64_t s_key[GLOBAL ? 1 : kMaxRowsLds];
     __shared__ double s_red[4];
     __shared__ int s_cnt[4];
     __shared__ double s_bcast[2];
     __shared__ int s_kstar;
     __shared__ double s_theta[2];
-    const FullLds L{nullptr, nullptr, s_key, s_red, s_cnt, s_bcast, &s_kstar, s_theta};
     const int count = a.fb_count[abs_step(a) & 1];
     for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
-        const ChainRef<T> r = make_ref<T>(a, a.fb_list[idx]);
-        move_chain<T>(r, full_chain<T, KEYS_ROW>(r, *r.sel, L));
+        const int c = a.fb_list[idx];
+        uint64_t* key = GLOBAL ? a.keys + static_cast<size_t>(c) * a.kstride : s_key;
+        const FullLds L{nullptr, nullptr, key, s_red, s_cnt, s_bcast, &s_kstar, s_theta};
+        const ChainRef<T> r = make_ref<T>(a, c);
+        const double2* abg = static_cast<const double2*>(a.ab) + static_cast<size_t>(c) * a.mp;
+        move_chain<T>(r, full_chain<T, KEYS_ROW_AB>(r, *r.sel, L, abg));
         __syncthreads();
     }
 }

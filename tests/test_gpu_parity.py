@@ -73,6 +73,9 @@ CASES = [
     ("large_m_f64", 30, 9000, 8, 64, 0.0),
     ("large_m_many_f32", 30, 5000, 300, 32, 1e-6),
     ("max_large_m_f32", 20, 16384, 4, 32, 1e-6),
+    # more than 16384 rows: the full sort's keys in device memory
+    ("large_m_global_keys_f32", 12, 32768, 6, 32, 1e-6),
+    ("large_m_global_keys_max_f64", 8, 65536, 2, 64, 0.0),
 ]
 LARGE = [c for c in CASES if c[0].startswith("large_m")]
 
@@ -349,7 +352,7 @@ def test_errors_are_reported(E):
         E.Sampler(pr.A, pr.b, np.full(pr.d, 50.0), 4, precision=64)
     assert ei.value.status == E.ESS_ERR_INFEASIBLE_START and "chain 0" in str(ei.value)
     with pytest.raises(E.EssError) as ei:
-        E.Sampler(np.zeros((20000, 3)), np.ones(20000), np.zeros(3), 2)
+        E.Sampler(np.zeros((65537, 3)), np.ones(65537), np.zeros(3), 2)
     assert ei.value.status == E.ESS_ERR_UNSUPPORTED
     with pytest.raises(E.EssError) as ei:
         E.Sampler(pr.A, pr.b, pr.x0, 4, precision=16)

@@ -62,7 +62,9 @@ def without_allocation(E, A, b, x, nu, u, precision, eps):
 
 
 @pytest.mark.parametrize("precision,shapes", [
-    (32, [(1000, 2000, 300), (60, 150, 40)]),      # more than 256 chains, then ragged and few
+    # 128 x 128 tiles and the split projections, more than 256 chains with
+    # 64 x 64 tiles, then ragged and few
+    (32, [(64, 2000, 1024), (1000, 2000, 300), (60, 150, 40)]),
     (64, [(65, 300, 130), (10, 20, 16)]),
 ])
 def test_static_transition_equals_the_context_transition(E, precision, shapes):
