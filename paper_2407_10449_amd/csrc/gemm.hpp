@@ -341,41 +341,47 @@ __device__ __forceinline__ void gemm_tile_split(const uint16_t* __restrict__ A0,
     const size_t ao0 = static_cast<size_t>(m0 + r0) * K + q0, ao1 = static_cast<size_t>(m0 + r1) * K + q1;
     const size_t bo0 = static_cast<size_t>(r0) * K + q0, bo1 = static_cast<size_t>(r1) * K + q1;
     const int lo0 = r0 * LK + q0, lo1 = r1 * LK + q1;
-    uint4 a00, a01, a02, a10, a11, a12;
-    float4 b0a, b0b, b1a, b1b;
-    auto gload = [&](int k0) {
-        a00 = *reinterpret_cast<const uint4*>(A0 + ao0 + k0);
-        a01 = *reinterpret_cast<const uint4*>(A1 + ao0 + k0);
-        a02 = *reinterpret_cast<const uint4*>(A2 + ao0 + k0);
-        b0a = *reinterpret_cast<const float4*>(Bb + bo0 + k0);
-        b0b = *reinterpret_cast<const float4*>(Bb + bo0 + k0 + 4);
-        if constexpr (LD == 2) {
-            a10 = *reinterpret_cast<const uint4*>(A0 + ao1 + k0);
-            a11 = *reinterpret_cast<const uint4*>(A1 + ao1 + k0);
-            a12 = *reinterpret_cast<const uint4*>(A2 + ao1 + k0);
-            b1a = *reinterpret_cast<const float4*>(Bb + bo1 + k0);
-            b1b = *reinterpret_cast<const float4*>(Bb + bo1 + k0 + 4);
-        }
-    };
-    auto lstore = [&](int buf) {
-        uint4 h, m, l;
-        split8(b0a, b0b, h, m, l);
-        *reinterpret_cast<uint4*>(&L.a[buf][0][lo0]) = a00;
-        *reinterpret_cast<uint4*>(&L.a[buf][1][lo0]) = a01;
-        *reinterpret_cast<uint4*>(&L.a[buf][2][lo0]) = a02;
-        *reinterpret_cast<uint4*>(&L.b[buf][0][lo0]) = h;
-        *reinterpret_cast<uint4*>(&L.b[buf][1][lo0]) = m;
-        *reinterpret_cast<uint4*>(&L.b[buf][2][lo0]) = l;
-        if constexpr (LD == 2) {
-            split8(b1a, b1b, h, m, l);
-            *reinterpret_cast<uint4*>(&L.a[buf][0][lo1]) = a10;
-            *reinterpret_cast<uint4*>(&L.a[buf][1][lo1]) = a11;
-            *reinterpret_cast<uint4*>(&L.a[buf][2][lo1]) = a12;
-            *reinterpret_cast<uint4*>(&L.b[buf][0][lo1]) = h;
-            *reinterpret_cast<uint4*>(&L.b[buf][1][lo1]) = m;
-            *reinterpret_cast<uint4*>(&L.b[buf][2][lo1]) = l;
-        }
-    };
+    // one slab's staged operands; two sets, so a slab's loads are issued two
+    // slabs before they are stored to LDS (the A pieces and x' / nu rows come
+    // from L2 or the MALL, whose latency exceeds one slab of matrix work)
+    // two register sets (suffix _0 and _1) of one slab's operands each
+    uint4 a00_0, a01_0, a02_0, a10_0, a11_0, a12_0, a00_1, a01_1, a02_1, a10_1, a11_1, a12_1;
+    float4 b0a_0, b0b_0, b1a_0, b1b_0, b0a_1, b0b_1, b1a_1, b1b_1;
+#define ESS_SPLIT_GLOAD(S, k0)                                                     \
+    do {                                                                           \
+        a00##S = *reinterpret_cast<const uint4*>(A0 + ao0 + (k0));                 \
+        a01##S = *reinterpret_cast<const uint4*>(A1 + ao0 + (k0));                 \
+        a02##S = *reinterpret_cast<const uint4*>(A2 + ao0 + (k0));                 \
+        b0a##S = *reinterpret_cast<const float4*>(Bb + bo0 + (k0));                \
+        b0b##S = *reinterpret_cast<const float4*>(Bb + bo0 + (k0) + 4);            \
+        if constexpr (LD == 2) {                                                   \
+            a10##S = *reinterpret_cast<const uint4*>(A0 + ao1 + (k0));             \
+            a11##S = *reinterpret_cast<const uint4*>(A1 + ao1 + (k0));             \
+            a12##S = *reinterpret_cast<const uint4*>(A2 + ao1 + (k0));             \
+            b1a##S = *reinterpret_cast<const float4*>(Bb + bo1 + (k0));            \
+            b1b##S = *reinterpret_cast<const float4*>(Bb + bo1 + (k0) + 4);        \
+        }                                                                          \
+    } while (0)
+#define ESS_SPLIT_LSTORE(S, buf)                                                   \
+    do {                                                                           \
+        uint4 h_, m_, l_;                                                          \
+        split8(b0a##S, b0b##S, h_, m_, l_);                                        \
+        *reinterpret_cast<uint4*>(&L.a[buf][0][lo0]) = a00##S;                     \
+        *reinterpret_cast<uint4*>(&L.a[buf][1][lo0]) = a01##S;                     \
+        *reinterpret_cast<uint4*>(&L.a[buf][2][lo0]) = a02##S;                     \
+        *reinterpret_cast<uint4*>(&L.b[buf][0][lo0]) = h_;                         \
+        *reinterpret_cast<uint4*>(&L.b[buf][1][lo0]) = m_;                         \
+        *reinterpret_cast<uint4*>(&L.b[buf][2][lo0]) = l_;                         \
+        if constexpr (LD == 2) {                                                   \
+            split8(b1a##S, b1b##S, h_, m_, l_);                                    \
+            *reinterpret_cast<uint4*>(&L.a[buf][0][lo1]) = a10##S;                 \
+            *reinterpret_cast<uint4*>(&L.a[buf][1][lo1]) = a11##S;                 \
+            *reinterpret_cast<uint4*>(&L.a[buf][2][lo1]) = a12##S;                 \
+            *reinterpret_cast<uint4*>(&L.b[buf][0][lo1]) = h_;                     \
+            *reinterpret_cast<uint4*>(&L.b[buf][1][lo1]) = m_;                     \
+            *reinterpret_cast<uint4*>(&L.b[buf][2][lo1]) = l_;                     \
+        }                                                                          \
+    } while (0)
 
     f32x4 acc[TM][TN];
 #pragma unroll
@@ -393,13 +399,8 @@ __device__ __forceinline__ void gemm_tile_split(const uint16_t* __restrict__ A0,
             }
     }
 
-    const int KT = K / BK;
-    gload(0);
-    lstore(0);
-    __syncthreads();
-    for (int kt = 0; kt < KT; ++kt) {
-        const int buf = kt & 1;
-        if (kt + 1 < KT) gload((kt + 1) * BK);
+    // slab kt: the six products of its fragments from LDS buffer kt & 1
+    auto compute = [&](int buf) {
         // lane l supplies k = 8 (l / 16) .. + 7 of row l % 16 for A and of
         // column l % 16 for B; the output is rows 4 (l / 16) .. + 3 of column l % 16
         const int kofs = 8 * (lane >> 4);
@@ -429,9 +430,31 @@ __device__ __forceinline__ void gemm_tile_split(const uint16_t* __restrict__ A0,
                 c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bfr[0][j], c, 0, 0, 0);
                 acc[i][j] = c;
             }
-        if (kt + 1 < KT) lstore(buf ^ 1);
+    };
+
+    // pipeline: slab kt in LDS, slab kt + 1 staged in registers, slab kt + 2
+    // being fetched; two iterations per trip so the register sets keep their
+    // roles (K is a multiple of 32; an odd slab count ends with one half trip)
+    const int KT = K / BK;
+    ESS_SPLIT_GLOAD(_0, 0);
+    ESS_SPLIT_LSTORE(_0, 0);
+    if (KT > 1) ESS_SPLIT_GLOAD(_1, BK);
+    __syncthreads();
+    for (int kt = 0; kt < KT; kt += 2) {
+        // even slab kt: set _1 holds slab kt + 1, set _0 is free
+        if (kt + 2 < KT) ESS_SPLIT_GLOAD(_0, (kt + 2) * BK);
+        compute(0);
+        if (kt + 1 < KT) ESS_SPLIT_LSTORE(_1, 1);
+        __syncthreads();
+        if (kt + 1 >= KT) break;
+        // odd slab kt + 1: set _0 holds slab kt + 2, set _1 is free
+        if (kt + 3 < KT) ESS_SPLIT_GLOAD(_1, (kt + 3) * BK);
+        compute(1);
+        if (kt + 2 < KT) ESS_SPLIT_LSTORE(_0, 0);
         __syncthreads();
     }
+#undef ESS_SPLIT_GLOAD
+#undef ESS_SPLIT_LSTORE
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
