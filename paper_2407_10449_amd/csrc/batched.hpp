@@ -30,6 +30,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "gemm.hpp"
 #include "sample.hpp"
 
@@ -46,6 +48,7 @@ __host__ __device__ constexpr int shape_bn(int s) { return (s & 2) ? 32 : 64; }
 struct ProbDesc {
     int d, m, C, dp, mp, Cp;
     int shape;           // projection tile shape (see shape_bm / shape_bn)
+    int cls;             // chain class: m <= 256 2^cls
     int tiles_n;         // tile columns: 2 Cp / shape_bn(shape)
     int ntiles;          // tiles: ceil(m / shape_bm(shape)) x tiles_n
     int chain_off;       // first padded chain index (sel / flag / rej)
@@ -65,7 +68,7 @@ struct BatchArgs {
     const int* wg_prob;    // [NT + NC]: the problem of each workgroup of the step launch
     const int4* tiles;     // [NTL]: (problem, tile row, tile column, 0) or (-1, ...) padding
     int NTL;               // entries of the tile table (NT plus padding)
-    const int2* chains;    // [NC]: (problem, chain) in the caller's order
+    const int2* chains;    // [NC]: (problem, chain), larger chain classes first
     const float* A;
     const double* b;
     float* X;
@@ -179,12 +182,18 @@ __device__ __forceinline__ void batch_tile(const BatchArgs& a, const ProbDesc& p
     }
 }
 
-template <int NB, int NK>
+// LDS of a chain item: the bucket arrays of its class or, for a chain the
+// bucket path hands back, the keys of the full sort done in place.  The
+// fused form adds the projection tiles' arrays to the union.
+template <int NK, bool GEMM>
 struct BatchLds {
     union {
-        BatchGemmLds g;
-        BucketLds<NB> bucket;
-        uint64_t key[NK];   // the full sort of a chain the bucket path hands back
+        BucketLds<256> b0;
+        BucketLds<512> b1;
+        BucketLds<1024> b2;
+        BucketLds<2048> b3;
+        uint64_t key[NK];
+        typename std::conditional<GEMM, BatchGemmLds, char>::type g;
     };
     double red[8];
     int cnt[8];
@@ -196,25 +205,54 @@ struct BatchLds {
 // The per-chain part of a batched step after the commit: the bucket path, and
 // for a chain whose survivors overflow the full sort in place from its roots,
 // which the bucket path leaves in a.ab (keys in the bucket arrays' LDS).
-template <int RPT, int NB, typename Lds>
+template <int RPT, int NB>
 __device__ __forceinline__ void batch_sample(const BatchArgs& a, const ProbDesc& pd, int c,
-                                             const ChainRef<float>& r, int sel, Lds& lds) {
+                                             const ChainRef<float>& r, int sel,
+                                             BucketLds<NB>& bucket, const FullLds& L) {
     double2* abg = a.ab + pd.q_off + static_cast<size_t>(c) * pd.mp;
     double theta = 0.0;
-    if (!bucket_chain<float, RPT, NB>(r, sel, lds.bucket, theta, nullptr, abg)) {
+    if (!bucket_chain<float, RPT, NB>(r, sel, bucket, theta, nullptr, abg)) {
         __syncthreads();   // every row's alpha and beta is in a.ab
-        const FullLds L{nullptr, nullptr, lds.key, lds.red, lds.cnt, lds.bcast, &lds.kstar, lds.theta};
         theta = full_chain<float, KEYS_ROW_AB, 256>(r, sel, L, abg);
     }
     move_chain<float>(r, theta);
 }
 
+// The chain's class picks the rows per thread and the bucket count, so a
+// chain of a small problem runs no more passes and bucket sweeps than its
+// rows need, whatever the largest problem of the batch: up to 256 rows one
+// row per thread and 256 buckets, up to 1024 rows four and 1024 buckets (two
+// and 512 when no problem is larger), the rest the batch's largest.  When
+// some problem has more than 2048 rows, only the first class is kept apart.
+// A further variant inlined beside these has put the row arrays of every
+// variant in scratch memory.  The bucket path's result does not depend on
+// the bucket count (survivors that coarser buckets add have empty
+// candidates), so the chains are those of the single-problem kernels.
+template <int RPT_MAX, typename Lds>
+__device__ __forceinline__ void batch_sample_class(const BatchArgs& a, const ProbDesc& pd, int c,
+                                                   const ChainRef<float>& r, int sel, Lds& lds) {
+    const FullLds L{nullptr, nullptr, lds.key, lds.red, lds.cnt, lds.bcast, &lds.kstar, lds.theta};
+    const int cls = __builtin_amdgcn_readfirstlane(pd.cls);
+    constexpr int MID = RPT_MAX > 8 ? 1 : (RPT_MAX < 4 ? RPT_MAX : 4);
+    constexpr int TOP = RPT_MAX > 8 ? 1 : 3;   // first class of the largest variant
+    if constexpr (RPT_MAX > 4) {
+        if (cls >= TOP) return batch_sample<RPT_MAX, 2048>(a, pd, c, r, sel, lds.b3, L);
+    }
+    if constexpr (MID > 1) {
+        if (cls >= 1) {
+            if constexpr (MID == 4) return batch_sample<4, 1024>(a, pd, c, r, sel, lds.b2, L);
+            else return batch_sample<2, 512>(a, pd, c, r, sel, lds.b1, L);
+        }
+    }
+    batch_sample<1, 256>(a, pd, c, r, sel, lds.b0, L);
+}
+
 template <int RPT>
 constexpr int batch_keys() { return RPT * 256 > 512 ? RPT * 256 : 512; }
 
-template <int RPT, int NB>
+template <int RPT_MAX>
 __global__ __launch_bounds__(256) void batched_step_kernel(BatchArgs a) {
-    __shared__ __attribute__((aligned(16))) BatchLds<NB, batch_keys<RPT>()> lds;
+    __shared__ __attribute__((aligned(16))) BatchLds<batch_keys<RPT_MAX>(), true> lds;
     __shared__ int s_item;
     const int tid = threadIdx.x;
     const int par = static_cast<int>(abs_step(a) & 1u);
@@ -255,18 +293,20 @@ __global__ __launch_bounds__(256) void batched_step_kernel(BatchArgs a) {
     __syncthreads();
     const ChainRef<float> r = batch_ref(a, pd, p, c);
     const int sel = a.has_pending ? commit_chain<float>(r) : *r.sel;
-    if (a.do_sample) batch_sample<RPT, NB>(a, pd, c, r, sel, lds);
+    if (a.do_sample) batch_sample_class<RPT_MAX>(a, pd, c, r, sel, lds);
 }
 
 // Split form, second launch: one workgroup per chain (the caller's order).
-template <int RPT, int NB>
-__global__ __launch_bounds__(256, RPT <= 8 ? 6 : 1) void batched_chain_kernel(BatchArgs a) {
-    __shared__ __attribute__((aligned(16))) BucketOrKeys<NB, batch_keys<RPT>()> lds;
+// Chains of the larger classes come first in a.chains, so the longest items
+// start early.
+template <int RPT_MAX>
+__global__ __launch_bounds__(256, RPT_MAX <= 4 ? 6 : 1) void batched_chain_kernel(BatchArgs a) {
+    __shared__ __attribute__((aligned(16))) BatchLds<batch_keys<RPT_MAX>(), false> lds;
     const int2 ch = a.chains[blockIdx.x];
     const ProbDesc& pd = a.descs[ch.x];
     const ChainRef<float> r = batch_ref(a, pd, ch.x, ch.y);
     const int sel = a.has_pending ? commit_chain<float>(r) : *r.sel;
-    if (a.do_sample) batch_sample<RPT, NB>(a, pd, ch.y, r, sel, lds);
+    if (a.do_sample) batch_sample_class<RPT_MAX>(a, pd, ch.y, r, sel, lds);
 }
 
 // Projection tiles, one block per entry of the tile table (split form, and

@@ -141,7 +141,7 @@ struct ess_ctx {
     long long prof_n[4] = {0, 0, 0, 0};
     // many problems advanced together (ess_init_batched)
     struct Batch {
-        int n = 0, NT = 0, NTL = 0, NC = 0, rpt = 1, nb = 256;
+        int n = 0, NT = 0, NTL = 0, NC = 0, rpt = 1;
         bool fused = false;          // one launch per step instead of tiles, then chains
         long long state_elems = 0;   // sum of C d (caller layout)
         int chains_padded = 0;
@@ -654,12 +654,12 @@ BatchArgs batch_args(const ess_ctx* c) {
     return a;
 }
 
-template <int RPT, int NB>
+template <int RPT_MAX>
 ess_status launch_step_t(ess_ctx* c, const BatchArgs& a, hipStream_t st) {
     const ess_ctx::Batch& B = *c->batch;
     if (B.fused)
         return timed(c, ESS_KERNEL_BATCHED, st, [&] {
-            hipLaunchKernelGGL((batched_step_kernel<RPT, NB>), dim3(a.NT + a.NC), dim3(256), 0, st, a);
+            hipLaunchKernelGGL((batched_step_kernel<RPT_MAX>), dim3(a.NT + a.NC), dim3(256), 0, st, a);
             HIP_TRY(hipGetLastError());
             return ESS_OK;
         });
@@ -669,19 +669,20 @@ ess_status launch_step_t(ess_ctx* c, const BatchArgs& a, hipStream_t st) {
         return ESS_OK;
     }));
     return timed(c, ESS_KERNEL_SAMPLE, st, [&] {
-        hipLaunchKernelGGL((batched_chain_kernel<RPT, NB>), dim3(a.NC), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((batched_chain_kernel<RPT_MAX>), dim3(a.NC), dim3(256), 0, st, a);
         HIP_TRY(hipGetLastError());
         return ESS_OK;
     });
 }
 
+// The kernels carry the chain classes up to the largest problem's.
 ess_status launch_batched_step(ess_ctx* c, const BatchArgs& a, hipStream_t st) {
     const ess_ctx::Batch& B = *c->batch;
-    if (B.nb == 256) return launch_step_t<1, 256>(c, a, st);
-    if (B.rpt <= 2) return launch_step_t<2, 2048>(c, a, st);
-    if (B.rpt <= 4) return launch_step_t<4, 2048>(c, a, st);
-    if (B.rpt <= 8) return launch_step_t<8, 2048>(c, a, st);
-    return launch_step_t<16, 2048>(c, a, st);
+    if (B.rpt <= 1) return launch_step_t<1>(c, a, st);
+    if (B.rpt <= 2) return launch_step_t<2>(c, a, st);
+    if (B.rpt <= 4) return launch_step_t<4>(c, a, st);
+    if (B.rpt <= 8) return launch_step_t<8>(c, a, st);
+    return launch_step_t<16>(c, a, st);
 }
 
 // A x for the rows in X (p_direct) with the strict start check, then the flags.
@@ -818,6 +819,8 @@ ess_status batched_init(ess_ctx* c, const ess_problem* pr, int n) {
         d.mp = round_up(d.m, kBatchPadM);
         d.Cp = round_up(d.C, kBatchPadC);
         d.chain_off = chain_off;
+        d.cls = 0;
+        while ((256 << d.cls) < d.m) ++d.cls;
         d.a_off = a_off;
         d.b_off = b_off;
         d.x_off = x_off;
@@ -845,7 +848,6 @@ ess_status batched_init(ess_ctx* c, const ess_problem* pr, int n) {
     // greedy by count: list lengths differ by at most one panel
     B.max_table = static_cast<int>(max_tiles + 8ll * (max_panel + 1));
     B.rpt = (max_m + 255) / 256;
-    B.nb = max_m <= 256 ? 256 : 2048;
     // problems with the most projection work first, so their tiles start early
     B.order.resize(n);
     std::iota(B.order.begin(), B.order.end(), 0);
@@ -853,9 +855,12 @@ ess_status batched_init(ess_ctx* c, const ess_problem* pr, int n) {
         return static_cast<long long>(B.h[x].mp) * B.h[x].dp * B.h[x].Cp >
                static_cast<long long>(B.h[y].mp) * B.h[y].dp * B.h[y].Cp;
     });
+    // chains of the larger classes first, so the longest chain items start early
     std::vector<int2> chains;
-    for (int p = 0; p < n; ++p)
-        for (int ch = 0; ch < B.h[p].C; ++ch) chains.push_back(make_int2(p, ch));
+    for (int cls = 4; cls >= 0; --cls)
+        for (int p = 0; p < n; ++p)
+            if (B.h[p].cls == cls)
+                for (int ch = 0; ch < B.h[p].C; ++ch) chains.push_back(make_int2(p, ch));
     B.NC = static_cast<int>(chains.size());
 
     ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.descs), sizeof(ProbDesc) * n));

@@ -1,4 +1,5 @@
 """Batched contexts: many uneven polytopes advanced by one launch per step."""
+import math
 import sys
 
 import numpy as np
@@ -37,7 +38,23 @@ def test_batched_matches_oracle_per_step(E):
     batch reached, the oracle's transition with the step's Philox draws
     (problem word p) gives the decision and the new state to 1e-5.  Four
     steps, so the states are generic mid-chain states after the first."""
-    probs = problems(10, 16)
+    per_step_against_oracle(E, problems(10, 16))
+
+
+def test_batched_with_a_problem_above_2048_rows_per_step(E):
+    """A problem of 3000 rows beside small ones (the chain kernels' widest
+    variant, with every smaller chain in one class of its own), per step
+    against the oracle as above."""
+    rng = np.random.default_rng(41)
+    probs = problems(5, 16, seed=41)
+    d, m = 48, 3000
+    A = rng.standard_normal((m, d)) / math.sqrt(d)
+    probs.insert(2, dict(A=A, b=rng.uniform(0.5, 1.5, m), x0=np.zeros(d), n_chains=16,
+                         seed=777, trim_eps=1e-6))
+    per_step_against_oracle(E, probs)
+
+
+def per_step_against_oracle(E, probs):
     say("[batched] shapes", [(p["A"].shape, p["n_chains"]) for p in probs])
     s = E.BatchedSampler(probs)
     x_prev = [x.astype(np.float64) for x in s.split(s.state()[0].cpu().numpy())]
