@@ -428,7 +428,12 @@ void launch_sample_t(const ess_ctx* c, const Group& g, hipStream_t st, const Sam
     } else if (rpt <= 4) {
         hipLaunchKernelGGL((sample_bucket_kernel<T, 4, 2048>), grid, b, 0, st, a);
     } else if (rpt <= 8) {
-        hipLaunchKernelGGL((sample_bucket_kernel<T, 4, 2048, 512>), grid, b2, 0, st, a);
+        if (std::getenv("ESS_ROOTS_PREPASS")) {
+            const long long blocks = static_cast<long long>((c->m + 255) / 256) * g.n;
+            hipLaunchKernelGGL((large_roots_kernel<T>), dim3(static_cast<unsigned>(blocks)), b, 0, st, a);
+            hipLaunchKernelGGL((sample_bucket_kernel<T, 4, 2048, 512, false, true>), grid, b2, 0, st, a);
+        } else
+            hipLaunchKernelGGL((sample_bucket_kernel<T, 4, 2048, 512>), grid, b2, 0, st, a);
     } else {
         hipLaunchKernelGGL((sample_bucket_kernel<T, 8, 2048, 512>), grid, b2, 0, st, a);
     }

@@ -1387,8 +1387,11 @@ __global__ __launch_bounds__(BS, (BS == 512 && RPT <= 4 && !REFINE) ? 8 : 1) voi
         const PairAhead<T> ahead = pair_ahead<T>(r, from_prop);
         double theta = 0.0;
         if (!a.force_full) {
-            done = bucket_chain<T, RPT, NB, BS, false>(r, sel, lds.bucket, theta, nullptr, abg);
-        } else {
+            if constexpr (PRE)
+                done = bucket_chain<T, RPT, NB, BS, false>(r, sel, lds.bucket, theta, abg, nullptr);
+            else
+                done = bucket_chain<T, RPT, NB, BS, false>(r, sel, lds.bucket, theta, nullptr, abg);
+        } else if constexpr (!PRE) {
             double al[RPT], be[RPT];
             block_roots<T, RPT, BS>(r, r.P0 + static_cast<size_t>(sel) * r.pstride, 0, true, al, be);
             store_ab<RPT, BS>(abg, 0, r.m, al, be);

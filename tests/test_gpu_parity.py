@@ -139,10 +139,15 @@ def test_near_tangent_rows_cross_both_root_branches(E):
         assert abs(g["theta"][c] - ref2["theta"][c]) <= 1e-5 * max(1.0, len(gi)), c
 
 
-def test_explicit_full_size_gp_rbf(E):
+@pytest.mark.parametrize("roots", ["in_kernel", "prepass"])
+def test_explicit_full_size_gp_rbf(E, monkeypatch, roots):
     """d=1000, m=2000, 1024 chains (the benchmarked shape and kernel), from
-    mid-chain states: 128 sampled chains, tier 1 and tier 2."""
-    say("[explicit] gp_rbf full size")
+    mid-chain states: 128 sampled chains, tier 1 and tier 2.  `prepass`: the
+    measured alternative with every root solved ahead of the per-chain kernel
+    (ESS_ROOTS_PREPASS)."""
+    if roots == "prepass":
+        monkeypatch.setenv("ESS_ROOTS_PREPASS", "1")
+    say(f"[explicit] gp_rbf full size, roots {roots}")
     pr = synth.gp_rbf()
     Ab, x, nu, u, g, ref, ref2 = explicit_case(E, pr.A, pr.b, pr.n_chains, 32, seed=0, eps=1e-6,
                                                n_ref=128, rng_seed=3)
