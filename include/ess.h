@@ -192,17 +192,27 @@ ess_status ess_transition_explicit_static(int32_t d, int32_t m, int32_t n_chains
  * theta uniforms u (n_chains double, nullable).  Does not change the context. */
 ess_status ess_draw(ess_ctx* ctx, uint64_t step, void* nu, double* u);
 
-/* Autotuner for batched contexts (ess_init_batched).  Problems fall into six
- * size classes (d <= 64, d <= 192, d > 192, each split at m <= 256); each
- * class has its own projection tile shape (64x64, 32x64, 64x32 or 32x32 rows
- * x chain columns).  One pass of coordinate descent times every shape of
- * every class present, the other classes fixed, each trial 2 x steps_per_trial
- * steps (the first captures and warms the graph, the second is timed), keeps
- * the fastest, and stores it in a JSON cache keyed by GPU architecture and
- * workload ($ESS_TUNE_CACHE, default ~/.cache/ess_tune.json), which later
- * batched contexts of the same workload load at init.  The chains' state and
- * step counter are restored afterwards.  report (host, nullable) receives one
- * line per trial.  A single-problem context returns ESS_ERR_UNSUPPORTED. */
+/* Autotuner of the projection kernels (Section 2's products A x and A nu;
+ * the sampled chains do not depend on the choice in a batched context).
+ * Every trial runs 2 x steps_per_trial steps (the first captures and warms
+ * the graph, the second is timed); the fastest choice is kept and stored in
+ * a JSON cache keyed by GPU architecture and workload ($ESS_TUNE_CACHE,
+ * default ~/.cache/ess_tune.json), which later contexts of the same workload
+ * load at init.  The chains' state, step counter and rejection counts are
+ * restored afterwards.  report (host, nullable) receives one line per trial
+ * and a last line "chosen: ...".
+ * Batched contexts (ess_init_batched): problems fall into six size classes
+ *   (d <= 64, d <= 192, d > 192, each split at m <= 256), each with its own
+ *   tile shape (64x64, 32x64, 64x32 or 32x32 rows x chain columns); one pass
+ *   of coordinate descent over the classes present, then the other launch
+ *   form.
+ * Single-problem contexts: in precision 32 the split bfloat16 tiles (128 x
+ *   128) and the float32 tiles 128x128, 128x64, 64x128 and 64x64, then the
+ *   band height (1 to 16 tile rows) of the XCD-aware tile order; precision
+ *   64 tunes the band height only.  A context of at most 12 chains (the
+ *   row-parallel projection) has nothing to tune and reports so.  The chains
+ *   continue from the restored state on the chosen kernels, whose float32
+ *   sums may round differently from the previous choice. */
 ess_status ess_autotune(ess_ctx* ctx, int32_t steps_per_trial, char* report, int32_t report_len);
 
 /* Kernel timing for measurement.  While enabled, every launch made by ess_run

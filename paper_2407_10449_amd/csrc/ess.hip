@@ -970,6 +970,20 @@ ess_status drop_graphs(ess_ctx* c) {
     return ESS_OK;
 }
 
+// A's three bfloat16 pieces for the split projections (allocated once).
+ess_status split_A(ess_ctx* c) {
+    if (c->A3) return ESS_OK;
+    const size_t plane = static_cast<size_t>(c->mp) * c->dp;
+    ESS_TRY(dalloc(c, reinterpret_cast<void**>(&c->A3), 3 * plane * sizeof(uint16_t)));
+    const unsigned grid = static_cast<unsigned>(std::min<size_t>((plane / 2 + 255) / 256, 4096));
+    hipLaunchKernelGGL(split_rows_kernel, dim3(grid), dim3(256), 0, c->st,
+                       static_cast<const float*>(c->A), plane, c->A3, c->A3 + plane,
+                       c->A3 + 2 * plane);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(ESS_ERR_HIP, "splitting A: %s", hipGetErrorString(e));
+    return ESS_OK;
+}
+
 // ---------------------------------------------------------------- autotuning
 // Tile choices per batched workload, cached in a small JSON file:
 //   {"<key>": {"shape_code": 1365, "fused": 0, "us_per_step": 162.5}, ...}
@@ -1068,7 +1082,7 @@ int max_shape_code() {
 // The cached choice for this workload, then the overrides ESS_BATCH_TILE
 // ("BMxBN" for every size class) and ESS_BATCH_LAUNCH ("split" or "fused").
 ess_status load_tuned(ess_ctx* c) {
-    if (!c->batch) return ESS_OK;   // single-problem tuning is switched off (see ess_autotune)
+    if (!c->batch) return ESS_OK;   // single problems: load_tuned_single at init
     const std::string obj = cache_entry(read_file(tune_cache_path()), tune_key(c));
     if (!obj.empty()) {
         TuneChoice t;
@@ -1094,24 +1108,22 @@ ess_status load_tuned(ess_ctx* c) {
     return batched_layout(c);
 }
 
-void store_tuned(const ess_ctx* c, const TuneChoice& t) {
+// Writes `"key": value` into the cache file, replacing the key's old entry.
+void store_entry(const std::string& key, const std::string& value) {
     const std::string path = tune_cache_path();
     std::string text = read_file(path);
-    const std::string key = tune_key(c);
-    std::ostringstream e;
-    e << "\"" << key << "\": {\"shape_code\": " << t.shape_code << ", \"fused\": " << t.fused
-      << ", \"us_per_step\": " << t.us << "}";
+    const std::string e = "\"" + key + "\": " + value;
     const std::string q = "\"" + key + "\"";
     const size_t at = text.find(q);
     if (at != std::string::npos) {
         const size_t close = text.find('}', at);
-        text.replace(at, close - at + 1, e.str());
+        text.replace(at, close - at + 1, e);
     } else {
         const size_t last = text.rfind('}');
-        if (text.empty() || last == std::string::npos) text = "{\n" + e.str() + "\n}\n";
+        if (text.empty() || last == std::string::npos) text = "{\n" + e + "\n}\n";
         else {
             const bool empty_obj = text.find('"') == std::string::npos;
-            text.insert(last, (empty_obj ? "" : ",\n") + e.str() + "\n");
+            text.insert(last, (empty_obj ? "" : ",\n") + e + "\n");
         }
     }
     const size_t slash = path.rfind('/');
@@ -1123,6 +1135,172 @@ void store_tuned(const ess_ctx* c, const TuneChoice& t) {
     }
     std::ofstream f(path);
     f << text;
+}
+
+void store_tuned(const ess_ctx* c, const TuneChoice& t) {
+    std::ostringstream v;
+    v << "{\"shape_code\": " << t.shape_code << ", \"fused\": " << t.fused
+      << ", \"us_per_step\": " << t.us << "}";
+    store_entry(tune_key(c), v.str());
+}
+
+// ---------------------------------------------------------- single problems
+// A single-problem context's projection kernel: float32 through the split
+// bfloat16 tiles (128 x 128) or float32 matrix-core tiles of 128 or 64 rows
+// by 128 or 64 chain columns (float64: its one 64 x 64 tile), and the band
+// height of the XCD-aware tile order.  Cached under the context's key as
+//   {"split": 1, "bm": 128, "bn": 128, "group_m": 4, "us_per_step": 80.1}.
+// Chain groups, their streams and events are never changed here.
+struct SingleChoice {
+    int split = 0, bm = 64, bn = 64, group_m = 4;
+    double us = 0;
+};
+
+SingleChoice single_current(const ess_ctx* c) {
+    SingleChoice t;
+    t.split = c->split_proj ? 1 : 0;
+    t.bm = c->bm;
+    t.bn = c->bn;
+    t.group_m = c->group_m;
+    return t;
+}
+
+bool single_valid(const ess_ctx* c, const SingleChoice& t) {
+    const bool tile = (t.bm == 64 || t.bm == 128) && (t.bn == 64 || t.bn == 128);
+    if (t.group_m < 1 || t.group_m > 64 || !tile) return false;
+    if (c->prec == 64) return t.split == 0 && t.bm == 64 && t.bn == 64;
+    return !t.split || (t.bm == 128 && t.bn == 128);
+}
+
+// The cached choice for this shape, if any; ESS_PROJ_TILE keeps its tile.
+void load_tuned_single(ess_ctx* c) {
+    const std::string obj = cache_entry(read_file(tune_cache_path()), tune_key(c));
+    if (obj.empty()) return;
+    SingleChoice t;
+    t.split = field(obj, "split", 0) != 0 ? 1 : 0;
+    t.bm = static_cast<int>(field(obj, "bm", 0));
+    t.bn = static_cast<int>(field(obj, "bn", 0));
+    t.group_m = static_cast<int>(field(obj, "group_m", 0));
+    if (!single_valid(c, t)) return;
+    if (!std::getenv("ESS_PROJ_TILE")) {
+        c->bm = t.bm;
+        c->bn = t.bn;
+        c->split_proj = t.split != 0;
+    }
+    c->group_m = t.group_m;
+}
+
+ess_status single_apply(ess_ctx* c, const SingleChoice& t) {
+    c->bm = t.bm;
+    c->bn = t.bn;
+    c->group_m = t.group_m;
+    c->split_proj = t.split != 0;
+    if (c->split_proj) ESS_TRY(split_A(c));
+    return drop_graphs(c);
+}
+
+void store_tuned_single(const ess_ctx* c, const SingleChoice& t) {
+    std::ostringstream v;
+    v << "{\"split\": " << t.split << ", \"bm\": " << t.bm << ", \"bn\": " << t.bn
+      << ", \"group_m\": " << t.group_m << ", \"us_per_step\": " << t.us << "}";
+    store_entry(tune_key(c), v.str());
+}
+
+// Times the candidates on graph replays of steps_per_trial steps each
+// (one pass over the kernel shapes at the current band height, then the
+// band heights for the best shape), keeps the fastest, and puts the chains
+// back where they were: state, step and rejection counts.
+ess_status autotune_single(ess_ctx* c, int32_t steps_per_trial, std::ostringstream& rep,
+                           SingleChoice& best) {
+    struct Scratch {
+        hipStream_t st = nullptr;
+        void* saved = nullptr;
+        long long* rej = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        ~Scratch() {
+            if (saved || rej) (void)hipStreamSynchronize(st);   // no copy still uses them
+            if (saved) (void)hipFree(saved);
+            if (rej) (void)hipFree(rej);
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+        }
+    } scr;
+    scr.st = c->st;
+    const size_t bytes = static_cast<size_t>(c->C) * c->d * c->esz;
+    HIP_TRY(hipMalloc(&scr.saved, bytes));
+    HIP_TRY(hipMalloc(reinterpret_cast<void**>(&scr.rej), sizeof(long long) * c->Cp));
+    ESS_TRY(copy_rows_out(c, scr.saved, c->X));
+    HIP_TRY(hipMemcpyAsync(scr.rej, c->rej, sizeof(long long) * c->Cp, hipMemcpyDeviceToDevice,
+                           c->st));
+    const uint64_t step0 = c->step;
+    HIP_TRY(hipEventCreate(&scr.e0));
+    HIP_TRY(hipEventCreate(&scr.e1));
+
+    auto trial = [&](SingleChoice& t) -> ess_status {
+        ESS_TRY(single_apply(c, t));
+        ESS_TRY(run_dispatch(c, steps_per_trial, 1, nullptr));   // capture and warm
+        c->step += steps_per_trial;
+        HIP_TRY(hipEventRecord(scr.e0, c->st));
+        ESS_TRY(run_dispatch(c, steps_per_trial, 1, nullptr));
+        c->step += steps_per_trial;
+        HIP_TRY(hipEventRecord(scr.e1, c->st));
+        HIP_TRY(hipEventSynchronize(scr.e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, scr.e0, scr.e1));
+        t.us = 1e3 * ms / steps_per_trial;
+        rep << (t.split ? "split" : "f32") << " " << t.bm << "x" << t.bn << ", band "
+            << t.group_m << ": " << t.us << " us/step\n";
+        return ESS_OK;
+    };
+    const SingleChoice before = single_current(c);
+    std::vector<SingleChoice> shapes;
+    if (c->prec == 64) {
+        shapes.push_back(before);
+    } else {
+        const int tiles[4][2] = {{128, 128}, {128, 64}, {64, 128}, {64, 64}};
+        SingleChoice sp;
+        sp.split = 1;
+        sp.bm = sp.bn = 128;
+        sp.group_m = before.group_m;
+        shapes.push_back(sp);
+        for (const auto& tb : tiles) {
+            SingleChoice t;
+            t.bm = tb[0];
+            t.bn = tb[1];
+            t.group_m = before.group_m;
+            shapes.push_back(t);
+        }
+    }
+    ess_status st = ESS_OK;
+    best = before;
+    best.us = 1e30;
+    for (auto& t : shapes) {
+        if (st != ESS_OK) break;
+        st = trial(t);
+        if (st == ESS_OK && t.us < best.us) best = t;
+    }
+    for (const int gm : {1, 2, 4, 8, 16}) {
+        if (st != ESS_OK) break;
+        if (gm == best.group_m) continue;
+        SingleChoice t = best;
+        t.group_m = gm;
+        st = trial(t);
+        if (st == ESS_OK && t.us < best.us) best = t;
+    }
+    // the chains go back to where they were, on the chosen kernels
+    ess_status fin = single_apply(c, st == ESS_OK ? best : before);
+    if (fin == ESS_OK) fin = copy_rows_in(c, c->Xprop, scr.saved);
+    if (fin == ESS_OK) fin = check_rows(c, "ess_autotune", 1);
+    if (fin == ESS_OK) fin = launch_step_counter(c, c->st, step0, 0);
+    if (fin == ESS_OK) fin = prime_direction(c);
+    c->step = step0;
+    if (fin == ESS_OK) {
+        const hipError_t e = hipMemcpyAsync(c->rej, scr.rej, sizeof(long long) * c->Cp,
+                                            hipMemcpyDeviceToDevice, c->st);
+        if (e != hipSuccess) fin = fail(ESS_ERR_HIP, "restoring rejections: %s", hipGetErrorString(e));
+    }
+    if (st != ESS_OK) return st;
+    return fin;
 }
 
 // ---------------------------------------------------------------- network
@@ -1556,25 +1734,16 @@ ess_status ess_init(const ess_problem* pr, void* stream, ess_ctx** out) {
         return bail(ESS_ERR_HIP);
     }
     // float32 projections through exact bfloat16 splits wherever the 128 x
-    // 128 tiles fill the device (ESS_PROJ=f32 keeps the float32 matrix cores)
+    // 128 tiles fill the device, unless a tuned choice for this shape is
+    // cached (ess_autotune); ESS_PROJ=f32 keeps the float32 matrix cores and
+    // ESS_PROJ_TILE a tile shape whatever the cache holds
+    c->split_proj = c->prec == 32 && c->bm == 128 && c->bn == 128;
+    load_tuned_single(c);
     {
         const char* pe = std::getenv("ESS_PROJ");
-        c->split_proj = c->prec == 32 && c->bm == 128 && c->bn == 128 &&
-                        !(pe && std::strcmp(pe, "f32") == 0);
+        if (pe && std::strcmp(pe, "f32") == 0) c->split_proj = false;
     }
-    if (c->split_proj) {
-        const size_t plane = static_cast<size_t>(c->mp) * c->dp;
-        if ((s = dalloc(c, reinterpret_cast<void**>(&c->A3), 3 * plane * sizeof(uint16_t))) != ESS_OK)
-            return bail(s);
-        const unsigned grid = static_cast<unsigned>(std::min<size_t>((plane / 2 + 255) / 256, 4096));
-        hipLaunchKernelGGL(split_rows_kernel, dim3(grid), dim3(256), 0, c->st,
-                           static_cast<const float*>(c->A), plane, c->A3, c->A3 + plane,
-                           c->A3 + 2 * plane);
-        if ((e = hipGetLastError()) != hipSuccess) {
-            fail(ESS_ERR_HIP, "splitting A: %s", hipGetErrorString(e));
-            return bail(ESS_ERR_HIP);
-        }
-    }
+    if (c->split_proj && (s = split_A(c)) != ESS_OK) return bail(s);
     if ((s = check_rows(c, "ess_init", 0)) != ESS_OK || (s = prime_direction(c)) != ESS_OK)
         return bail(s);
     *out = c;
@@ -2131,10 +2300,26 @@ ess_status ess_autotune(ess_ctx* c, int32_t steps_per_trial, char* report, int32
     g_err.clear();
     ESS_TRY(check_ctx(c));
     if (steps_per_trial < 1) return fail(ESS_ERR_INVALID_ARG, "steps_per_trial must be >= 1");
-    if (!c->batch)
-        return fail(ESS_ERR_UNSUPPORTED,
-                    "ess_autotune is switched off for single-problem contexts: its trial loop "
-                    "ended the process with a host segmentation fault whose cause is not yet known");
+    if (!c->batch) {
+        std::ostringstream rep;
+        if (c->G == 1 && c->C <= kGemvChains) {
+            rep << "chosen: nothing to tune (the projections of at most " << kGemvChains
+                << " chains take the row-parallel kernel)\n";
+        } else {
+            SingleChoice best;
+            ESS_TRY(autotune_single(c, steps_per_trial, rep, best));
+            store_tuned_single(c, best);
+            rep << "chosen: " << (best.split ? "split" : "f32") << " " << best.bm << "x" << best.bn
+                << ", band " << best.group_m << " (" << best.us << " us/step)\n";
+        }
+        if (report && report_len > 0) {
+            const std::string r = rep.str();
+            const size_t n = std::min(r.size(), static_cast<size_t>(report_len - 1));
+            std::memcpy(report, r.data(), n);
+            report[n] = 0;
+        }
+        return ESS_OK;
+    }
     ess_ctx::Batch& B = *c->batch;
     // the saved state and the two timing events, released on every return
     struct Scratch {
