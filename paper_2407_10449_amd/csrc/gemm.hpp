@@ -260,17 +260,24 @@ __global__ __launch_bounds__(64 * NW_M * NW_N) void proj_gemm_f32(const float* _
 //
 // A is split once at init (three [mp][dp] arrays of bfloat16); the x' and
 // nu rows stay float32 in memory and are split while they are staged into
-// LDS.  Tile 128 x 128, K slabs of 32 (one MFMA deep), double-buffered LDS
-// with rows of 40 bfloat16 (80 bytes: the 16 rows of a fragment read fall on
-// distinct banks).
+// LDS.  Tile 128 x 128, K slabs of 32 (one MFMA deep), double-buffered LDS.
+// A row of a slab is 32 bfloat16 = four 16-byte chunks, stored unpadded with
+// chunk q of row r at position q ^ ((r >> 2) & 3): the 16 rows of a fragment
+// read (one chunk each) and the 16 chunks of four rows a store covers both
+// fall on 16 distinct 16-byte bank groups.
 // ---------------------------------------------------------------------------
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 struct SplitLds {
-    static constexpr int BM = 128, BN = 128, BK = 32, LK = 40;
+    static constexpr int BM = 128, BN = 128, BK = 32, LK = 32;
     uint16_t a[2][3][BM * LK];
     uint16_t b[2][3][BN * LK];
 };
+
+// element offset of chunk q (8 bfloat16) of row r in a swizzled slab
+__device__ __forceinline__ int split_chunk(int r, int q) {
+    return r * SplitLds::LK + ((q ^ ((r >> 2) & 3)) << 3);
+}
 
 // bfloat16 rounding (to nearest, ties to even) of a float's bits, as the
 // high half of a float32 pattern
@@ -340,7 +347,7 @@ __device__ __forceinline__ void gemm_tile_split(const uint16_t* __restrict__ A0,
     const int r1 = (tid + NT) >> 2, q1 = ((tid + NT) & 3) * 8;
     const size_t ao0 = static_cast<size_t>(m0 + r0) * K + q0, ao1 = static_cast<size_t>(m0 + r1) * K + q1;
     const size_t bo0 = static_cast<size_t>(r0) * K + q0, bo1 = static_cast<size_t>(r1) * K + q1;
-    const int lo0 = r0 * LK + q0, lo1 = r1 * LK + q1;
+    const int lo0 = split_chunk(r0, q0 >> 3), lo1 = split_chunk(r1, q1 >> 3);
     // one slab's staged operands; two sets, so a slab's loads are issued two
     // slabs before they are stored to LDS (the A pieces and x' / nu rows come
     // from L2 or the MALL, whose latency exceeds one slab of matrix work)
@@ -403,18 +410,19 @@ __device__ __forceinline__ void gemm_tile_split(const uint16_t* __restrict__ A0,
     auto compute = [&](int buf) {
         // lane l supplies k = 8 (l / 16) .. + 7 of row l % 16 for A and of
         // column l % 16 for B; the output is rows 4 (l / 16) .. + 3 of column l % 16
-        const int kofs = 8 * (lane >> 4);
+        // (fragment rows start at multiples of 16, so the swizzle of row
+        // l % 16 is that of the fragment's row)
+        const int fa = split_chunk(wm * WM + (lane & 15), lane >> 4);
+        const int fb = split_chunk(wn * WN + (lane & 15), lane >> 4);
         bf16x8 af[3][TM], bfr[3][TN];
 #pragma unroll
         for (int p = 0; p < 3; ++p) {
 #pragma unroll
             for (int i = 0; i < TM; ++i)
-                af[p][i] = *reinterpret_cast<const bf16x8*>(
-                    &L.a[buf][p][(wm * WM + i * 16 + (lane & 15)) * LK + kofs]);
+                af[p][i] = *reinterpret_cast<const bf16x8*>(&L.a[buf][p][fa + i * 16 * LK]);
 #pragma unroll
             for (int j = 0; j < TN; ++j)
-                bfr[p][j] = *reinterpret_cast<const bf16x8*>(
-                    &L.b[buf][p][(wn * WN + j * 16 + (lane & 15)) * LK + kofs]);
+                bfr[p][j] = *reinterpret_cast<const bf16x8*>(&L.b[buf][p][fb + j * 16 * LK]);
         }
         // smallest products first
 #pragma unroll
