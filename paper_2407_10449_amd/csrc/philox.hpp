@@ -18,6 +18,7 @@
 namespace ess {
 
 constexpr double kTwoPi = 6.283185307179586;
+constexpr double kPi = 3.141592653589793;
 
 struct u32x4 {
     uint32_t x, y, z, w;

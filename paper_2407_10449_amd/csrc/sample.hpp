@@ -47,7 +47,7 @@
 // after large_roots_kernel has solved the roots over the whole device (which
 // the kernels for few chains also use above 2048 rows).
 // The quadratic comparators sit beside them: likelihood testing at midpoints
-// (Section 3.1, sample_midpoint_kernel) and Algorithm 2's sequential
+// (Section 2.2, sample_midpoint_kernel) and Algorithm 2's sequential
 // intersection (sample_alg2_kernel).
 #pragma once
 #include <hip/hip_runtime.h>
@@ -103,15 +103,20 @@ constexpr int SMAX = 128;   // survivors the bucket path resolves in place
 // T is the storage type of p and q.  With float storage, a float32 test of
 // z = b / r >= 1.01 (as b^2 >= 1.0201 r^2, relative error a few 1e-7) first
 // discards rows that certainly miss the ellipse, which saves the float64 work
-// for about a third of the rows at the benchmarked shape.  For every other row z is float64,
-// and while |z| <= 0.99 the two angles come from float32 atan2 / acos
-// of the exact floats p, q and of z rounded once: atan2 is off by a few float
-// ulps (< 1e-6 rad) and that rounding moves acos by at most
-// 6e-8 / sqrt(1 - 0.99^2) (< 5e-7 rad), inside the 1e-6 rad trim of the
-// interval ends.  (A float32 z, rounded several times, moved acos by up to
-// 1.5e-6 rad there and let a few proposals cross a constraint.)  Near
-// tangency, where acos amplifies rounding without bound, both angles are
-// float64, as all of them are with double storage.  The wrap, alpha, beta and
+// for about a third of the rows at the benchmarked shape.  For every other
+// row z is float64, and the two angles come from float32 functions of
+// well-conditioned float64 quantities:
+// * tau = atan2 of the exact floats q, p, off by a few float ulps (< 1e-6 rad);
+// * phi = acos z through the half-angle form 2 asin sqrt((1 - |z|) / 2),
+//   mirrored to pi - that for z < 0.  1 - |z| is formed in float64, where it
+//   is exact to the rounding of z, so the one float32 rounding of its half
+//   moves phi by a relative 2^-24, and sqrt and asin (argument at most
+//   sqrt(1/2), where asin's slope is at most sqrt(2)) add a few ulps: phi is
+//   within a few 1e-7 rad everywhere, near tangency (z -> 1, a tiny arc)
+//   included, inside the 1e-6 rad trim of the interval ends.  (acos of z
+//   rounded to float32 amplifies that rounding by 1 / sqrt(1 - z^2) without
+//   bound near tangency.)
+// With double storage both angles are float64.  The wrap, alpha, beta and
 // every later comparison are float64.
 template <typename T>
 __device__ __forceinline__ bool solve_roots(double p, double q, double bi, double& al,
@@ -140,9 +145,11 @@ __device__ __forceinline__ bool solve_roots(double p, double q, double bi, doubl
     if (!(z < 1.0)) return false;
     z = fmax(z, -1.0);
     double tau, phi;
-    if (sizeof(T) == 4 && fabs(z) <= 0.99) {
+    if (sizeof(T) == 4) {
         tau = static_cast<double>(atan2f(static_cast<float>(q), static_cast<float>(p)));
-        phi = static_cast<double>(acosf(static_cast<float>(z)));
+        const float w = static_cast<float>(0.5 * (1.0 - fabs(z)));
+        const double h = 2.0 * static_cast<double>(asinf(sqrtf(w)));
+        phi = z >= 0.0 ? h : kPi - h;
     } else {
         tau = atan2(q, p);
         phi = acos(z);
@@ -1406,7 +1413,7 @@ __global__ __launch_bounds__(BS, (BS == 512 && RPT <= 4 && !REFINE) ? 8 : 1) voi
 }
 
 // ---------------------------------------------------------------------------
-// Comparator: likelihood testing at midpoints (Section 3.1), O(m^2) per chain.
+// Comparator: likelihood testing at midpoints (Section 2.2), O(m^2) per chain.
 // The 2n intersection angles of the n crossing rows are sorted (48-bit keys
 // carrying 2 row + end); each gap between consecutive angles, with 0 and
 // 2 pi as the outer ends, is active when x(theta) at its midpoint satisfies
