@@ -57,7 +57,7 @@ typedef enum {
 #define ESS_LIKELIHOOD_MIDPOINT 16u  /* comparator, not Algorithm 3: find the
                                  active intervals by likelihood testing at the
                                  midpoints between sorted intersection angles
-                                 (Section 3.1), O(m^2) per chain; m <= 4096,
+                                 (Section 2.2), O(m^2) per chain; m <= 4096,
                                  single-problem contexts only */
 #define ESS_BRUTE_FORCE 32u   /* comparator, not Algorithm 3: intersect the rows'
                                  sets one at a time (Algorithm 2), O(m^2) per chain
@@ -109,7 +109,9 @@ ess_status ess_init_batched(const ess_problem* problems, int32_t n_problems, voi
  * T, receives the state after the step. */
 ess_status ess_step(ess_ctx* ctx, void* x_out);
 
-/* n_steps transitions.  The first call with a given (n_steps, thin, trace)
+/* n_steps transitions of Algorithm 1 (Section 2: ellipse through x_t and
+ * nu_t, active intervals by Algorithm 3, theta uniform over them, Section
+ * 3.3's trim and reject-and-stay safeguard).  The first call with a given (n_steps, thin, trace)
  * captures the launches into a HIP graph; later calls with the same shape
  * replay it (unless ESS_EAGER or profiling is on).  A trace buffer that is
  * freed and reallocated at the same address is fine; the graph only stores
@@ -121,10 +123,12 @@ ess_status ess_step(ess_ctx* ctx, void* x_out);
 ess_status ess_run(ess_ctx* ctx, int64_t n_steps, int64_t thin, void* trace,
                    int64_t* n_rejected);
 
-/* Current state (n_chains x d, T) and step counter (host). Either may be NULL. */
+/* Current state x_t of Algorithm 1 (n_chains x d, T) and step counter t
+ * (host). Either may be NULL. */
 ess_status ess_get_state(ess_ctx* ctx, void* x_out, uint64_t* step_out);
 
-/* Replaces the state (n_chains x d, T; strictly feasible) and the step counter.
+/* Replaces the state x_t of Algorithm 1 (n_chains x d, T; strictly feasible,
+ * as Section 3.2's edge cases require of a start) and the step counter.
  * Running n steps after ess_set_state(x, s) reproduces the run that reached
  * (x, s), bit for bit. */
 ess_status ess_set_state(ess_ctx* ctx, const void* x_in, uint64_t step);
@@ -140,7 +144,9 @@ ess_status ess_set_state_gated(ess_ctx* ctx, const void* x_candidate, const void
 /* Per-chain rejection counters since ess_init (host, n_chains int64). */
 ess_status ess_rejections(ess_ctx* ctx, int64_t* per_chain);
 
-/* One transition from explicit inputs, for testing against a reference.
+/* One transition of Algorithm 1 from explicit inputs (Section 2's ellipse,
+ * Algorithm 3's active intervals, Section 3.3's trim and safeguard), for
+ * testing against a reference.
  *  x (n_chains x d, T) becomes the state first (it must be feasible), nu
  *  (n_chains x d, T) is the ellipse direction and u (n_chains, double, in
  *  (0, 1)) picks theta.  Afterwards the context holds the new state and its

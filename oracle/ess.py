@@ -14,7 +14,7 @@ Implementation for Linearly Truncated Multivariate Normal Distributions"
   alternative forms, for the ablation of the root formula;
 * the active intervals by brute force (Algorithm 2), by sort + cumulative
   max (Algorithm 3 / Proposition 1), with the no-root padding of Section 3.2,
-  and by likelihood testing at midpoints (Section 3.1, the quadratic method
+  and by likelihood testing at midpoints (Section 2.2, the quadratic method
   the paper compares against);
 * the two safeguards of Section 3.3: trimming by epsilon and reject-and-stay;
 * Appendix A's change of variables for N(mu, Sigma), Sigma = L L^T.
@@ -185,17 +185,17 @@ def nonempty(lo, hi, min_len=0.0):
 
 
 # --------------------------------------------------------------------------
-# Section 3.1: likelihood testing at midpoints (the quadratic comparator)
+# Section 2.2: likelihood testing at midpoints (the quadratic comparator)
 # --------------------------------------------------------------------------
 def likelihood(p, q, b, theta):
-    """Section 3.1's likelihood: 1 when x(theta) satisfies every constraint,
+    """Section 2.2's likelihood: 1 when x(theta) satisfies every constraint,
     evaluated from the cached projections p = A x_t and q = A nu_t."""
     return bool(np.all(p * math.cos(theta) + q * math.sin(theta) <= b))
 
 
 def midpoint_intervals(p, q, b):
     """Active intervals of one chain by likelihood testing at midpoints
-    (Section 3.1, the variant that tests the point halfway between two
+    (Section 2.2, the variant that tests the point halfway between two
     consecutive intersection angles instead of a fixed offset).
 
     The intersection angles of the crossing rows are sorted, with 0 and 2 pi
@@ -263,7 +263,7 @@ def transition(A, b, x, nu, u, eps=0.0, pq=None, store=np.float64, method="alg3"
     (C, m)) is given, those projections are used instead of A x and A nu.
     The proposal is rounded to `store` before the feasibility check, as the
     code under test stores it.  method="midpoint" builds the active intervals
-    by Section 3.1's likelihood testing and method="alg2" by Algorithm 2's
+    by Section 2.2's likelihood testing and method="alg2" by Algorithm 2's
     sequential intersection instead of Algorithm 3.
     Returns a dict with x_new, rejected, theta, intervals (list per chain of
     the non-empty trimmed pieces), alpha, beta, p, q, x_prop.

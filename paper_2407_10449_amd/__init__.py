@@ -348,7 +348,7 @@ class Sampler:
 
     b of shape (n_chains, m) gives every chain its own right-hand side.
     full_sort=True builds every chain's intervals with the full sort (the same
-    intervals); method="midpoint" uses Section 3.1's likelihood testing at
+    intervals); method="midpoint" uses Section 2.2's likelihood testing at
     midpoints and method="alg2" Algorithm 2's sequential intersection instead
     of Algorithm 3 (the quadratic comparators, m <= 4096);
     eager=True launches kernel by kernel instead of replaying a HIP graph."""
@@ -374,7 +374,7 @@ class Sampler:
             flags |= ESS_PER_CHAIN_B
         if eager:
             flags |= ESS_EAGER
-        if method == "midpoint":    # Section 3.1's likelihood testing (comparator)
+        if method == "midpoint":    # Section 2.2's likelihood testing (comparator)
             flags |= ESS_LIKELIHOOD_MIDPOINT
         elif method == "alg2":      # Algorithm 2's sequential intersection (comparator)
             flags |= ESS_BRUTE_FORCE

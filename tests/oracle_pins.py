@@ -8,7 +8,7 @@ Sources of truth:
 * the worked examples drawn in Figures 1 and 2 (golden files, cited there);
 * Algorithm 2 (the definition of I_act) and a dense theta grid that tests
   feasibility of x(theta) directly (they pin Algorithm 3 and the midpoint
-  likelihood testing of Section 3.1 alike);
+  likelihood testing of Section 2.2 alike);
 * closed forms: Appendix D's worst case, the sorting reduction of Section 3.1,
   the residual of the trigonometric equation, rotation covariance;
 * textbook distributions: uniformity of theta (Kolmogorov-Smirnov), moments
@@ -334,7 +334,7 @@ def pin_alg3_equals_alg2(seed=13, n_sets=3000):
 
 
 def pin_midpoint_equals_alg2(seed=21, n_cases=400):
-    """Section 3.1's likelihood testing at midpoints finds the set that
+    """Section 2.2's likelihood testing at midpoints finds the set that
     Algorithm 2 defines, on random polytopes through random ellipses."""
     rng = np.random.default_rng(seed)
     for case in range(n_cases):
