@@ -360,8 +360,9 @@ def main():
                                    "f32 operands split exactly into three bf16 pieces, six "
                                    "bf16 MFMA products (dropped terms < 2^-24 |a x|), f32 "
                                    "accumulate; error vs f64 below the f32 MFMA kernel's"),
-                   "roots": "f32 pretest drops b/r >= 1.01; b/r = b rsqrt(p^2 + q^2) in f64; "
-                            "f32 atan2, acos where |b/r| <= 0.99, f64 near tangency",
+                   "roots": "f32 pretest drops b/r >= 1.01; z = b/r = b rsqrt(p^2 + q^2) in f64; "
+                            "tau = f32 atan2(q, p); phi = acos z = 2 asin sqrt((1 - |z|)/2) "
+                            "(mirrored for z < 0) in f32 from f64 1 - |z|",
                    "interval_ends_and_sampling": "f64", "trim_eps": 1e-6, "seed": 0},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS,
                      "unit": "TFLOP/s",
