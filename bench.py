@@ -226,7 +226,7 @@ def bench_paper_timing(E, torch, dims=(100, 250, 500, 1000, 2000, 4000)):
         row = {"d": d, "m": d}
         pr = synth.paper_highdim(d=d)
         # Algorithm 3, and up to 4096 rows the quadratic comparators (Section
-        # 3.1's likelihood testing at midpoints, Algorithm 2's sequential
+        # 2.2's likelihood testing at midpoints, Algorithm 2's sequential
         # intersection) on the same instance
         methods = ((("alg3", ""), ("midpoint", "_midpoint"), ("alg2", "_alg2")) if d <= 4096
                    else (("alg3", ""),))
