@@ -282,7 +282,11 @@ void launch_gemv(const ess_ctx* c, hipStream_t st, const T* B0, const T* B1, int
 // chains with the four waves splitting K, 5 to 12 as four waves of 3 chains
 // over the whole of K (measured 10 % faster than two waves of 6 chains with
 // K split in two: 7.7 against 8.5 ms for 10 chains x 100 steps at d = 4000).
+// The four waves of 3 chains each stream the workgroup's rows of A, which
+// the caches absorb while A fits in them; above kGemvCachedBytes (the
+// last-level cache is 256 MB) two waves of 6 chains read A half as often.
 constexpr int kGemvChains = 12;
+constexpr size_t kGemvCachedBytes = static_cast<size_t>(128) << 20;
 
 ess_status launch_proj(const ess_ctx* c, const Group& g, hipStream_t st, const void* Y, int cols,
                        int p_direct, int strict) {
@@ -292,14 +296,18 @@ ess_status launch_proj(const ess_ctx* c, const Group& g, hipStream_t st, const v
         if (c->prec == 32) {
             const float* B0 = static_cast<const float*>(Y) + off;
             const float* B1 = static_cast<const float*>(c->N) + off;
+            const bool big = static_cast<size_t>(c->mp) * c->dp * c->esz > kGemvCachedBytes;
             if (g.n <= 2) launch_gemv<float, 2, 1>(c, st, B0, B1, cols, o);
             else if (g.n <= 4) launch_gemv<float, 4, 1>(c, st, B0, B1, cols, o);
+            else if (big) launch_gemv<float, kGemvChains / 2, 2>(c, st, B0, B1, cols, o);
             else launch_gemv<float, kGemvChains / 4, 4>(c, st, B0, B1, cols, o);
         } else {
             const double* B0 = static_cast<const double*>(Y) + off;
             const double* B1 = static_cast<const double*>(c->N) + off;
+            const bool big = static_cast<size_t>(c->mp) * c->dp * c->esz > kGemvCachedBytes;
             if (g.n <= 2) launch_gemv<double, 2, 1>(c, st, B0, B1, cols, o);
             else if (g.n <= 4) launch_gemv<double, 4, 1>(c, st, B0, B1, cols, o);
+            else if (big) launch_gemv<double, kGemvChains / 2, 2>(c, st, B0, B1, cols, o);
             else launch_gemv<double, kGemvChains / 4, 4>(c, st, B0, B1, cols, o);
         }
         HIP_TRY(hipGetLastError());
@@ -386,11 +394,21 @@ void launch_sample_t(const ess_ctx* c, const Group& g, hipStream_t st, const Sam
         return;
     }
     if (c->m > 4096) {
-        // the roots over the whole device first, then rows in chunks of 4096
-        // per pass; the full sort keeps keys only
-        const dim3 fg(a.force_full ? std::min(g.n, 768) : std::min(g.n, 32));
+        // the roots over the whole device first
         const long long blocks = static_cast<long long>((c->m + 255) / 256) * g.n;
         hipLaunchKernelGGL((large_roots_kernel<T>), dim3(static_cast<unsigned>(blocks)), b, 0, st, a);
+        if (g.n <= 256 && c->m <= 16384) {
+            // few chains: every row's alpha and beta in registers, 16 or 32
+            // per thread, for all passes (the chunked passes reload a.ab and
+            // wait on it once per chunk), the full sort in place from a.ab
+            if (c->m <= 8192)
+                hipLaunchKernelGGL((sample_bucket_kernel<T, 16, 2048, 512, true, true>), grid, b2, 0, st, a);
+            else
+                hipLaunchKernelGGL((sample_bucket_kernel<T, 32, 2048, 512, true, true>), grid, b2, 0, st, a);
+            return;
+        }
+        // then rows in chunks of 4096 per pass; the full sort keeps keys only
+        const dim3 fg(a.force_full ? std::min(g.n, 768) : std::min(g.n, 32));
         hipLaunchKernelGGL((sample_large_kernel<T>), grid, b2, 0, st, a);
         if (c->m > kMaxRowsLds)
             hipLaunchKernelGGL((fallback_large_kernel<T, true>), fg, b, 0, st, a);

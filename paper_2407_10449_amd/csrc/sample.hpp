@@ -1368,14 +1368,27 @@ __global__ __launch_bounds__(BS, (BS == 512 && RPT <= 4 && !REFINE) ? 8 : 1) voi
         // the variants for few chains refine crowded buckets and keep alpha
         // and beta of a chain they sort in LDS (occupancy does not matter
         // with no more chains than compute units)
-        __shared__ BucketLds<NB> lds;
         // PRE: large_roots_kernel has solved this step's roots into a.ab
         const double2* ab = PRE ? static_cast<const double2*>(a.ab) + static_cast<size_t>(c) * a.mp : nullptr;
         double theta = 0.0;
-        const bool done = !a.force_full && bucket_chain<T, RPT, NB, BS, true>(r, sel, lds, theta, ab);
-        if (!done) {
-            ESS_FULL_LDS(RPT * BS)
-            theta = full_chain<T, KEYS_SLOT, BS>(r, sel, full_lds);
+        if constexpr (PRE && RPT * BS > 4096) {
+            // up to 16384 rows held in registers across every pass; a chain
+            // the buckets cannot resolve sorts keys only, in the bucket
+            // arrays' LDS, with alpha and beta read back from a.ab
+            __shared__ BucketOrKeys<NB, RPT * BS> lds;
+            const bool done = !a.force_full && bucket_chain<T, RPT, NB, BS, true>(r, sel, lds.bucket, theta, ab);
+            if (!done) {
+                __syncthreads();
+                const FullLds L{nullptr, nullptr, lds.key, lds.red, lds.cnt, lds.bcast, &lds.kstar, lds.theta};
+                theta = full_chain<T, KEYS_ROW_AB, BS>(r, sel, L, ab);
+            }
+        } else {
+            __shared__ BucketLds<NB> lds;
+            const bool done = !a.force_full && bucket_chain<T, RPT, NB, BS, true>(r, sel, lds, theta, ab);
+            if (!done) {
+                ESS_FULL_LDS(RPT * BS)
+                theta = full_chain<T, KEYS_SLOT, BS>(r, sel, full_lds);
+            }
         }
         move_chain<T>(r, theta);
     } else {

@@ -514,11 +514,14 @@ def test_large_m_overflow_takes_keys_only_full_sort(E, precision):
     assert not fails, fails[:5]
 
 
-def test_section_4_2_at_d_8000(E):
+@pytest.mark.parametrize("C", [2, 10])
+def test_section_4_2_at_d_8000(E, C):
     """Section 4.2's instance beyond 4096 rows (d = m = 8000) from x0: crowded
-    buckets on the chunked path, against the oracle and the full sort."""
+    buckets on the chunked path (refinement on the gathered rows), against
+    the oracle and the full sort.  Ten chains take the row-parallel
+    projection's two waves of six chains (A, 256 MB, exceeds what the caches
+    hold)."""
     pr = synth.paper_highdim(d=8000)
-    C = 2
     rng = np.random.default_rng(43)
     x = np.tile(pr.x0, (C, 1)).astype(np.float32)
     nu = rng.standard_normal(x.shape).astype(np.float32)
