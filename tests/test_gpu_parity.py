@@ -674,6 +674,22 @@ def test_full_sort_path_matches_bucket_path(E, name, d, m, C, precision, eps):
     assert np.abs(a["x_new"] - f["x_new"]).max() <= 1e-6
 
 
+def test_graph_cache_eviction_keeps_results(E):
+    """Eleven runs, each into a new live trace buffer and without counting
+    rejections (no synchronisation inside ess_run), so the library captures a
+    graph per run and evicts the oldest beyond eight while earlier replays may
+    still be queued: every trace equals an eager run's, bit for bit."""
+    pr = synth.box_halfspace(n_chains=300)
+    g = E.Sampler(pr.A, pr.b, pr.x0, pr.n_chains, seed=6, precision=32)
+    parts = [g.run(2 + (k % 3), count_rejections=False)[0] for k in range(11)]
+    torch.cuda.synchronize()
+    e = E.Sampler(pr.A, pr.b, pr.x0, pr.n_chains, seed=6, precision=32, eager=True)
+    want, _ = e.run(sum(p.shape[0] for p in parts))
+    assert torch.equal(torch.cat(parts), want)
+    g.close()
+    e.close()
+
+
 def test_graph_replay_equals_eager_launches(E):
     """Captured-graph runs (default) and kernel-by-kernel runs agree bit for bit,
     across repeated replays of one captured shape and a state reset."""
