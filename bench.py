@@ -95,6 +95,27 @@ def cpu_baseline(pr, seconds, n_chains=64, store=None, eps=1e-6):
                       f"({dt:.1f} s, float64 numpy oracle)"}
 
 
+def bench_trim_sweep(E, torch):
+    """The paper leaves the trim width open (Section 3.3): safeguard
+    rejections in float32 against eps on the Section 4.1 truncation N(0, 1)
+    on [15, 16] (2000 chains x 1000 steps, the paper's 2e6 transitions, 8
+    rejections reported at its own eps) and on gp_rbf (1024 chains x 200
+    steps)."""
+    import synth
+    out = {}
+    for name, pr, steps in (("univariate_15_16", synth.univariate(15.0, 16.0, n_chains=2000), 1000),
+                            ("gp_rbf", synth.gp_rbf(), 200)):
+        rows = []
+        for eps in (0.0, 1e-7, 1e-6, 1e-5):
+            s = E.Sampler(pr.A, pr.b, pr.x0, pr.n_chains, seed=0, precision=32, trim_eps=eps)
+            _, nrej = s.run(steps, keep_trace=False)
+            s.close()
+            rows.append({"eps": eps, "rejections": int(nrej),
+                         "rate": nrej / (pr.n_chains * steps)})
+        out[name] = {"transitions": pr.n_chains * steps, "rows": rows}
+    return out
+
+
 def bench_config(E, torch, pr, precision, steps, cpu_seconds, cpu_chains):
     """One of the smaller workloads at its own chain count and step count:
     chain-steps/s of a graph replay, the per-kernel durations of the same steps
@@ -269,6 +290,8 @@ def main():
                     help="run only the warm-start comparison and print its JSON")
     ap.add_argument("--warm-steps", type=int, default=216000,
                     help="steps per arm of the warm-start comparison")
+    ap.add_argument("--trim-sweep-only", action="store_true",
+                    help="only the trim-width sweep (rejections against eps)")
     ap.add_argument("--paper-timing-only", action="store_true",
                     help="run only Section 4.2's timing protocol and print its JSON")
     ap.add_argument("--paper-dims", default="100,250,500,1000,2000,4000,8000,16000",
@@ -302,6 +325,9 @@ def main():
         del src, dst
     if args.batched_only:
         print(json.dumps({"batched": bench_batched(E, torch, steps=args.steps)}), flush=True)
+        return
+    if args.trim_sweep_only:
+        print(json.dumps({"trim_sweep": bench_trim_sweep(E, torch)}), flush=True)
         return
     if args.paper_timing_only:
         print(json.dumps({"paper_timing": bench_paper_timing(E, torch, paper_dims)}), flush=True)
@@ -396,6 +422,8 @@ def main():
         out["batched"] = bench_batched(E, torch)
         out["warm_start"] = bench_warm_start(E, torch, log, args.warm_steps)
         out["paper_timing"] = bench_paper_timing(E, torch, paper_dims)
+        out["trim_sweep"] = bench_trim_sweep(E, torch)
+        log(f"trim sweep: {out['trim_sweep']}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pr, args.cpu_seconds)
     print(json.dumps(out), flush=True)
