@@ -300,7 +300,7 @@ __global__ __launch_bounds__(256) void batched_step_kernel(BatchArgs a) {
 // Chains of the larger classes come first in a.chains, so the longest items
 // start early.
 template <int RPT_MAX>
-__global__ __launch_bounds__(256, RPT_MAX <= 4 ? 6 : 1) void batched_chain_kernel(BatchArgs a) {
+__global__ __launch_bounds__(256, RPT_MAX <= 8 ? 6 : 1) void batched_chain_kernel(BatchArgs a) {
     __shared__ __attribute__((aligned(16))) BatchLds<batch_keys<RPT_MAX>(), false> lds;
     const int2 ch = a.chains[blockIdx.x];
     const ProbDesc& pd = a.descs[ch.x];
