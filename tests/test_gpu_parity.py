@@ -296,8 +296,9 @@ def run_step_by_step(E, s, A, b, seed, T, idx, eps, store=np.float32):
         rej = s.rejections()
         nu = ref_philox.normals(seed, step, idx, d).astype(store).astype(np.float64)
         u = ref_philox.uniforms(seed, step, idx)
-        ref = ref_ess.transition(A_s, b, x_prev[idx], nu, u, eps=eps, store=store)
-        fails, exc = compare_states(A_s, b, x_next[idx], (rej - rej_prev)[idx], ref)
+        bs = b[idx] if np.ndim(b) == 2 else b   # one b per chain, or shared
+        ref = ref_ess.transition(A_s, bs, x_prev[idx], nu, u, eps=eps, store=store)
+        fails, exc = compare_states(A_s, bs, x_next[idx], (rej - rej_prev)[idx], ref)
         assert not fails, (t, fails[:10])
         excused += exc
         moved += int((x_next[idx] != x_prev[idx]).any(axis=1).sum())
@@ -316,6 +317,22 @@ def test_run_matches_oracle_fp32_per_step(E, workload, C):
     s = E.Sampler(pr.A, pr.b, pr.x0, C, seed=0, precision=32, trim_eps=1e-6)
     idx = np.linspace(0, C - 1, 96).astype(int)
     excused = run_step_by_step(E, s, pr.A, pr.b, 0, 4, idx, 1e-6)
+    assert excused <= 2
+    s.close()
+
+
+def test_run_matches_oracle_per_step_warm_family(E):
+    """The warm-start family's shape (d=256, m=768, 32 right-hand sides x 64
+    chains = 2048 chains with one b per chain), the context the batched +
+    warm-start comparison runs, checked one step at a time against the
+    oracle."""
+    A, b0, draw = synth.warm_family()
+    B = np.repeat(draw(np.random.default_rng(3), 32), 64, axis=0)
+    C, d = B.shape[0], A.shape[1]
+    s = E.Sampler(A, B, np.zeros(d), C, seed=7, precision=32, trim_eps=1e-6)
+    s.run(3, keep_trace=False)                  # generic states first
+    idx = np.linspace(0, C - 1, 96).astype(int)
+    excused = run_step_by_step(E, s, A, B, 7, 3, idx, 1e-6)
     assert excused <= 2
     s.close()
 
