@@ -226,6 +226,62 @@ __device__ __forceinline__ double block_excl_scan(double v, double id, Op op, do
     return (lane == 0) ? pre : op(pre, ex);
 }
 
+// A 64-bit value moved across lanes by one DPP control, both halves with the
+// same control: lanes whose source lies outside the row, or which the row
+// mask leaves out, receive 0 (the bits of +0.0).
+template <int CTRL, int ROW_MASK, bool BOUND>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
+    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), CTRL, ROW_MASK, 0xf, BOUND);
+    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, ROW_MASK, 0xf,
+                                               BOUND);
+    return __longlong_as_double(static_cast<long long>(
+        (static_cast<unsigned long long>(static_cast<unsigned>(hi)) << 32) |
+        static_cast<unsigned>(lo)));
+}
+
+// v of lane k (k the same in every lane), in every lane of the wave
+__device__ __forceinline__ double lane_value(double v, int k) {
+    const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
+    const unsigned lo = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(b), k));
+    const unsigned hi = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(b >> 32), k));
+    return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+
+// Inclusive max over lanes 0 .. lane of a wave, for values >= 0 (0 is the
+// identity, which is what lanes without a source receive).  Within each row
+// of 16 lanes a Hillis-Steele scan with shifts 1, 2, 4, 8 (DPP row_shr); then
+// lane 15 of a row is broadcast into the next row (rows 1 and 3) and lane 31
+// into rows 2 and 3 (DPP row_bcast), as in AMD's published GCN cross-lane
+// scan.  Register-to-register moves only: no LDS round trip per step.
+__device__ __forceinline__ double wave_incl_max(double x) {
+    x = fmax(x, dpp_f64<0x111, 0xf, true>(x));   // row_shr:1
+    x = fmax(x, dpp_f64<0x112, 0xf, true>(x));   // row_shr:2
+    x = fmax(x, dpp_f64<0x114, 0xf, true>(x));   // row_shr:4
+    x = fmax(x, dpp_f64<0x118, 0xf, true>(x));   // row_shr:8
+    x = fmax(x, dpp_f64<0x142, 0xa, false>(x));  // row_bcast:15 into rows 1, 3
+    x = fmax(x, dpp_f64<0x143, 0xc, false>(x));  // row_bcast:31 into rows 2, 3
+    return x;
+}
+
+// Exclusive max-scan of one value >= 0 per thread over a block of NW waves
+// (0 for thread 0).  One barrier: s_w (NW values) must not be written again
+// before the caller's next barrier.
+template <int NW>
+__device__ __forceinline__ double block_excl_max(double v, double* s_w) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const double x = wave_incl_max(v);
+    if (lane == 63) s_w[w] = x;
+    double ex = __shfl_up(x, 1, 64);
+    if (lane == 0) ex = 0.0;
+    __syncthreads();
+    double pre = 0.0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i)
+        if (i < w) pre = fmax(pre, s_w[i]);
+    return fmax(pre, ex);
+}
+
 // Ascending bitonic sort of key[0 .. n2), n2 a power of two >= 512, by BS threads.
 template <int BS = 256>
 __device__ __forceinline__ void bitonic_sort_lds(uint64_t* key, int n2) {
@@ -412,15 +468,39 @@ __device__ __forceinline__ void move_chain(const ChainRef<T>& r, double theta) {
     }
 }
 
+// The next step's normals of element pair (2 tid, 2 tid + 1), drawn before
+// the move: the draw needs no loaded value, so it can run while loads are in
+// flight.  `valid` is false when the thread has no pair or nothing is drawn.
+template <typename T>
+struct NextPair {
+    T z0, z1;
+    bool valid;
+};
+
+template <typename T>
+__device__ __forceinline__ NextPair<T> draw_next_pair(const ChainRef<T>& r) {
+    NextPair<T> n{T(0), T(0), false};
+    if (r.gen_next && 2 * static_cast<int>(threadIdx.x) < r.d) {
+        double z0, z1;
+        Rng(r.seed).normal_pair(threadIdx.x, r.chain, r.step + 1, r.problem, z0, z1);
+        n = NextPair<T>{static_cast<T>(z0), static_cast<T>(z1), true};
+    }
+    return n;
+}
+
 // The bookkeeping half of a commit (Section 3.3): the decision on the pending
 // proposal, the rejection count and the projection buffer the roots read.
 // The rows are copied later, by move_pairs, in the same pass as the move.
 // Returns the committed projection buffer; `from_prop` tells whether the
 // proposal became the state.
+// `next`, when given, receives the early draw of the next direction's pair,
+// made while flag and sel are loaded.
 template <typename T>
-__device__ __forceinline__ int commit_flags(const ChainRef<T>& r, bool& from_prop) {
+__device__ __forceinline__ int commit_flags(const ChainRef<T>& r, bool& from_prop,
+                                            NextPair<T>* next = nullptr) {
     const int fl = *r.flag;
     const int s = *r.sel;
+    if (next) *next = draw_next_pair<T>(r);
     __syncthreads();   // every read of flag / sel precedes the writes below
     const int snew = fl ? s : (s ^ 1);
     if (threadIdx.x == 0) {
@@ -464,7 +544,8 @@ __device__ __forceinline__ PairAhead<T> pair_ahead(const ChainRef<T>& r, bool fr
 // the first taken from `q`.
 template <typename T, int BS>
 __device__ __forceinline__ void move_pairs(const ChainRef<T>& r, double theta, bool from_prop,
-                                           bool copy_state, const PairAhead<T>& q) {
+                                           bool copy_state, const PairAhead<T>& q,
+                                           const NextPair<T>* next = nullptr) {
     if (threadIdx.x == 0 && r.theta_out) *r.theta_out = theta;
     double sd, cd;
     sincos(theta, &sd, &cd);
@@ -500,8 +581,16 @@ __device__ __forceinline__ void move_pairs(const ChainRef<T>& r, double theta, b
     // the next nu over the same pairs: each thread overwrites only the nu
     // elements it has read itself, so no barrier is needed
     if (r.gen_next) {
+        int j = threadIdx.x;
+        if (next) {   // the first pair, drawn ahead
+            if (next->valid) {
+                r.nu[2 * j] = next->z0;
+                if (2 * j + 1 < r.d) r.nu[2 * j + 1] = next->z1;
+            }
+            j += BS;
+        }
         const Rng rng(r.seed);
-        for (int j = threadIdx.x; 2 * j < r.d; j += BS) {
+        for (; 2 * j < r.d; j += BS) {
             double z0, z1;
             rng.normal_pair(j, r.chain, r.step + 1, r.problem, z0, z1);
             r.nu[2 * j] = static_cast<T>(z0);
@@ -896,7 +985,7 @@ __device__ __forceinline__ void bucket_prefix_max(BucketLds<NB>& L, double g0, b
     double tmax = 0.0;
 #pragma unroll
     for (int j = 0; j < BPT; ++j) tmax = fmax(tmax, ofloat(L.G[tid * BPT + j]));
-    const double g_in = block_excl_scan<MaxOp, BS / 64>(tmax, 0.0, MaxOp(), L.red);
+    const double g_in = block_excl_max<BS / 64>(tmax, L.red);
     double run = fmax(g0, g_in);
 #pragma unroll
     for (int j = 0; j < BPT; ++j) {
@@ -967,15 +1056,19 @@ __device__ __forceinline__ void pred_max_pass(BucketLds<NB>& L, const RefineMap&
                                               const double (&al)[RPT], const double (&be)[RPT],
                                               int row0) {
     const int tid = threadIdx.x;
+    // every row's bucket head first: one LDS round trip, not one per row
+    int head[RPT];
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
         const int b = be[j] > 0.0 ? bucket_of<NB>(R, al[j]) : -1;
-        if (b >= 0) {
-            const int i = row0 + tid + BS * j;
-            for (int s = L.head[b]; s >= 0; s = L.nxt[s]) {
-                if (al[j] < L.sa[s] || (al[j] == L.sa[s] && i < L.si[s]))
-                    atomicMax(&L.sm[s], obits(be[j]));
-            }
+        head[j] = b >= 0 ? L.head[b] : -1;
+    }
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int i = row0 + tid + BS * j;
+        for (int s = head[j]; s >= 0; s = L.nxt[s]) {
+            if (al[j] < L.sa[s] || (al[j] == L.sa[s] && i < L.si[s]))
+                atomicMax(&L.sm[s], obits(be[j]));
         }
     }
 }
@@ -1014,36 +1107,40 @@ __device__ __forceinline__ double finish_bucket(const ChainRef<T>& r, BucketLds<
 
     // inverse CDF over the S + 1 candidates in order: the running sums are a
     // sequential left-to-right sum (those of a cumulative sum), and theta lies
-    // in the first non-empty candidate whose running sum exceeds s = u L.  Few
-    // candidates: one thread walks them.  Many: the lengths are formed in
-    // parallel, one thread keeps the running sums, and the search is
-    // parallel.  Both give the same theta bit for bit.
-    if (S < 16) {
-        if (tid == 0) {
-            double total = 0.0;
-            for (int k = 0; k <= S; ++k) total += fmax(L.hi[k] - L.lo[k], 0.0);
-            double theta = 0.0;
+    // in the first non-empty candidate whose running sum exceeds s = u L.  Up
+    // to 64 candidates: lane k of the first wave holds candidate k, the
+    // running sums pass from lane to lane through scalar registers (no LDS
+    // round trip per candidate), and ballots find the candidate.  More: the
+    // lengths are formed in parallel, one thread keeps the running sums in
+    // LDS, and the search is parallel.  Both give the same theta bit for bit.
+    const int Su = __builtin_amdgcn_readfirstlane(S);
+    if (Su < 64) {
+        if (tid < 64) {
+            const bool in = tid <= Su;
+            const double lo = in ? L.lo[tid] : 0.0;
+            const double hi = in ? L.hi[tid] : 0.0;
+            const double len = in ? fmax(hi - lo, 0.0) : 0.0;
+            double run = 0.0, before = 0.0, cum = 0.0;
+            for (int k = 0; k <= Su; ++k) {
+                if (tid == k) before = run;
+                run += lane_value(len, k);
+                if (tid == k) cum = run;
+            }
+            const double total = run;   // the same in every lane
             if (total > 0.0) {
                 const double sv = L.u * total;
-                double run = 0.0;
-                int last = -1;
-                bool found = false;
-                for (int k = 0; k <= S; ++k) {
-                    const double len = fmax(L.hi[k] - L.lo[k], 0.0);
-                    if (len > 0.0) {
-                        last = k;
-                        if (!found && run + len > sv) {
-                            theta = fmax(L.lo[k], fmin(L.lo[k] + (sv - run), L.hi[k]));
-                            found = true;
-                        }
-                    }
-                    run += len;
+                const unsigned long long pos = __ballot(len > 0.0);
+                const unsigned long long hit = __ballot(len > 0.0 && cum > sv);
+                if (hit) {
+                    if (tid == __ffsll(static_cast<long long>(hit)) - 1)
+                        L.theta = fmax(lo, fmin(lo + (sv - before), hi));
+                } else if (tid == 63 - __clzll(static_cast<long long>(pos))) {
+                    L.theta = hi;   // rounding put s at the total
                 }
-                if (!found) theta = L.hi[last];   // rounding put s at the total
-            } else {
+            } else if (tid == 0) {
+                L.theta = 0.0;
                 *r.flag = 1;   // empty active set: stay, counted as a rejection
             }
-            L.theta = theta;
         }
     } else {
         if (tid <= S) L.len[tid] = fmax(L.hi[tid] - L.lo[tid], 0.0);
@@ -1403,7 +1500,21 @@ __global__ __launch_bounds__(BS, (BS == 512 && RPT <= 4 && !REFINE) ? 8 : 1) voi
         bool done = false;
         // the commit's bookkeeping now, its row copies with the move
         bool from_prop = false;
-        const int sel = a.has_pending ? commit_flags<T>(r, from_prop) : *r.sel;
+        // the next direction's first pair, drawn while flag and sel load;
+        // 512-thread chains (registers capped at 64) park it in LDS
+        NextPair<T> next;
+        int sel;
+        if (a.has_pending) {
+            sel = commit_flags<T>(r, from_prop, &next);
+        } else {
+            next = draw_next_pair<T>(r);
+            sel = *r.sel;
+        }
+        __shared__ T next_lds[BS == 512 ? 2 * BS : 1];
+        if constexpr (BS == 512) {
+            next_lds[2 * threadIdx.x] = next.z0;
+            next_lds[2 * threadIdx.x + 1] = next.z1;
+        }
         const PairAhead<T> ahead = pair_ahead<T>(r, from_prop);
         double theta = 0.0;
         if (!a.force_full) {
@@ -1421,7 +1532,11 @@ __global__ __launch_bounds__(BS, (BS == 512 && RPT <= 4 && !REFINE) ? 8 : 1) voi
             const FullLds L{nullptr, nullptr, lds.key, lds.red, lds.cnt, lds.bcast, &lds.kstar, lds.theta};
             theta = full_chain<T, KEYS_ROW_AB, BS>(r, sel, L, abg);
         }
-        move_pairs<T, BS>(r, theta, from_prop, from_prop && a.has_pending, ahead);
+        if constexpr (BS == 512) {   // each thread reads back its own pair
+            next.z0 = next_lds[2 * threadIdx.x];
+            next.z1 = next_lds[2 * threadIdx.x + 1];
+        }
+        move_pairs<T, BS>(r, theta, from_prop, from_prop && a.has_pending, ahead, &next);
     }
 }
 
