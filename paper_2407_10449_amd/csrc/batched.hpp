@@ -202,20 +202,31 @@ struct BatchLds {
     double theta[2];
 };
 
+// A chain after the commit's decision: the committed projection buffer,
+// whether the proposal became the state (its row copies then happen in the
+// move's pass, as in the single-problem kernel), and the next direction's
+// first pair, drawn already.
+struct ChainStart {
+    int sel;
+    bool from_prop;
+    NextPair<float> next;
+};
+
 // The per-chain part of a batched step after the commit: the bucket path, and
 // for a chain whose survivors overflow the full sort in place from its roots,
 // which the bucket path leaves in a.ab (keys in the bucket arrays' LDS).
 template <int RPT, int NB>
 __device__ __forceinline__ void batch_sample(const BatchArgs& a, const ProbDesc& pd, int c,
-                                             const ChainRef<float>& r, int sel,
+                                             const ChainRef<float>& r, const ChainStart& st,
                                              BucketLds<NB>& bucket, const FullLds& L) {
     double2* abg = a.ab + pd.q_off + static_cast<size_t>(c) * pd.mp;
     double theta = 0.0;
-    if (!bucket_chain<float, RPT, NB>(r, sel, bucket, theta, nullptr, abg)) {
+    if (!bucket_chain<float, RPT, NB>(r, st.sel, bucket, theta, nullptr, abg)) {
         __syncthreads();   // every row's alpha and beta is in a.ab
-        theta = full_chain<float, KEYS_ROW_AB, 256>(r, sel, L, abg);
+        theta = full_chain<float, KEYS_ROW_AB, 256>(r, st.sel, L, abg);
     }
-    move_chain<float>(r, theta);
+    move_pairs<float, 256>(r, theta, st.from_prop, st.from_prop && a.has_pending, nullptr,
+                           &st.next);
 }
 
 // The chain's class picks the rows per thread and the bucket count, so a
@@ -230,21 +241,44 @@ __device__ __forceinline__ void batch_sample(const BatchArgs& a, const ProbDesc&
 // candidates), so the chains are those of the single-problem kernels.
 template <int RPT_MAX, typename Lds>
 __device__ __forceinline__ void batch_sample_class(const BatchArgs& a, const ProbDesc& pd, int c,
-                                                   const ChainRef<float>& r, int sel, Lds& lds) {
+                                                   const ChainRef<float>& r, const ChainStart& st,
+                                                   Lds& lds) {
     const FullLds L{nullptr, nullptr, lds.key, lds.red, lds.cnt, lds.bcast, &lds.kstar, lds.theta};
     const int cls = __builtin_amdgcn_readfirstlane(pd.cls);
     constexpr int MID = RPT_MAX > 8 ? 1 : (RPT_MAX < 4 ? RPT_MAX : 4);
     constexpr int TOP = RPT_MAX > 8 ? 1 : 3;   // first class of the largest variant
     if constexpr (RPT_MAX > 4) {
-        if (cls >= TOP) return batch_sample<RPT_MAX, 2048>(a, pd, c, r, sel, lds.b3, L);
+        if (cls >= TOP) return batch_sample<RPT_MAX, 2048>(a, pd, c, r, st, lds.b3, L);
     }
     if constexpr (MID > 1) {
         if (cls >= 1) {
-            if constexpr (MID == 4) return batch_sample<4, 1024>(a, pd, c, r, sel, lds.b2, L);
-            else return batch_sample<2, 512>(a, pd, c, r, sel, lds.b1, L);
+            if constexpr (MID == 4) return batch_sample<4, 1024>(a, pd, c, r, st, lds.b2, L);
+            else return batch_sample<2, 512>(a, pd, c, r, st, lds.b1, L);
         }
     }
-    batch_sample<1, 256>(a, pd, c, r, sel, lds.b0, L);
+    batch_sample<1, 256>(a, pd, c, r, st, lds.b0, L);
+}
+
+// One chain's share of a step: the commit of its pending proposal, then
+// (unless this launch only commits) Algorithm 3's step and the move.  The
+// next direction's first pair is drawn while flag and sel load.
+template <int RPT_MAX, typename Lds>
+__device__ __forceinline__ void batch_chain_item(const BatchArgs& a, const ProbDesc& pd, int p,
+                                                 int c, Lds& lds) {
+    const ChainRef<float> r = batch_ref(a, pd, p, c);
+    if (!a.do_sample) {
+        if (a.has_pending) commit_chain<float>(r);
+        return;
+    }
+    ChainStart st;
+    st.from_prop = false;
+    if (a.has_pending) {
+        st.sel = commit_flags<float>(r, st.from_prop, &st.next);
+    } else {
+        st.next = draw_next_pair<float>(r);
+        st.sel = *r.sel;
+    }
+    batch_sample_class<RPT_MAX>(a, pd, c, r, st, lds);
 }
 
 template <int RPT>
@@ -291,9 +325,7 @@ __global__ __launch_bounds__(256) void batched_step_kernel(BatchArgs a) {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // one acquire, after the wait
     }
     __syncthreads();
-    const ChainRef<float> r = batch_ref(a, pd, p, c);
-    const int sel = a.has_pending ? commit_chain<float>(r) : *r.sel;
-    if (a.do_sample) batch_sample_class<RPT_MAX>(a, pd, c, r, sel, lds);
+    batch_chain_item<RPT_MAX>(a, pd, p, c, lds);
 }
 
 // Split form, second launch: one workgroup per chain (the caller's order).
@@ -303,10 +335,7 @@ template <int RPT_MAX>
 __global__ __launch_bounds__(256, RPT_MAX <= 8 ? 6 : 1) void batched_chain_kernel(BatchArgs a) {
     __shared__ __attribute__((aligned(16))) BatchLds<batch_keys<RPT_MAX>(), false> lds;
     const int2 ch = a.chains[blockIdx.x];
-    const ProbDesc& pd = a.descs[ch.x];
-    const ChainRef<float> r = batch_ref(a, pd, ch.x, ch.y);
-    const int sel = a.has_pending ? commit_chain<float>(r) : *r.sel;
-    if (a.do_sample) batch_sample_class<RPT_MAX>(a, pd, ch.y, r, sel, lds);
+    batch_chain_item<RPT_MAX>(a, a.descs[ch.x], ch.x, ch.y, lds);
 }
 
 // Projection tiles, one block per entry of the tile table (split form, and

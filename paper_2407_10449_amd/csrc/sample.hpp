@@ -544,7 +544,7 @@ __device__ __forceinline__ PairAhead<T> pair_ahead(const ChainRef<T>& r, bool fr
 // the first taken from `q`.
 template <typename T, int BS>
 __device__ __forceinline__ void move_pairs(const ChainRef<T>& r, double theta, bool from_prop,
-                                           bool copy_state, const PairAhead<T>& q,
+                                           bool copy_state, const PairAhead<T>* q,
                                            const NextPair<T>* next = nullptr) {
     if (threadIdx.x == 0 && r.theta_out) *r.theta_out = theta;
     double sd, cd;
@@ -555,11 +555,11 @@ __device__ __forceinline__ void move_pairs(const ChainRef<T>& r, double theta, b
         const int k = 2 * j;
         const bool two = k + 1 < r.d;
         T v0, v1, n0, n1;
-        if (j < BS) {
-            v0 = q.v0;
-            v1 = q.v1;
-            n0 = q.n0;
-            n1 = q.n1;
+        if (q && j < BS) {
+            v0 = q->v0;
+            v1 = q->v1;
+            n0 = q->n0;
+            n1 = q->n1;
         } else {
             v0 = src[k];
             n0 = r.nu[k];
@@ -1536,7 +1536,7 @@ __global__ __launch_bounds__(BS, (BS == 512 && RPT <= 4 && !REFINE) ? 8 : 1) voi
             next.z0 = next_lds[2 * threadIdx.x];
             next.z1 = next_lds[2 * threadIdx.x + 1];
         }
-        move_pairs<T, BS>(r, theta, from_prop, from_prop && a.has_pending, ahead, &next);
+        move_pairs<T, BS>(r, theta, from_prop, from_prop && a.has_pending, &ahead, &next);
     }
 }
 
