@@ -182,7 +182,8 @@ ess_status ess_transition_explicit(ess_ctx* ctx, const void* x, const void* nu,
  *   4 (mp dp + 3 Cp dp + 3 Cp mp) + 16 Cp mp bytes in precision 32 (8 in
  *   place of 4 in precision 64), mp = m and Cp = n_chains rounded up to 128,
  *   dp = d rounded up to 32; plus 6 mp dp bytes where precision 32 takes the
- *   split projections (as ess_init would: both 128 x 128 tiles), and 8 Cp m2
+ *   split projections (as ess_init would: 128 x 128 tiles, or 64 x 64 tiles
+ *   with d > 192), and 8 Cp m2
  *   bytes above 16384 rows (m2 = m rounded up to a power of two).
  * Every call on a device shares that device's array and keeps the last
  * call's contents there (the call clears what it needs): calls that overlap
@@ -208,14 +209,15 @@ ess_status ess_draw(ess_ctx* ctx, uint64_t step, void* nu, double* u);
  * restored afterwards.  report (host, nullable) receives one line per trial
  * and a last line "chosen: ...".
  * Batched contexts (ess_init_batched): problems fall into six size classes
- *   (d <= 64, d <= 192, d > 192, each split at m <= 256), each with its own
- *   tile shape (64x64, 32x64, 64x32 or 32x32 rows x chain columns); one pass
- *   of coordinate descent over the classes present, then the other launch
- *   form.
+ *   (d <= 64, d <= 192, d > 192, each split at m <= 256); the classes up to
+ *   192 columns each take a float32 tile shape (64x64, 32x64, 64x32 or
+ *   32x32 rows x chain columns), tuned by one pass of coordinate descent over
+ *   the classes present, then the other launch form.  Problems above 192
+ *   columns keep the split bfloat16 64 x 64 tiles.
  * Single-problem contexts: in precision 32 the split bfloat16 tiles (128 x
- *   128) and the float32 tiles 128x128, 128x64, 64x128 and 64x64, then the
- *   band height (1 to 16 tile rows) of the XCD-aware tile order; precision
- *   64 tunes the band height only.  A context of at most 12 chains (the
+ *   128 and 64 x 64) and the float32 tiles 128x128, 128x64, 64x128 and
+ *   64x64, then the band height (1 to 16 tile rows) of the XCD-aware tile
+ *   order; precision 64 tunes the band height only.  A context of at most 12 chains (the
  *   row-parallel projection) has nothing to tune and reports so.  The chains
  *   continue from the restored state on the chosen kernels, whose float32
  *   sums may round differently from the previous choice. */

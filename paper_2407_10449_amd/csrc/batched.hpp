@@ -38,9 +38,12 @@
 namespace ess {
 
 // Projection tile shapes, chosen per problem: 0 = 64 x 64, 1 = 32 x 64,
-// 2 = 64 x 32, 3 = 32 x 32 (rows of A x chain columns).  Rows are padded to
-// 64 and chains to 64, so every shape tiles the padded blocks exactly.
-constexpr int kBatchShapes = 4;
+// 2 = 64 x 32, 3 = 32 x 32 (rows of A x chain columns) on the float32
+// matrix cores, and 4 = 64 x 64 split bfloat16 tiles (problems with more than
+// 192 columns, as single-problem contexts take them).  Rows are padded to 64
+// and chains to 64, so every shape tiles the padded blocks exactly.
+constexpr int kBatchShapes = 4;   // the float32 shapes the autotuner picks from
+constexpr int kBatchSplitShape = 4;
 constexpr int kBatchPadM = 64, kBatchPadC = 64;
 __host__ __device__ constexpr int shape_bm(int s) { return (s & 1) ? 32 : 64; }
 __host__ __device__ constexpr int shape_bn(int s) { return (s & 2) ? 32 : 64; }
@@ -70,6 +73,8 @@ struct BatchArgs {
     int NTL;               // entries of the tile table (NT plus padding)
     const int2* chains;    // [NC]: (problem, chain), larger chain classes first
     const float* A;
+    const uint16_t* A3;    // [3][a_elems] bfloat16 pieces of A (piece p at A3 + p a_elems)
+    size_t a_elems;
     const double* b;
     float* X;
     float* Xprop;
@@ -152,13 +157,15 @@ __device__ __forceinline__ ChainRef<float> batch_ref(const BatchArgs& a, const P
 }
 
 // rows of 40 floats (conflict-free fragment reads, as in the single-problem
-// kernel); the largest shape takes 40 KB, so four workgroups share a CU
+// kernel); the largest float32 shape takes 40 KB and the split tile 48 KB, so
+// three workgroups share a CU
 constexpr int kBatchPadK = 8;
 union BatchGemmLds {
     GemmLds<64, 64, kBatchPadK> s0;
     GemmLds<32, 64, kBatchPadK> s1;
     GemmLds<64, 32, kBatchPadK> s2;
     GemmLds<32, 32, kBatchPadK> s3;
+    SplitLds<64> s4;
 };
 
 // Tile (tm, tn) of problem pd in its own shape (skipped when outside the
@@ -178,7 +185,13 @@ __device__ __forceinline__ void batch_tile(const BatchArgs& a, const ProbDesc& p
         case 0: gemm_tile_f32<64, 64, 2, 2, kBatchPadK>(A, B0, B1, pd.dp, m0, n0, o, L.s0); break;
         case 1: gemm_tile_f32<32, 64, 2, 2, kBatchPadK>(A, B0, B1, pd.dp, m0, n0, o, L.s1); break;
         case 2: gemm_tile_f32<64, 32, 2, 2, kBatchPadK>(A, B0, B1, pd.dp, m0, n0, o, L.s2); break;
-        default: gemm_tile_f32<32, 32, 2, 2, kBatchPadK>(A, B0, B1, pd.dp, m0, n0, o, L.s3); break;
+        case 3: gemm_tile_f32<32, 32, 2, 2, kBatchPadK>(A, B0, B1, pd.dp, m0, n0, o, L.s3); break;
+        default: {
+            const uint16_t* A3 = a.A3 + pd.a_off;
+            gemm_tile_split<64, 2, 2>(A3, A3 + a.a_elems, A3 + 2 * a.a_elems, B0, B1, pd.dp, m0, n0,
+                                      o, L.s4);
+            break;
+        }
     }
 }
 

@@ -155,6 +155,8 @@ struct ess_ctx {
         int4* tiles = nullptr;       // [max_table]
         int2* chains = nullptr;      // [NC], the caller's order
         float* A = nullptr;
+        uint16_t* A3 = nullptr;      // [3][sum mp dp] bfloat16 pieces of A (split tiles)
+        size_t a_elems = 0;          // sum over problems of mp dp
         float* X = nullptr;
         float* Xprop = nullptr;
         float* N = nullptr;
@@ -317,12 +319,18 @@ ess_status launch_proj(const ess_ctx* c, const Group& g, hipStream_t st, const v
         const float* B0 = static_cast<const float*>(Y) + off;
         const float* B1 = static_cast<const float*>(c->N) + off;
         const size_t plane = static_cast<size_t>(c->mp) * c->dp;
-        const int tiles_m = c->mp / 128, half = g.Cg / 128;
+        const int bt = c->bm;   // 128 or 64 (bm = bn)
+        const int tiles_m = c->mp / bt, half = g.Cg / bt;
         const int tn0 = (cols == COLS_NU) ? half : 0;
         const int tiles_n = (cols == COLS_BOTH) ? 2 * half : half;
-        hipLaunchKernelGGL((proj_gemm_split<4, 2>), dim3(tiles_m * tiles_n), dim3(512), 0, st,
-                           c->A3, c->A3 + plane, c->A3 + 2 * plane, B0, B1, c->dp, tiles_m,
-                           tiles_n, tn0, c->group_m, o);
+        if (bt == 128)
+            hipLaunchKernelGGL((proj_gemm_split<128, 4, 2>), dim3(tiles_m * tiles_n), dim3(512), 0,
+                               st, c->A3, c->A3 + plane, c->A3 + 2 * plane, B0, B1, c->dp, tiles_m,
+                               tiles_n, tn0, c->group_m, o);
+        else
+            hipLaunchKernelGGL((proj_gemm_split<64, 2, 2>), dim3(tiles_m * tiles_n), dim3(256), 0,
+                               st, c->A3, c->A3 + plane, c->A3 + 2 * plane, B0, B1, c->dp, tiles_m,
+                               tiles_n, tn0, c->group_m, o);
     } else if (c->prec == 32) {
         const float* B0 = static_cast<const float*>(Y) + off;
         if (c->bm == 128 && c->bn == 128) launch_f32<128, 128, 4, 2>(c, g, st, B0, cols, o);
@@ -658,6 +666,8 @@ BatchArgs batch_args(const ess_ctx* c) {
     a.NTL = B.NTL;
     a.chains = B.chains;
     a.A = B.A;
+    a.A3 = B.A3;
+    a.a_elems = B.a_elems;
     a.b = B.b;
     a.X = B.X;
     a.Xprop = B.Xprop;
@@ -788,7 +798,9 @@ ess_status batched_layout(ess_ctx* c) {
     constexpr int kXcds = 8;
     ess_ctx::Batch& B = *c->batch;
     for (auto& d : B.h) {
-        d.shape = B.bucket_shape[tile_bucket(d)];
+        // the split tiles for d > 192, whatever the class shapes (as in a
+        // single-problem context, so a problem's chains are the same alone)
+        d.shape = d.d > 192 ? kBatchSplitShape : B.bucket_shape[tile_bucket(d)];
         d.tiles_n = 2 * d.Cp / shape_bn(d.shape);
         d.ntiles = ((d.m + shape_bm(d.shape) - 1) / shape_bm(d.shape)) * d.tiles_n;
     }
@@ -891,6 +903,8 @@ ess_status batched_init(ess_ctx* c, const ess_problem* pr, int n) {
     ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.tiles), sizeof(int4) * B.max_table));
     ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.chains), sizeof(int2) * B.NC));
     ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.A), sizeof(float) * a_off));
+    B.a_elems = static_cast<size_t>(a_off);
+    ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.A3), 3 * sizeof(uint16_t) * B.a_elems));
     ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.b), sizeof(double) * b_off));
     ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.X), sizeof(float) * x_off));
     ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.Xprop), sizeof(float) * x_off));
@@ -921,6 +935,13 @@ ess_status batched_init(ess_ctx* c, const ess_problem* pr, int n) {
                                      sizeof(float) * d.d, sizeof(float) * d.d, d.C,
                                      hipMemcpyDefault, c->st));
         }
+    }
+    {   // A's bfloat16 pieces for the split tiles (padding stays zero)
+        const size_t n_el = B.a_elems;
+        const unsigned grid = static_cast<unsigned>(std::min<size_t>((n_el / 2 + 255) / 256, 4096));
+        hipLaunchKernelGGL(split_rows_kernel, dim3(grid), dim3(256), 0, c->st, B.A, n_el, B.A3,
+                           B.A3 + n_el, B.A3 + 2 * n_el);
+        HIP_TRY(hipGetLastError());
     }
     ESS_TRY(batched_layout(c));   // synchronises: the host chain table is copied
     return batched_set_state_from_X(c, "ess_init_batched");
@@ -1187,7 +1208,7 @@ bool single_valid(const ess_ctx* c, const SingleChoice& t) {
     const bool tile = (t.bm == 64 || t.bm == 128) && (t.bn == 64 || t.bn == 128);
     if (t.group_m < 1 || t.group_m > 64 || !tile) return false;
     if (c->prec == 64) return t.split == 0 && t.bm == 64 && t.bn == 64;
-    return !t.split || (t.bm == 128 && t.bn == 128);
+    return !t.split || t.bm == t.bn;   // split tiles: 128 x 128 or 64 x 64
 }
 
 // The cached choice for this shape, if any; ESS_PROJ_TILE keeps its tile.
@@ -1276,11 +1297,13 @@ ess_status autotune_single(ess_ctx* c, int32_t steps_per_trial, std::ostringstre
         shapes.push_back(before);
     } else {
         const int tiles[4][2] = {{128, 128}, {128, 64}, {64, 128}, {64, 64}};
-        SingleChoice sp;
-        sp.split = 1;
-        sp.bm = sp.bn = 128;
-        sp.group_m = before.group_m;
-        shapes.push_back(sp);
+        for (const int bt : {128, 64}) {
+            SingleChoice sp;
+            sp.split = 1;
+            sp.bm = sp.bn = bt;
+            sp.group_m = before.group_m;
+            shapes.push_back(sp);
+        }
         for (const auto& tb : tiles) {
             SingleChoice t;
             t.bm = tb[0];
@@ -1504,6 +1527,16 @@ ess_status mlp_backward(ess_mlp* n, const float* target, int B, double* loss) {
 
 // Start states for every chain: the candidate row where it is strictly
 // feasible, the fallback row elsewhere.
+// Float32 projections go through the split bfloat16 tiles at 128 x 128, and
+// at 64 x 64 once A has more than 192 columns (K of 224 or more, where the
+// matrix work dominates the tile); float32 matrix-core tiles otherwise.
+// Batched contexts follow the same rule per problem, so a problem's chains
+// are the same in a batch and alone.
+bool default_split(const ess_ctx* c) {
+    if (c->prec != 32 || c->bm != c->bn) return false;
+    return c->bm == 128 || c->d > 192;
+}
+
 // Projection tile shape of a single-problem context.
 void choose_tiles(ess_ctx* c) {
     if (c->prec == 32) {
@@ -1751,11 +1784,11 @@ ess_status ess_init(const ess_problem* pr, void* stream, ess_ctx** out) {
         fail(ESS_ERR_HIP, "copying the problem: %s", hipGetErrorString(e));
         return bail(ESS_ERR_HIP);
     }
-    // float32 projections through exact bfloat16 splits wherever the 128 x
-    // 128 tiles fill the device, unless a tuned choice for this shape is
-    // cached (ess_autotune); ESS_PROJ=f32 keeps the float32 matrix cores and
-    // ESS_PROJ_TILE a tile shape whatever the cache holds
-    c->split_proj = c->prec == 32 && c->bm == 128 && c->bn == 128;
+    // float32 projections through exact bfloat16 splits where default_split
+    // says so, unless a tuned choice for this shape is cached (ess_autotune);
+    // ESS_PROJ=f32 keeps the float32 matrix cores and ESS_PROJ_TILE a tile
+    // shape whatever the cache holds
+    c->split_proj = default_split(c);
     load_tuned_single(c);
     {
         const char* pe = std::getenv("ESS_PROJ");
@@ -2001,8 +2034,7 @@ ess_status ess_transition_explicit_static(int32_t d, int32_t m, int32_t n_chains
     {
         // the projections ess_init would choose, so the values agree
         const char* pe = std::getenv("ESS_PROJ");
-        c.split_proj = precision == 32 && c.bm == 128 && c.bn == 128 &&
-                       !(pe && std::strcmp(pe, "f32") == 0);
+        c.split_proj = default_split(&c) && !(pe && std::strcmp(pe, "f32") == 0);
     }
     if (m > kMaxRowsLds) {
         c.kstride = 512;
@@ -2362,7 +2394,8 @@ ess_status ess_autotune(ess_ctx* c, int32_t steps_per_trial, char* report, int32
     HIP_TRY(hipMemcpyAsync(saved, B.X, bytes, hipMemcpyDeviceToDevice, c->st));
     const uint64_t step0 = c->step;
     bool present[kTileBuckets] = {};
-    for (const auto& d : B.h) present[tile_bucket(d)] = true;
+    for (const auto& d : B.h)   // problems above 192 columns keep the split tiles
+        if (d.d <= 192) present[tile_bucket(d)] = true;
 
     HIP_TRY(hipEventCreate(&scr.e0));
     HIP_TRY(hipEventCreate(&scr.e1));

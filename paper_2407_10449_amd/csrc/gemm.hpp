@@ -260,7 +260,8 @@ __global__ __launch_bounds__(64 * NW_M * NW_N) void proj_gemm_f32(const float* _
 //
 // A is split once at init (three [mp][dp] arrays of bfloat16); the x' and
 // nu rows stay float32 in memory and are split while they are staged into
-// LDS.  Tile 128 x 128, K slabs of 32 (one MFMA deep), double-buffered LDS.
+// LDS.  Tiles of 128 x 128 (eight waves) or 64 x 64 (four waves), K slabs of
+// 32 (one MFMA deep), double-buffered LDS.
 // A row of a slab is 32 bfloat16 = four 16-byte chunks, stored unpadded with
 // chunk q of row r at position q ^ ((r >> 2) & 3): the 16 rows of a fragment
 // read (one chunk each) and the 16 chunks of four rows a store covers both
@@ -268,15 +269,16 @@ __global__ __launch_bounds__(64 * NW_M * NW_N) void proj_gemm_f32(const float* _
 // ---------------------------------------------------------------------------
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
+template <int BT>
 struct SplitLds {
-    static constexpr int BM = 128, BN = 128, BK = 32, LK = 32;
+    static constexpr int BM = BT, BN = BT, BK = 32, LK = 32;
     uint16_t a[2][3][BM * LK];
     uint16_t b[2][3][BN * LK];
 };
 
 // element offset of chunk q (8 bfloat16) of row r in a swizzled slab
 __device__ __forceinline__ int split_chunk(int r, int q) {
-    return r * SplitLds::LK + ((q ^ ((r >> 2) & 3)) << 3);
+    return r * 32 + ((q ^ ((r >> 2) & 3)) << 3);
 }
 
 // bfloat16 rounding (to nearest, ties to even) of a float's bits, as the
@@ -326,14 +328,14 @@ __global__ __launch_bounds__(256) void split_rows_kernel(const float* __restrict
     }
 }
 
-template <int NW_M, int NW_N>
+template <int BT, int NW_M, int NW_N>
 __device__ __forceinline__ void gemm_tile_split(const uint16_t* __restrict__ A0,
                                                 const uint16_t* __restrict__ A1,
                                                 const uint16_t* __restrict__ A2,
                                                 const float* __restrict__ B0,
                                                 const float* __restrict__ B1, int K, int m0, int n0,
-                                                const ProjOut& o, SplitLds& L) {
-    constexpr int BM = SplitLds::BM, BN = SplitLds::BN, BK = SplitLds::BK, LK = SplitLds::LK;
+                                                const ProjOut& o, SplitLds<BT>& L) {
+    constexpr int BM = BT, BN = BT, BK = SplitLds<BT>::BK, LK = SplitLds<BT>::LK;
     constexpr int NT = 64 * NW_M * NW_N;
     constexpr int WM = BM / NW_M, WN = BN / NW_N, TM = WM / 16, TN = WN / 16;
     constexpr int LD = BM * BK / 8 / NT;   // 16-byte chunks of 8 k per thread and piece
@@ -474,16 +476,16 @@ __device__ __forceinline__ void gemm_tile_split(const uint16_t* __restrict__ A0,
         }
 }
 
-template <int NW_M, int NW_N>
+template <int BT, int NW_M, int NW_N>
 __global__ __launch_bounds__(64 * NW_M * NW_N) void proj_gemm_split(
     const uint16_t* __restrict__ A0, const uint16_t* __restrict__ A1,
     const uint16_t* __restrict__ A2, const float* __restrict__ B0, const float* __restrict__ B1,
     int K, int tiles_m, int tiles_n, int tn0, int group_m, ProjOut o) {
-    __shared__ __attribute__((aligned(16))) SplitLds lds;
+    __shared__ __attribute__((aligned(16))) SplitLds<BT> lds;
     int tm, tn;
     tile_coords(blockIdx.x, tiles_m, tiles_n, group_m, tm, tn);
     tn += tn0;
-    gemm_tile_split<NW_M, NW_N>(A0, A1, A2, B0, B1, K, tm * SplitLds::BM, tn * SplitLds::BN, o, lds);
+    gemm_tile_split<BT, NW_M, NW_N>(A0, A1, A2, B0, B1, K, tm * BT, tn * BT, o, lds);
 }
 
 // float64 projections on the vector ALUs (MI355X runs float64 FMA on the
