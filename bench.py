@@ -201,9 +201,12 @@ def bench_batched(E, torch, steps=50, plain_steps=10):
     for q in singles:
         q.close()
     flops = sum(4.0 * p.m * p.d * p.n_chains for p in probs)
-    kernels = ({"fused_step_ms": fused_ms / fused_n} if fused_n else
-               {"tiles_ms": tile_ms / max(tile_n, 1), "chains_ms": chain_ms / max(chain_n, 1),
-                "projection_tflops": flops / (tile_ms / max(tile_n, 1) / 1e3) / 1e12 if tile_n else None})
+    # durations per step, summed over the step's launches (one tile and one
+    # chain launch per problem set; the sets' launches overlap on the device)
+    kernels = ({"fused_step_ms": fused_ms / steps} if fused_n else
+               {"tiles_ms": tile_ms / steps, "chains_ms": chain_ms / steps,
+                "launches_per_step": round(tile_n / (steps + 1)),
+                "projection_tflops": flops / (tile_ms / steps / 1e3) / 1e12 if tile_n else None})
     return {"workload": "batched_uneven: 256 polytopes, d log-uniform [16,512], m = d U{1..4}, 64 chains each",
             "chain_steps_per_s": C * steps / dt,
             "ms_per_step": dt * 1e3 / steps,

@@ -148,6 +148,13 @@ struct ess_ctx {
         int max_tiles = 0;           // NT with the smallest tiles everywhere
         int max_table = 0;           // tile table capacity (max_tiles plus XCD padding)
         int bucket_shape[kTileBuckets] = {};   // tile shape of each size class
+        // problem sets advanced on streams of their own (split launch form):
+        // set k's tiles are tiles[set_toff[k] ..) (set_ntl[k] entries) and its
+        // chains chains[set_coff[k] ..) (set_nc[k])
+        int nsets = 1;
+        std::vector<int> set_of;     // [n] the set of each problem
+        int set_toff[kMaxGroups] = {}, set_ntl[kMaxGroups] = {};
+        int set_coff[kMaxGroups] = {}, set_nc[kMaxGroups] = {};
         std::vector<ProbDesc> h;
         std::vector<int> order;      // problems by decreasing projection work
         ProbDesc* descs = nullptr;
@@ -185,6 +192,19 @@ ess_status dalloc(ess_ctx* c, void** p, size_t bytes) {
     HIP_TRY(hipMalloc(p, bytes));
     c->allocs.push_back(*p);
     HIP_TRY(hipMemsetAsync(*p, 0, bytes, c->st));
+    return ESS_OK;
+}
+
+// The group streams and their events (every one exists from the start: the
+// autotuner and cached choices may raise the group count later).
+ess_status create_group_streams(ess_ctx* c) {
+    hipError_t ee = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
+    for (int g = 0; g < kMaxGroups && ee == hipSuccess; ++g) {
+        ee = hipStreamCreateWithFlags(&c->gs[g], hipStreamNonBlocking);
+        if (ee == hipSuccess) ee = hipEventCreateWithFlags(&c->join[g], hipEventDisableTiming);
+        if (ee == hipSuccess) ee = hipEventCreateWithFlags(&c->stagger[g], hipEventDisableTiming);
+    }
+    if (ee != hipSuccess) return fail(ESS_ERR_HIP, "creating group streams: %s", hipGetErrorString(ee));
     return ESS_OK;
 }
 
@@ -757,6 +777,13 @@ ess_status batched_issue(ess_ctx* c, int64_t n_steps, int64_t thin, void* trace,
         return ESS_OK;
     }));
     const size_t row = static_cast<size_t>(B.state_elems);
+    // the split form with several problem sets: each set's steps on a stream
+    // of its own, forked from st after the draw and joined before the counter
+    const bool sets = !B.fused && B.nsets > 1;
+    if (sets) {
+        HIP_TRY(hipEventRecord(c->fork, st));
+        for (int k = 0; k < B.nsets; ++k) HIP_TRY(hipStreamWaitEvent(c->gs[k], c->fork, 0));
+    }
     for (int64_t s = 0; s <= n_steps; ++s) {
         a.step = static_cast<uint32_t>(s);
         a.has_pending = s > 0;
@@ -768,7 +795,24 @@ ess_status batched_issue(ess_ctx* c, int64_t n_steps, int64_t thin, void* trace,
         a.trace = (trace && s > 0 && s % thin == 0)
                       ? static_cast<float*>(trace) + (s / thin - 1) * row
                       : nullptr;
-        ESS_TRY(launch_batched_step(c, a, st));
+        if (!sets) {
+            ESS_TRY(launch_batched_step(c, a, st));
+            continue;
+        }
+        for (int k = 0; k < B.nsets; ++k) {
+            BatchArgs ak = a;
+            ak.tiles = B.tiles + B.set_toff[k];
+            ak.NTL = B.set_ntl[k];
+            ak.chains = B.chains + B.set_coff[k];
+            ak.NC = B.set_nc[k];
+            ESS_TRY(launch_batched_step(c, ak, c->gs[k]));
+        }
+    }
+    if (sets) {
+        for (int k = 0; k < B.nsets; ++k) {
+            HIP_TRY(hipEventRecord(c->join[k], c->gs[k]));
+            HIP_TRY(hipStreamWaitEvent(st, c->join[k], 0));
+        }
     }
     return launch_step_counter(c, st, static_cast<uint64_t>(n_steps), 1);
 }
@@ -805,25 +849,34 @@ ess_status batched_layout(ess_ctx* c) {
         d.ntiles = ((d.m + shape_bm(d.shape) - 1) / shape_bm(d.shape)) * d.tiles_n;
     }
     std::vector<int> wg;
-    std::vector<int4> lists[kXcds];
+    std::vector<int4> table;
     B.NT = 0;
-    for (int p : B.order) {
-        const ProbDesc& d = B.h[p];
-        wg.insert(wg.end(), d.ntiles, p);
-        B.NT += d.ntiles;
-        for (int tm = 0; tm < d.ntiles / d.tiles_n; ++tm) {
-            int x = 0;
-            for (int y = 1; y < kXcds; ++y)
-                if (lists[y].size() < lists[x].size()) x = y;
-            for (int tn = 0; tn < d.tiles_n; ++tn) lists[x].push_back(make_int4(p, tm, tn, 0));
-        }
+    for (const int p : B.order) {
+        wg.insert(wg.end(), B.h[p].ntiles, p);
+        B.NT += B.h[p].ntiles;
     }
     for (int p : B.order) wg.insert(wg.end(), B.h[p].C, p);
-    size_t len = 0;
-    for (auto& l : lists) len = std::max(len, l.size());
-    std::vector<int4> table(kXcds * len, make_int4(-1, 0, 0, 0));
-    for (int x = 0; x < kXcds; ++x)
-        for (size_t k = 0; k < lists[x].size(); ++k) table[kXcds * k + x] = lists[x][k];
+    // one XCD-interleaved segment of the tile table per problem set
+    for (int k = 0; k < B.nsets; ++k) {
+        std::vector<int4> lists[kXcds];
+        for (int p : B.order) {
+            if (B.set_of[p] != k) continue;
+            const ProbDesc& d = B.h[p];
+            for (int tm = 0; tm < d.ntiles / d.tiles_n; ++tm) {
+                int x = 0;
+                for (int y = 1; y < kXcds; ++y)
+                    if (lists[y].size() < lists[x].size()) x = y;
+                for (int tn = 0; tn < d.tiles_n; ++tn) lists[x].push_back(make_int4(p, tm, tn, 0));
+            }
+        }
+        size_t len = 0;
+        for (auto& l : lists) len = std::max(len, l.size());
+        B.set_toff[k] = static_cast<int>(table.size());
+        B.set_ntl[k] = static_cast<int>(kXcds * len);
+        table.resize(table.size() + kXcds * len, make_int4(-1, 0, 0, 0));
+        for (int x = 0; x < kXcds; ++x)
+            for (size_t j = 0; j < lists[x].size(); ++j) table[B.set_toff[k] + kXcds * j + x] = lists[x][j];
+    }
     if (B.NT > B.max_tiles || static_cast<long long>(table.size()) > B.max_table)
         return fail(ESS_ERR_INVALID_ARG, "batched layout: tile table overflow");
     B.NTL = static_cast<int>(table.size());
@@ -880,8 +933,8 @@ ess_status batched_init(ess_ctx* c, const ess_problem* pr, int n) {
     B.state_elems = t_off;
     B.chains_padded = chain_off;
     B.max_tiles = static_cast<int>(max_tiles);
-    // greedy by count: list lengths differ by at most one panel
-    B.max_table = static_cast<int>(max_tiles + 8ll * (max_panel + 1));
+    // greedy by count: list lengths differ by at most one panel (per set)
+    B.max_table = static_cast<int>(max_tiles + 8ll * kMaxGroups * (max_panel + 1));
     B.rpt = (max_m + 255) / 256;
     // problems with the most projection work first, so their tiles start early
     B.order.resize(n);
@@ -890,12 +943,36 @@ ess_status batched_init(ess_ctx* c, const ess_problem* pr, int n) {
         return static_cast<long long>(B.h[x].mp) * B.h[x].dp * B.h[x].Cp >
                static_cast<long long>(B.h[y].mp) * B.h[y].dp * B.h[y].Cp;
     });
-    // chains of the larger classes first, so the longest chain items start early
+    // Problem sets, each advanced on a stream of its own: a set's chains wait
+    // only for its own tiles, so one set's chain kernel runs beside another
+    // set's tiles instead of after every tile of the batch.  Problems go,
+    // largest first, to the set with the least work so far (rows x chains x
+    // (columns + 128), projections plus per-row chain work).
+    {
+        int ns = 2;
+        if (const char* e = std::getenv("ESS_BATCH_SETS")) ns = std::atoi(e);
+        B.nsets = std::max(1, std::min(std::min(ns, kMaxGroups), n));
+        B.set_of.assign(n, 0);
+        double load[kMaxGroups] = {};
+        for (int p : B.order) {
+            int k = 0;
+            for (int j = 1; j < B.nsets; ++j)
+                if (load[j] < load[k]) k = j;
+            B.set_of[p] = k;
+            load[k] += static_cast<double>(B.h[p].m) * B.h[p].C * (B.h[p].d + 128);
+        }
+    }
+    // within a set, chains of the larger classes first, so the longest chain
+    // items start early
     std::vector<int2> chains;
-    for (int cls = 4; cls >= 0; --cls)
-        for (int p = 0; p < n; ++p)
-            if (B.h[p].cls == cls)
-                for (int ch = 0; ch < B.h[p].C; ++ch) chains.push_back(make_int2(p, ch));
+    for (int k = 0; k < B.nsets; ++k) {
+        B.set_coff[k] = static_cast<int>(chains.size());
+        for (int cls = 4; cls >= 0; --cls)
+            for (int p = 0; p < n; ++p)
+                if (B.set_of[p] == k && B.h[p].cls == cls)
+                    for (int ch = 0; ch < B.h[p].C; ++ch) chains.push_back(make_int2(p, ch));
+        B.set_nc[k] = static_cast<int>(chains.size()) - B.set_coff[k];
+    }
     B.NC = static_cast<int>(chains.size());
 
     ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.descs), sizeof(ProbDesc) * n));
@@ -919,6 +996,7 @@ ess_status batched_init(ess_ctx* c, const ess_problem* pr, int n) {
     ESS_TRY(dalloc(c, reinterpret_cast<void**>(&c->rej), sizeof(long long) * chain_off));
     ESS_TRY(dalloc(c, reinterpret_cast<void**>(&c->d_step), sizeof(uint32_t)));
     ESS_TRY(create_run_streams(c));
+    ESS_TRY(create_group_streams(c));
     HIP_TRY(hipMemcpyAsync(B.chains, chains.data(), sizeof(int2) * B.NC, hipMemcpyHostToDevice,
                            c->st));
     for (int p = 0; p < n; ++p) {
@@ -1743,20 +1821,7 @@ ess_status ess_init(const ess_problem* pr, void* stream, ess_ctx** out) {
                         sizeof(uint64_t) * static_cast<size_t>(c->Cp) * c->kstride)) != ESS_OK)
             return bail(s);
     }
-    {
-        // every group stream and event exists from the start: the autotuner and
-        // cached choices may raise the group count up to kMaxGroups later
-        hipError_t ee = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
-        for (int g = 0; g < kMaxGroups && ee == hipSuccess; ++g) {
-            ee = hipStreamCreateWithFlags(&c->gs[g], hipStreamNonBlocking);
-            if (ee == hipSuccess) ee = hipEventCreateWithFlags(&c->join[g], hipEventDisableTiming);
-            if (ee == hipSuccess) ee = hipEventCreateWithFlags(&c->stagger[g], hipEventDisableTiming);
-        }
-        if (ee != hipSuccess) {
-            fail(ESS_ERR_HIP, "creating group streams: %s", hipGetErrorString(ee));
-            return bail(ESS_ERR_HIP);
-        }
-    }
+    if ((s = create_group_streams(c)) != ESS_OK) return bail(s);
 
     hipError_t e = hipMemcpy2DAsync(c->A, static_cast<size_t>(c->dp) * c->esz, pr->A,
                                     static_cast<size_t>(c->d) * c->esz,

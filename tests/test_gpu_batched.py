@@ -179,3 +179,18 @@ def test_batched_problem_zero_equals_its_own_context(E):
     alone, _ = s.run(6)
     s.close()
     assert torch.equal(first, alone)
+
+
+def test_batched_problem_sets_give_identical_chains(E, monkeypatch):
+    """Problem sets advanced on streams of their own change only which
+    launches may overlap: one, two and four sets give bit-identical chains."""
+    probs = problems(12, 16, seed=21)
+    outs = []
+    for n in ("1", "2", "4"):
+        monkeypatch.setenv("ESS_BATCH_SETS", n)
+        s = E.BatchedSampler(probs)
+        tr, _ = s.run(5)
+        s.close()
+        outs.append(tr)
+    assert torch.equal(outs[0], outs[1])
+    assert torch.equal(outs[0], outs[2])
