@@ -100,79 +100,22 @@ constexpr double kKeyScale = 281474976710656.0 / kTwoPi;   // 2^48 / (2 pi)
 constexpr uint64_t kKeyMax = (1ull << 48) - 1;
 constexpr int SMAX = 128;   // survivors the bucket path resolves in place
 
-// Float32 angle functions of the root solve, from near-minimax polynomials
-// fitted by fit_angle_poly.py (beside this file; coefficients lowest degree
-// first):
-//   atan(t) = t + t^3 P(t^2) on [0, 1], and
-//   asin(s) = s + s w Q(w) with w = s^2 on [0, 1/2].
-// Evaluated in float32 with the reciprocal and the square root anywhere
-// within their one-ulp hardware bound, the first gives atan2 within 1.2e-7
-// rad (its reflections are done in float64; atan2 correctly rounded to
-// float32 is within 1.2e-7) and the second asin(sqrt w) within 1.5e-7 (with
-// a correctly rounded root 8.3e-8, against 8.5e-8 for a correctly rounded
-// asinf); tests/test_angle_poly.py checks both.  They take the place of the
-// library's atan2f and asinf, which also handle infinities, NaNs and tiny
-// arguments that cannot reach them here.
-constexpr float kAtanP[9] = {-0.3333333134651184f, 0.1999979019165039f, -0.14279615879058838f,
-                             0.11042028665542603f, -0.08689016848802567f, 0.06318161636590958f,
-                             -0.036669593304395676f, 0.013996055349707603f,
-                             -0.0025084686931222677f};
-constexpr float kAsinQ[8] = {0.1666666567325592f, 0.0750032514333725f, 0.04451508820056915f,
-                             0.032277949154376984f, 0.008776996284723282f, 0.06869693100452423f,
-                             -0.08689224720001221f, 0.09881732612848282f};
-
-template <int N>
-__device__ __forceinline__ float horner_f32(const float (&c)[N], float x) {
-    float acc = c[N - 1];
-#pragma unroll
-    for (int k = N - 2; k >= 0; --k) acc = fmaf(acc, x, c[k]);
-    return acc;
-}
-
-// atan2(q, p) for finite q, p, not both zero: the octant's ratio t = min / max
-// in [0, 1] and atan(t) in float32, then the octant's reflections in float64
-// (pi / 2 - r, pi - r), so the result keeps the accuracy of r (at most pi / 4)
-// instead of a float32 rounding at the scale of pi; the sign of q, as atan2.
-__device__ __forceinline__ double atan2_poly(float q, float p) {
-    float ax = fabsf(p), ay = fabsf(q);
-    if (fmaxf(ax, ay) < 0x1p-100f) {   // keep the reciprocal away from denormals
-        ax *= 0x1p100f;
-        ay *= 0x1p100f;
-    }
-    const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
-    // the hardware reciprocal (one ulp) and one Newton step
-    const float r0 = __builtin_amdgcn_rcpf(mx);
-    const float inv = fmaf(r0, fmaf(-mx, r0, 1.0f), r0);
-    const float t = mn * inv;
-    const float u = t * t;
-    double r = static_cast<double>(fmaf(t * u, horner_f32(kAtanP, u), t));
-    if (ay > ax) r = 0.5 * kPi - r;
-    if (p < 0.0f) r = kPi - r;
-    return signbit(q) ? -r : r;
-}
-
-// asin(sqrt w) for w in [0, 1/2]
-__device__ __forceinline__ float asin_sqrt_poly(float w) {
-    const float s = __builtin_amdgcn_sqrtf(w);
-    return fmaf(s * w, horner_f32(kAsinQ, w), s);
-}
-
 // T is the storage type of p and q.  With float storage, a float32 test of
 // z = b / r >= 1.01 (as b^2 >= 1.0201 r^2, relative error a few 1e-7) first
 // discards rows that certainly miss the ellipse, which saves the float64 work
 // for about a third of the rows at the benchmarked shape.  For every other
 // row z is float64, and the two angles come from float32 functions of
 // well-conditioned float64 quantities:
-// * tau = atan2 of the exact floats q, p (atan2_poly, within 1.2e-7 rad);
+// * tau = atan2 of the exact floats q, p, off by a few float ulps (< 1e-6 rad);
 // * phi = acos z through the half-angle form 2 asin sqrt((1 - |z|) / 2),
 //   mirrored to pi - that for z < 0.  1 - |z| is formed in float64, where it
 //   is exact to the rounding of z, so the one float32 rounding of its half
 //   moves phi by a relative 2^-24, and sqrt and asin (argument at most
-//   sqrt(1/2), where asin's slope is at most sqrt(2); asin_sqrt_poly) add a
-//   few ulps: phi is within a few 1e-7 rad everywhere, near tangency (z -> 1,
-//   a tiny arc) included, inside the 1e-6 rad trim of the interval ends.
-//   (acos of z rounded to float32 amplifies that rounding by
-//   1 / sqrt(1 - z^2) without bound near tangency.)
+//   sqrt(1/2), where asin's slope is at most sqrt(2)) add a few ulps: phi is
+//   within a few 1e-7 rad everywhere, near tangency (z -> 1, a tiny arc)
+//   included, inside the 1e-6 rad trim of the interval ends.  (acos of z
+//   rounded to float32 amplifies that rounding by 1 / sqrt(1 - z^2) without
+//   bound near tangency.)
 // With double storage both angles are float64.  The wrap, alpha, beta and
 // every later comparison are float64.
 template <typename T>
@@ -203,9 +146,9 @@ __device__ __forceinline__ bool solve_roots(double p, double q, double bi, doubl
     z = fmax(z, -1.0);
     double tau, phi;
     if (sizeof(T) == 4) {
-        tau = atan2_poly(static_cast<float>(q), static_cast<float>(p));
+        tau = static_cast<double>(atan2f(static_cast<float>(q), static_cast<float>(p)));
         const float w = static_cast<float>(0.5 * (1.0 - fabs(z)));
-        const double h = 2.0 * static_cast<double>(asin_sqrt_poly(w));
+        const double h = 2.0 * static_cast<double>(asinf(sqrtf(w)));
         phi = z >= 0.0 ? h : kPi - h;
     } else {
         tau = atan2(q, p);
