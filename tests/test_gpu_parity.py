@@ -57,6 +57,9 @@ CASES = [
     # name, d, m, C, precision, eps
     ("ragged_f32", 37, 150, 300, 32, 1e-6),
     ("bm128_f32", 200, 1030, 600, 32, 1e-6),
+    # d > 192 where 128 x 128 tiles would not fill the device: the split
+    # bfloat16 projection on 64 x 64 tiles, ragged in rows, chains and K
+    ("split64_ragged_f32", 229, 777, 333, 32, 1e-6),
     ("small_f64", 10, 20, 16, 64, 0.0),
     ("ragged_f64", 65, 300, 130, 64, 0.0),
     ("univariate_f32", 1, 2, 64, 32, 0.0),
@@ -808,4 +811,39 @@ def test_split_projections_are_as_accurate_as_float32_matrix_cores(E, monkeypatc
         errs[mode] = max(v.max() for v in e)
     say("projection error / sum |a y|:", errs)
     assert errs["split"] <= pr.d * 2.0 ** -24
+    assert errs["split"] <= 2 * errs["f32"]
+
+
+def test_split_64_tiles_are_as_accurate_as_float32_matrix_cores(E, monkeypatch):
+    """The same comparison on the split bfloat16 64 x 64 tiles (the default
+    for d > 192 where 128 x 128 tiles do not fill the device) against the
+    float32 matrix-core 64 x 64 tiles, at d = 300, m = 900, 512 chains."""
+    rng = np.random.default_rng(8)
+    d, m, C = 300, 900, 512
+    A = rng.standard_normal((m, d)) / math.sqrt(d)
+    b = rng.uniform(0.5, 1.5, m)
+    x = chain_states(A, b, C, np.float32, seed=5)
+    nu = rng.standard_normal(x.shape).astype(np.float32)
+    u = rng.uniform(size=C)
+    A32 = A.astype(np.float32).astype(np.float64)
+    rows = rng.choice(m, 300, replace=False)
+    chains = rng.choice(C, 64, replace=False)
+    errs = {}
+    for mode in ("split", "f32"):
+        if mode == "f32":
+            monkeypatch.setenv("ESS_PROJ", "f32")
+        else:
+            monkeypatch.delenv("ESS_PROJ", raising=False)
+        s = E.Sampler(A, b, x, C, seed=0, precision=32, trim_eps=1e-6)
+        pq = s.transition_explicit(x, nu, u)["pq"].cpu().numpy().astype(np.float64)
+        s.close()
+        e = []
+        for k, y in enumerate((x, nu)):
+            Y = y[chains].astype(np.float64)
+            ref = Y @ A32[rows].T
+            mag = np.abs(Y) @ np.abs(A32[rows]).T
+            e.append(np.abs(pq[k][chains][:, rows] - ref) / mag)
+        errs[mode] = max(v.max() for v in e)
+    say("64 x 64 tiles, projection error / sum |a y|:", errs)
+    assert errs["split"] <= d * 2.0 ** -24
     assert errs["split"] <= 2 * errs["f32"]
