@@ -234,12 +234,13 @@ __device__ __forceinline__ void batch_sample(const BatchArgs& a, const ProbDesc&
                                              BucketLds<NB>& bucket, const FullLds& L) {
     double2* abg = a.ab + pd.q_off + static_cast<size_t>(c) * pd.mp;
     double theta = 0.0;
-    if (!bucket_chain<float, RPT, NB>(r, st.sel, bucket, theta, nullptr, abg)) {
+    const bool done = bucket_chain<float, RPT, NB>(r, st.sel, bucket, theta, nullptr, abg);
+    if (!done) {
         __syncthreads();   // every row's alpha and beta is in a.ab
         theta = full_chain<float, KEYS_ROW_AB, 256>(r, st.sel, L, abg);
     }
     move_pairs<float, 256>(r, theta, st.from_prop, st.from_prop && a.has_pending, nullptr,
-                           &st.next);
+                           &st.next, done ? bucket.sc : nullptr);
 }
 
 // The chain's class picks the rows per thread and the bucket count, so a

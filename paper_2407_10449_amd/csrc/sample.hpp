@@ -545,10 +545,16 @@ __device__ __forceinline__ PairAhead<T> pair_ahead(const ChainRef<T>& r, bool fr
 template <typename T, int BS>
 __device__ __forceinline__ void move_pairs(const ChainRef<T>& r, double theta, bool from_prop,
                                            bool copy_state, const PairAhead<T>* q,
-                                           const NextPair<T>* next = nullptr) {
+                                           const NextPair<T>* next = nullptr,
+                                           const double* sc = nullptr) {
     if (threadIdx.x == 0 && r.theta_out) *r.theta_out = theta;
     double sd, cd;
-    sincos(theta, &sd, &cd);
+    if (sc) {   // sin theta, cos theta taken once by the bucket path
+        sd = sc[0];
+        cd = sc[1];
+    } else {
+        sincos(theta, &sd, &cd);
+    }
     const T ct = static_cast<T>(cd), st = static_cast<T>(sd);
     const T* src = from_prop ? r.xp : r.x;
     for (int j = threadIdx.x; 2 * j < r.d; j += BS) {
@@ -855,6 +861,7 @@ struct BucketLds {
     int scount, kstar, klast;
     int smin, smax;                    // bucket range of the survivors (refinement)
     double theta;
+    double sc[2];                      // sin theta, cos theta (by the lane that set theta)
 };
 
 // Levels of bucket refinement before a chain goes to the full path, and the
@@ -1114,6 +1121,10 @@ __device__ __forceinline__ double finish_bucket(const ChainRef<T>& r, BucketLds<
     // lengths are formed in parallel, one thread keeps the running sums in
     // LDS, and the search is parallel.  Both give the same theta bit for bit.
     const int Su = __builtin_amdgcn_readfirstlane(S);
+    // the one lane that finds theta also takes its sine and cosine for the
+    // move, once per chain instead of once per wave
+    bool mine = false;
+    double th = 0.0;
     if (Su < 64) {
         if (tid < 64) {
             const bool in = tid <= Su;
@@ -1132,13 +1143,16 @@ __device__ __forceinline__ double finish_bucket(const ChainRef<T>& r, BucketLds<
                 const unsigned long long pos = __ballot(len > 0.0);
                 const unsigned long long hit = __ballot(len > 0.0 && cum > sv);
                 if (hit) {
-                    if (tid == __ffsll(static_cast<long long>(hit)) - 1)
-                        L.theta = fmax(lo, fmin(lo + (sv - before), hi));
+                    if (tid == __ffsll(static_cast<long long>(hit)) - 1) {
+                        th = fmax(lo, fmin(lo + (sv - before), hi));
+                        mine = true;
+                    }
                 } else if (tid == 63 - __clzll(static_cast<long long>(pos))) {
-                    L.theta = hi;   // rounding put s at the total
+                    th = hi;   // rounding put s at the total
+                    mine = true;
                 }
             } else if (tid == 0) {
-                L.theta = 0.0;
+                mine = true;   // theta 0
                 *r.flag = 1;   // empty active set: stay, counted as a rejection
             }
         }
@@ -1178,15 +1192,23 @@ __device__ __forceinline__ double finish_bucket(const ChainRef<T>& r, BucketLds<
                 const int k = L.kstar;
                 if (k <= S) {
                     const double before = k > 0 ? L.cum[k - 1] : 0.0;
-                    L.theta = fmax(L.lo[k], fmin(L.lo[k] + (sv - before), L.hi[k]));
+                    th = fmax(L.lo[k], fmin(L.lo[k] + (sv - before), L.hi[k]));
                 } else {
-                    L.theta = L.hi[L.klast];   // rounding put s at the total
+                    th = L.hi[L.klast];   // rounding put s at the total
                 }
+                mine = true;
             }
         } else if (tid == 0) {
-            L.theta = 0.0;
+            mine = true;   // theta 0
             *r.flag = 1;   // empty active set: stay, counted as a rejection
         }
+    }
+    if (mine) {
+        double sd, cd;
+        sincos(th, &sd, &cd);
+        L.theta = th;
+        L.sc[0] = sd;
+        L.sc[1] = cd;
     }
     if (tid == 0 && r.intervals) {
         int w = 0;
@@ -1536,7 +1558,8 @@ __global__ __launch_bounds__(BS, (BS == 512 && RPT <= 4 && !REFINE) ? 8 : 1) voi
             next.z0 = next_lds[2 * threadIdx.x];
             next.z1 = next_lds[2 * threadIdx.x + 1];
         }
-        move_pairs<T, BS>(r, theta, from_prop, from_prop && a.has_pending, &ahead, &next);
+        move_pairs<T, BS>(r, theta, from_prop, from_prop && a.has_pending, &ahead, &next,
+                          done ? lds.bucket.sc : nullptr);
     }
 }
 
