@@ -416,12 +416,14 @@ __device__ __forceinline__ void gemm_tile_split(const uint16_t* __restrict__ A0,
         // l % 16 is that of the fragment's row)
         const int fa = split_chunk(wm * WM + (lane & 15), lane >> 4);
         const int fb = split_chunk(wn * WN + (lane & 15), lane >> 4);
+        // read in the order the products below first need the pieces:
+        // (lo A, hi B), (mid A, mid B), (hi A, lo B)
         bf16x8 af[3][TM], bfr[3][TN];
 #pragma unroll
         for (int p = 0; p < 3; ++p) {
 #pragma unroll
             for (int i = 0; i < TM; ++i)
-                af[p][i] = *reinterpret_cast<const bf16x8*>(&L.a[buf][p][fa + i * 16 * LK]);
+                af[2 - p][i] = *reinterpret_cast<const bf16x8*>(&L.a[buf][2 - p][fa + i * 16 * LK]);
 #pragma unroll
             for (int j = 0; j < TN; ++j)
                 bfr[p][j] = *reinterpret_cast<const bf16x8*>(&L.b[buf][p][fb + j * 16 * LK]);
