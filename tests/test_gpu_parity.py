@@ -324,6 +324,24 @@ def test_run_matches_oracle_fp32_per_step(E, workload, C):
     s.close()
 
 
+@pytest.mark.parametrize("d,m,C", [(1300, 700, 300), (2500, 1500, 300)])
+def test_run_matches_oracle_per_step_wide(E, d, m, C):
+    """d above twice the threads per chain (256 and 512 threads here), so each
+    thread draws several of the next direction's element pairs: the first
+    ahead of the move, the rest in the move's loop.  The run path hands each
+    step's draw to the next, checked one step at a time against the oracle."""
+    say(f"[run] per-step wide d={d} m={m} C={C}")
+    rng = np.random.default_rng(d)
+    A = rng.standard_normal((m, d)) / math.sqrt(d)
+    b = rng.uniform(0.5, 1.5, m)
+    s = E.Sampler(A, b, np.zeros(d), C, seed=11, precision=32, trim_eps=1e-6)
+    s.run(2, keep_trace=False)                  # generic states first
+    idx = np.linspace(0, C - 1, 48).astype(int)
+    excused = run_step_by_step(E, s, A, b, 11, 3, idx, 1e-6)
+    assert excused <= 2
+    s.close()
+
+
 def test_run_matches_oracle_per_step_warm_family(E):
     """The warm-start family's shape (d=256, m=768, 32 right-hand sides x 64
     chains = 2048 chains with one b per chain), the context the batched +
