@@ -54,6 +54,20 @@ def test_batched_with_a_problem_above_2048_rows_per_step(E):
     per_step_against_oracle(E, probs)
 
 
+def test_batched_with_a_wide_problem_per_step(E):
+    """A problem of 700 columns beside small ones: each of its chains' threads
+    draws more than one of the next direction's element pairs (the first ahead
+    of the move, the rest in the move's loop), and its projections take the
+    split 64 x 64 tiles; per step against the oracle as above."""
+    rng = np.random.default_rng(43)
+    probs = problems(4, 16, seed=43)
+    d, m = 700, 900
+    A = rng.standard_normal((m, d)) / math.sqrt(d)
+    probs.insert(1, dict(A=A, b=rng.uniform(0.5, 1.5, m), x0=np.zeros(d), n_chains=16,
+                         seed=778, trim_eps=1e-6))
+    per_step_against_oracle(E, probs)
+
+
 def per_step_against_oracle(E, probs):
     say("[batched] shapes", [(p["A"].shape, p["n_chains"]) for p in probs])
     s = E.BatchedSampler(probs)
