@@ -212,8 +212,9 @@ ess_status ess_draw(ess_ctx* ctx, uint64_t step, void* nu, double* u);
  *   (d <= 64, d <= 192, d > 192, each split at m <= 256); the classes up to
  *   192 columns each take a float32 tile shape (64x64, 32x64, 64x32 or
  *   32x32 rows x chain columns), tuned by one pass of coordinate descent over
- *   the classes present, then the other launch form.  Problems above 192
- *   columns keep the split bfloat16 64 x 64 tiles.
+ *   the classes present, then the other launch form, then (split form) the
+ *   number of problem sets run on streams of their own (1 to 4).  Problems
+ *   above 192 columns keep the split bfloat16 64 x 64 tiles.
  * Single-problem contexts: in precision 32 the split bfloat16 tiles (128 x
  *   128 and 64 x 64) and the float32 tiles 128x128, 128x64, 64x128 and
  *   64x64, then the band height (1 to 16 tile rows) of the XCD-aware tile

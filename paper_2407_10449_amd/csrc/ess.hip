@@ -838,6 +838,42 @@ int tile_bucket(const ProbDesc& d) {
 // entry 8 k + x runs on XCD x: each row panel of a problem (the tiles that
 // share its rows of A) is given whole to the XCD with the fewest tiles so
 // far, and the eight lists are padded to one length and interleaved.
+// Problem sets, each advanced on a stream of its own: a set's chains wait
+// only for its own tiles, so one set's chain kernel runs beside another set's
+// tiles instead of after every tile of the batch.  Problems go, largest
+// first, to the set with the least work so far (rows x chains x (columns +
+// 128), projections plus per-row chain work); within a set, chains of the
+// larger classes come first, so the longest chain items start early.  The
+// chains do not depend on the set count (only the launches' order does).
+// Rebuilds the chain list (and leaves the tile table to batched_layout).
+ess_status batched_sets(ess_ctx* c, int nsets) {
+    ess_ctx::Batch& B = *c->batch;
+    const int n = B.n;
+    B.nsets = std::max(1, std::min(std::min(nsets, kMaxGroups), n));
+    B.set_of.assign(n, 0);
+    double load[kMaxGroups] = {};
+    for (int p : B.order) {
+        int k = 0;
+        for (int j = 1; j < B.nsets; ++j)
+            if (load[j] < load[k]) k = j;
+        B.set_of[p] = k;
+        load[k] += static_cast<double>(B.h[p].m) * B.h[p].C * (B.h[p].d + 128);
+    }
+    std::vector<int2> chains;
+    for (int k = 0; k < B.nsets; ++k) {
+        B.set_coff[k] = static_cast<int>(chains.size());
+        for (int cls = 4; cls >= 0; --cls)
+            for (int p = 0; p < n; ++p)
+                if (B.set_of[p] == k && B.h[p].cls == cls)
+                    for (int ch = 0; ch < B.h[p].C; ++ch) chains.push_back(make_int2(p, ch));
+        B.set_nc[k] = static_cast<int>(chains.size()) - B.set_coff[k];
+    }
+    if (static_cast<int>(chains.size()) != B.NC) return fail(ESS_ERR_INVALID_ARG, "batched sets: chain count");
+    HIP_TRY(hipMemcpyAsync(B.chains, chains.data(), sizeof(int2) * B.NC, hipMemcpyHostToDevice, c->st));
+    HIP_TRY(hipStreamSynchronize(c->st));   // the host list goes away at return
+    return ESS_OK;
+}
+
 ess_status batched_layout(ess_ctx* c) {
     constexpr int kXcds = 8;
     ess_ctx::Batch& B = *c->batch;
@@ -943,37 +979,9 @@ ess_status batched_init(ess_ctx* c, const ess_problem* pr, int n) {
         return static_cast<long long>(B.h[x].mp) * B.h[x].dp * B.h[x].Cp >
                static_cast<long long>(B.h[y].mp) * B.h[y].dp * B.h[y].Cp;
     });
-    // Problem sets, each advanced on a stream of its own: a set's chains wait
-    // only for its own tiles, so one set's chain kernel runs beside another
-    // set's tiles instead of after every tile of the batch.  Problems go,
-    // largest first, to the set with the least work so far (rows x chains x
-    // (columns + 128), projections plus per-row chain work).
-    {
-        int ns = 2;
-        if (const char* e = std::getenv("ESS_BATCH_SETS")) ns = std::atoi(e);
-        B.nsets = std::max(1, std::min(std::min(ns, kMaxGroups), n));
-        B.set_of.assign(n, 0);
-        double load[kMaxGroups] = {};
-        for (int p : B.order) {
-            int k = 0;
-            for (int j = 1; j < B.nsets; ++j)
-                if (load[j] < load[k]) k = j;
-            B.set_of[p] = k;
-            load[k] += static_cast<double>(B.h[p].m) * B.h[p].C * (B.h[p].d + 128);
-        }
-    }
-    // within a set, chains of the larger classes first, so the longest chain
-    // items start early
-    std::vector<int2> chains;
-    for (int k = 0; k < B.nsets; ++k) {
-        B.set_coff[k] = static_cast<int>(chains.size());
-        for (int cls = 4; cls >= 0; --cls)
-            for (int p = 0; p < n; ++p)
-                if (B.set_of[p] == k && B.h[p].cls == cls)
-                    for (int ch = 0; ch < B.h[p].C; ++ch) chains.push_back(make_int2(p, ch));
-        B.set_nc[k] = static_cast<int>(chains.size()) - B.set_coff[k];
-    }
-    B.NC = static_cast<int>(chains.size());
+    int nchains = 0;
+    for (int p = 0; p < n; ++p) nchains += B.h[p].C;
+    B.NC = nchains;
 
     ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.descs), sizeof(ProbDesc) * n));
     ESS_TRY(dalloc(c, reinterpret_cast<void**>(&B.wg_prob), sizeof(int) * (max_tiles + B.NC)));
@@ -997,8 +1005,11 @@ ess_status batched_init(ess_ctx* c, const ess_problem* pr, int n) {
     ESS_TRY(dalloc(c, reinterpret_cast<void**>(&c->d_step), sizeof(uint32_t)));
     ESS_TRY(create_run_streams(c));
     ESS_TRY(create_group_streams(c));
-    HIP_TRY(hipMemcpyAsync(B.chains, chains.data(), sizeof(int2) * B.NC, hipMemcpyHostToDevice,
-                           c->st));
+    {
+        int ns = 2;
+        if (const char* e = std::getenv("ESS_BATCH_SETS")) ns = std::atoi(e);
+        ESS_TRY(batched_sets(c, ns));
+    }
     for (int p = 0; p < n; ++p) {
         const ProbDesc& d = B.h[p];
         HIP_TRY(hipMemcpy2DAsync(B.A + d.a_off, sizeof(float) * d.dp, pr[p].A, sizeof(float) * d.d,
@@ -1160,6 +1171,7 @@ double field(const std::string& obj, const char* name, double dflt) {
 struct TuneChoice {
     int shape_code = 0;
     int fused = 0;
+    int sets = 0;   // problem sets of the split form (0: keep)
     double us = 0;
 };
 
@@ -1180,6 +1192,7 @@ void set_choice(ess_ctx* c, const TuneChoice& t) {
 
 ess_status apply_choice(ess_ctx* c, const TuneChoice& t) {
     set_choice(c, t);
+    if (t.sets > 0 && t.sets != c->batch->nsets) ESS_TRY(batched_sets(c, t.sets));
     return batched_layout(c);
 }
 
@@ -1187,6 +1200,7 @@ TuneChoice current_choice(const ess_ctx* c) {
     TuneChoice t;
     t.shape_code = encode_shapes(c);
     t.fused = c->batch->fused ? 1 : 0;
+    t.sets = c->batch->nsets;
     return t;
 }
 
@@ -1205,7 +1219,10 @@ ess_status load_tuned(ess_ctx* c) {
         TuneChoice t;
         t.shape_code = static_cast<int>(field(obj, "shape_code", -1));
         t.fused = field(obj, "fused", 0) != 0 ? 1 : 0;
+        const int sets = static_cast<int>(field(obj, "sets", 0));
         if (t.shape_code >= 0 && t.shape_code < max_shape_code()) set_choice(c, t);
+        if (sets >= 1 && sets <= kMaxGroups && !std::getenv("ESS_BATCH_SETS"))
+            ESS_TRY(batched_sets(c, sets));
     }
     if (const char* env = std::getenv("ESS_BATCH_TILE")) {
         int bm = 0, bn = 0, shape = -1;
@@ -1257,7 +1274,7 @@ void store_entry(const std::string& key, const std::string& value) {
 void store_tuned(const ess_ctx* c, const TuneChoice& t) {
     std::ostringstream v;
     v << "{\"shape_code\": " << t.shape_code << ", \"fused\": " << t.fused
-      << ", \"us_per_step\": " << t.us << "}";
+      << ", \"sets\": " << t.sets << ", \"us_per_step\": " << t.us << "}";
     store_entry(tune_key(c), v.str());
 }
 
@@ -2481,7 +2498,7 @@ ess_status ess_autotune(ess_ctx* c, int32_t steps_per_trial, char* report, int32
         float ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
         t.us = 1e3 * ms / steps_per_trial;
-        rep << (t.fused ? "fused" : "split") << ", shapes";
+        rep << (t.fused ? "fused" : "split") << ", " << c->batch->nsets << " sets, shapes";
         int code = t.shape_code;
         for (int k = 0; k < kTileBuckets; ++k, code /= kBatchShapes)
             rep << " " << shape_bm(code % kBatchShapes) << "x" << shape_bn(code % kBatchShapes);
@@ -2498,7 +2515,7 @@ ess_status ess_autotune(ess_ctx* c, int32_t steps_per_trial, char* report, int32
         const int digit = (best.shape_code / place) % kBatchShapes;
         for (int sh = 0; sh < kBatchShapes && st == ESS_OK; ++sh) {
             if (sh == digit) continue;
-            TuneChoice t;
+            TuneChoice t = best;
             t.shape_code = best.shape_code + (sh - digit) * place;
             st = trial(t);
             if (st == ESS_OK && t.us < best.us) best = t;
@@ -2507,6 +2524,14 @@ ess_status ess_autotune(ess_ctx* c, int32_t steps_per_trial, char* report, int32
     if (st == ESS_OK) {   // the other launch form with the chosen shapes
         TuneChoice t = best;
         t.fused = best.fused ? 0 : 1;
+        st = trial(t);
+        if (st == ESS_OK && t.us < best.us) best = t;
+    }
+    // the split form's problem-set count (the chains do not depend on it)
+    for (int ns = 1; ns <= std::min(kMaxGroups, B.n) && st == ESS_OK && !best.fused; ++ns) {
+        if (ns == best.sets) continue;
+        TuneChoice t = best;
+        t.sets = ns;
         st = trial(t);
         if (st == ESS_OK && t.us < best.us) best = t;
     }
@@ -2520,7 +2545,8 @@ ess_status ess_autotune(ess_ctx* c, int32_t steps_per_trial, char* report, int32
     c->step = step0;
     if (st != ESS_OK) return st;
     store_tuned(c, best);
-    rep << "chosen: " << (best.fused ? "fused" : "split") << ", shape_code " << best.shape_code
+    rep << "chosen: " << (best.fused ? "fused" : "split") << ", " << best.sets << " sets, shape_code "
+        << best.shape_code
         << " (" << best.us << " us/step)\n";
     if (report && report_len > 0) {
         const std::string r = rep.str();
