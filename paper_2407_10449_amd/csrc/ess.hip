@@ -738,12 +738,13 @@ ess_status launch_batched_step(ess_ctx* c, const BatchArgs& a, hipStream_t st) {
     return launch_step_t<16>(c, a, st);
 }
 
-// A x for the rows in X (p_direct) with the strict start check, then the flags.
-ess_status batched_set_state_from_X(ess_ctx* c, const char* what) {
+// A x for the rows in `rows` (X unless given; p_direct) with the strict start
+// check, then the flags.
+ess_status batched_set_state_from_X(ess_ctx* c, const char* what, float* rows = nullptr) {
     ess_ctx::Batch& B = *c->batch;
     HIP_TRY(hipMemsetAsync(c->flag, 0, sizeof(int) * B.chains_padded, c->st));
     BatchArgs a = batch_args(c);
-    a.Xprop = B.X;    // tiles read the committed rows
+    a.Xprop = rows ? rows : B.X;    // tiles read the rows to be committed
     a.cols = 0;
     a.p_direct = 1;
     a.strict = 1;
@@ -1974,8 +1975,20 @@ ess_status ess_set_state(ess_ctx* c, const void* x_in, uint64_t step) {
     if (!x_in) return fail(ESS_ERR_INVALID_ARG, "null state");
     if (step >= (1ull << 32)) return fail(ESS_ERR_UNSUPPORTED, "the step counter is limited to 2^32");
     if (c->batch) {
-        ESS_TRY(batched_copy_state(c, static_cast<const float*>(x_in), c->batch->X, 1));
-        ESS_TRY(batched_set_state_from_X(c, "ess_set_state"));
+        // staged in X' and checked there; a state that fails the strict check
+        // leaves the context where it was (its projections recomputed from X)
+        ess_ctx::Batch& B = *c->batch;
+        ESS_TRY(batched_copy_state(c, static_cast<const float*>(x_in), B.Xprop, 1));
+        const ess_status st = batched_set_state_from_X(c, "ess_set_state", B.Xprop);
+        if (st != ESS_OK) {
+            const std::string msg = g_err;
+            (void)batched_set_state_from_X(c, "ess_set_state", B.X);
+            g_err = msg;
+            return st;
+        }
+        const size_t bytes = sizeof(float) * (B.h.back().x_off +
+                                              static_cast<size_t>(B.h.back().Cp) * B.h.back().dp);
+        HIP_TRY(hipMemcpyAsync(B.X, B.Xprop, bytes, hipMemcpyDeviceToDevice, c->st));
         ESS_TRY(launch_step_counter(c, c->st, step, 0));
     } else {
         ESS_TRY(copy_rows_in(c, c->Xprop, x_in));

@@ -208,3 +208,27 @@ def test_batched_problem_sets_give_identical_chains(E, monkeypatch):
         outs.append(tr)
     assert torch.equal(outs[0], outs[1])
     assert torch.equal(outs[0], outs[2])
+
+
+def test_batched_infeasible_set_state_keeps_the_state(E):
+    """A state that fails the strict start check raises, and the batch keeps
+    its previous state, step and projections: it then runs exactly as a twin
+    batch that never saw the bad state."""
+    probs = problems(6, 16, seed=51)
+    a = E.BatchedSampler(probs)
+    b = E.BatchedSampler(probs)
+    a.run(3)
+    b.run(3)
+    x, step = a.state()
+    bad = x.clone()
+    bad[0] = 1.0e6   # far outside every polytope's rows that weigh coordinate 0
+    with pytest.raises(E.EssError) as ei:
+        a.set_state(bad, step)
+    assert ei.value.status == E.ESS_ERR_INFEASIBLE_START
+    x2, step2 = a.state()
+    assert torch.equal(x2, x) and step2 == step
+    ta, _ = a.run(4)
+    tb, _ = b.run(4)
+    assert torch.equal(ta, tb)
+    a.close()
+    b.close()

@@ -390,6 +390,30 @@ def test_iterates_stay_feasible(E):
     s.close()
 
 
+def test_infeasible_set_state_keeps_the_state(E):
+    """A state that fails the strict start check raises, and the context
+    keeps its previous state, step and projections: it then runs exactly as a
+    twin context that never saw the bad state."""
+    pr = synth.box_halfspace(n_chains=300)
+    a = E.Sampler(pr.A, pr.b, pr.x0, 300, seed=4, precision=32)
+    b = E.Sampler(pr.A, pr.b, pr.x0, 300, seed=4, precision=32)
+    a.run(3, keep_trace=False)
+    b.run(3, keep_trace=False)
+    x, step = a.state()
+    bad = x.clone()
+    bad[0, 0] = 1.0e6   # outside the box
+    with pytest.raises(E.EssError) as ei:
+        a.set_state(bad, step)
+    assert ei.value.status == E.ESS_ERR_INFEASIBLE_START
+    x2, step2 = a.state()
+    assert torch.equal(x2, x) and step2 == step
+    ta, _ = a.run(4)
+    tb, _ = b.run(4)
+    assert torch.equal(ta, tb)
+    a.close()
+    b.close()
+
+
 def test_errors_are_reported(E):
     pr = synth.small_fp64()
     with pytest.raises(E.EssError) as ei:
